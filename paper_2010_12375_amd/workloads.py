@@ -1,0 +1,211 @@
+"""Seeded synthetic inputs for the dam-break workloads.
+
+This module only builds inputs: particle lattices, seeded position jitter,
+wall dummy particles with their normals, the domain box and the case
+parameters. It holds none of the method's arithmetic (no kernel, no Riemann
+solver, no time stepping) and is shared by the HIP path's callers and by the
+tests that drive the oracle.
+
+Geometry follows the paper's dam-break cases (Section 10.1, 2D and 3D dam
+break): a water column at rest in the lower-left corner of a tank, released
+at t = 0 under gravity, with the tank walls made of wall dummy particles.
+The particle generators mirror the lattice generator of the paper's particle
+generator table (Section 9): particles sit at ((k + 1/2) dp, ...).
+
+Readings (the paper does not state these):
+* wall: 4 layers of lattice points outside the tank interior, so that the
+  wall lattice continues the fluid lattice; normals are the normalised sum of
+  the outward box-face normals the point lies beyond, i.e. unit vectors
+  pointing into the fluid, diagonal in the corners;
+* jitter: i.i.d. uniform in [-0.01 dp, 0.01 dp] per coordinate of every fluid
+  particle, numpy PCG64(seed);
+* 3D: x is the length, y the height (gravity along -y) and z the width; the
+  width is periodic and walls cover the floor, the ceiling and both end
+  walls;
+* sound speed c0 = 20 sqrt(g H) with H the water column height and reference
+  speed U_ref = c0 / 10 (Section 2.1: c = 10 U_max keeps density variation
+  near 1 %).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+FP64 = 0
+FP32 = 1
+
+
+@dataclasses.dataclass
+class Case:
+    """One simulation input: parameters plus fluid and wall particles."""
+
+    name: str
+    dim: int
+    dp: float
+    h: float
+    rho0: float
+    c0: float
+    u_ref: float
+    cfl_ad: float
+    cfl_ac: float
+    gravity: tuple
+    lo: tuple
+    hi: tuple
+    periodic: tuple
+    fluid_pos: np.ndarray          # (n_f, dim) float64
+    wall_pos: np.ndarray           # (n_w, dim) float64
+    wall_normal: np.ndarray        # (n_w, dim) float64, unit, into the fluid
+    precision: int = FP64
+    t_end: Optional[float] = None
+    n_adv_steps: Optional[int] = None
+    column: tuple = ()             # (L, H[, W]) of the water column
+    tank: tuple = ()               # (DL, DH[, DW]) of the tank interior
+    seed: int = 0
+
+    @property
+    def n_fluid(self) -> int:
+        return int(self.fluid_pos.shape[0])
+
+    @property
+    def n_wall(self) -> int:
+        return int(self.wall_pos.shape[0])
+
+
+def _lattice(counts, dp):
+    axes = [(np.arange(n, dtype=np.float64) + 0.5) * dp for n in counts]
+    grids = np.meshgrid(*axes, indexing="ij")
+    # particle order: x fastest is irrelevant to the method; keep ij order
+    return np.stack([g.reshape(-1) for g in grids], axis=1)
+
+
+def _jitter(pos, dp, seed, amp=0.01):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return pos + rng.uniform(-amp * dp, amp * dp, size=pos.shape)
+
+
+def tank_walls_2d(DL, DH, dp, layers=4):
+    """Wall dummy particles around the box [0, DL] x [0, DH] in 2D."""
+    k = np.arange(-layers, int(math.floor(DL / dp + layers - 0.5)) + 1)
+    l = np.arange(-layers, int(math.floor(DH / dp + layers - 0.5)) + 1)
+    x = (k + 0.5) * dp
+    y = (l + 0.5) * dp
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    X = X.reshape(-1)
+    Y = Y.reshape(-1)
+    inside = (X >= 0) & (X <= DL) & (Y >= 0) & (Y <= DH)
+    keep = (~inside) & (X >= -layers * dp) & (X <= DL + layers * dp) & \
+        (Y >= -layers * dp) & (Y <= DH + layers * dp)
+    X = X[keep]
+    Y = Y[keep]
+    nx = np.where(X < 0, 1.0, np.where(X > DL, -1.0, 0.0))
+    ny = np.where(Y < 0, 1.0, np.where(Y > DH, -1.0, 0.0))
+    nn = np.sqrt(nx * nx + ny * ny)
+    pos = np.stack([X, Y], axis=1)
+    nrm = np.stack([nx / nn, ny / nn], axis=1)
+    return pos, nrm
+
+
+def _params(dim, dp, H, g=1.0, h_ratio=1.3):
+    c0 = 20.0 * math.sqrt(g * H)
+    return dict(dim=dim, dp=dp, h=h_ratio * dp, rho0=1.0, c0=c0, u_ref=c0 / 10.0,
+                cfl_ad=0.25, cfl_ac=0.6)
+
+
+def dam_break_2d(dp, seed=0, L=2.0, H=1.0, DL=5.366, DH=5.366, precision=FP64,
+                 t_end=None, jitter=0.01, name=None, layers=4):
+    """2D dam break: column L x H at the lower-left of a DL x DH tank."""
+    nx = int(round(L / dp))
+    ny = int(round(H / dp))
+    pos = _lattice((nx, ny), dp)
+    if jitter:
+        pos = _jitter(pos, dp, seed, jitter)
+    wpos, wn = tank_walls_2d(DL, DH, dp, layers)
+    prm = _params(2, dp, H)
+    pad = layers * dp + 2.0 * prm["h"]
+    return Case(name=name or f"dambreak2d_dp{dp:g}", gravity=(0.0, -1.0, 0.0),
+                lo=(-pad, -pad, 0.0), hi=(DL + pad, DH + pad, 0.0), periodic=(0, 0, 0),
+                fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision,
+                t_end=t_end, column=(nx * dp, ny * dp), tank=(DL, DH), seed=seed, **prm)
+
+
+def dam_break_3d(dp, seed=0, L=2.0, H=1.0, W=1.0, DL=5.366, DH=2.0, precision=FP32,
+                 n_adv_steps=None, jitter=0.01, name=None, layers=4):
+    """3D dam break, periodic in the width z: column L x H x W in a DL x DH tank."""
+    nx = int(round(L / dp))
+    ny = int(round(H / dp))
+    nz = int(round(W / dp))
+    pos = _lattice((nx, ny, nz), dp)
+    if jitter:
+        pos = _jitter(pos, dp, seed, jitter)
+    w2, n2 = tank_walls_2d(DL, DH, dp, layers)
+    zs = (np.arange(nz, dtype=np.float64) + 0.5) * dp
+    wpos = np.concatenate([np.column_stack([w2, np.full(len(w2), z)]) for z in zs])
+    wn = np.concatenate([np.column_stack([n2, np.zeros(len(n2))]) for _ in zs])
+    prm = _params(3, dp, H)
+    pad = layers * dp + 2.0 * prm["h"]
+    return Case(name=name or f"dambreak3d_dp{dp:g}", gravity=(0.0, -1.0, 0.0),
+                lo=(-pad, -pad, 0.0), hi=(DL + pad, DH + pad, nz * dp), periodic=(0, 0, 1),
+                fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision,
+                n_adv_steps=n_adv_steps, column=(nx * dp, ny * dp, nz * dp),
+                tank=(DL, DH, nz * dp), seed=seed, **prm)
+
+
+# --- the configurations the build is measured on --------------------------
+
+def config_small(seed=0):
+    """2D, dp = 0.05 (800 fluid particles), FP64, run to t = 1."""
+    return dam_break_2d(0.05, seed=seed, precision=FP64, t_end=1.0, name="dambreak2d_800")
+
+
+def config_medium(seed=0, precision=FP32):
+    """2D, dp = 0.00625 (51 200 fluid particles), FP32 fields, run to t = 20."""
+    return dam_break_2d(0.00625, seed=seed, precision=precision, t_end=20.0,
+                        name="dambreak2d_51k")
+
+
+def config_large(seed=0, precision=FP32):
+    """3D, dp = 0.01 (2.0 M fluid, 0.596 M wall particles), 2 000 advection steps."""
+    return dam_break_3d(0.01, seed=seed, precision=precision, n_adv_steps=2000,
+                        name="dambreak3d_2M")
+
+
+ENSEMBLE_DPS = (0.05, 0.025, 0.0125, 0.00625)
+
+
+def ensemble_cases(n_cases=64, seed=0, precision=FP32) -> List[Case]:
+    """Batched ensemble of uneven 2D dam breaks: dp drawn uniformly from
+    ENSEMBLE_DPS, column aspect a = H/L uniform in [0.25, 1] with the column
+    area fixed at L H = 2 (so L = sqrt(2/a), H = sqrt(2a)); per-case sound
+    speed from its own column height."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for c in range(n_cases):
+        dp = float(ENSEMBLE_DPS[int(rng.integers(0, len(ENSEMBLE_DPS)))])
+        a = float(rng.uniform(0.25, 1.0))
+        L = math.sqrt(2.0 / a)
+        H = math.sqrt(2.0 * a)
+        case = dam_break_2d(dp, seed=seed * 1000 + c, L=L, H=H, precision=precision,
+                            name=f"ens{c:02d}_dp{dp:g}_a{a:.3f}")
+        out.append(case)
+    return out
+
+
+def hydrostatic_column_2d(dp=0.05, L=1.0, H=1.0, seed=0, jitter=0.0):
+    """Water column filling a closed 2D box of width L (walls on both sides),
+    for the resting-column check; densities are set by the caller."""
+    nx = int(round(L / dp))
+    ny = int(round(H / dp))
+    pos = _lattice((nx, ny), dp)
+    if jitter:
+        pos = _jitter(pos, dp, seed, jitter)
+    DH = 2.0 * H
+    wpos, wn = tank_walls_2d(L, DH, dp)
+    prm = _params(2, dp, H)
+    pad = 4 * dp + 2.0 * prm["h"]
+    return Case(name=f"column2d_dp{dp:g}", gravity=(0.0, -1.0, 0.0),
+                lo=(-pad, -pad, 0.0), hi=(L + pad, DH + pad, 0.0), periodic=(0, 0, 0),
+                fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=FP64,
+                column=(nx * dp, ny * dp), tank=(L, DH), seed=seed, **prm)
