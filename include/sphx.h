@@ -1,0 +1,173 @@
+/*
+ * sphx.h -- C ABI of the MI355X (gfx950) Riemann-WCSPH library.
+ *
+ * One library context holds one fluid body and one static wall body
+ * (bodies made of particles with inner and contact interactions, Section 9
+ * overview of the SPHinXsys paper, arXiv 2010.12375) and advances them with
+ * the paper's fluid scheme: Riemann-based continuity and momentum equations
+ * (Section 2.2, Eq. riemannsph) with the one-sided wall condition (Section
+ * 2.3), density re-initialisation (Eq. eqrhosum), dual-criteria time
+ * stepping (Section 2.4) and position-based Verlet (Section 7).
+ *
+ * Conventions, for every call:
+ *  - Return 0 on success or a negative SPHX_E* code; sphx_last_error() gives
+ *    a message for the last failure on the context.
+ *  - All host pointers belong to the caller and are only read or written
+ *    during the call. Device memory belongs to the library.
+ *  - Arrays at the boundary are FP64 and in original particle order (the
+ *    order of the arrays passed to sphx_set_fluid / sphx_set_walls), however
+ *    the library orders particles internally. Vectors are packed n * dim.
+ *  - Work is queued on the stream given to sphx_create (or one the library
+ *    creates); calls that return data synchronise that stream.
+ *  - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef SPHX_H
+#define SPHX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPHX_OK 0
+#define SPHX_EINVAL (-1)    /* bad argument or unsupported parameter */
+#define SPHX_ENOMEM (-2)    /* device or host allocation failed */
+#define SPHX_EHIP (-3)      /* a HIP runtime call failed */
+#define SPHX_EESCAPE (-4)   /* a fluid particle left the domain box */
+#define SPHX_ENAN (-5)      /* NaN in the particle state */
+#define SPHX_ECAP (-6)      /* caller buffer too small; *n_out holds the size needed */
+#define SPHX_EOVERFLOW (-7) /* a particle has more neighbours than the list capacity */
+#define SPHX_ESTATE (-8)    /* call out of order (e.g. rates before any particles) */
+
+#define SPHX_FP64 0 /* every field and every pair computation in FP64 */
+#define SPHX_FP32 1 /* FP32 fields and pair arithmetic; FP64 positions, clock and diagnostics */
+
+#define SPHX_INNER 0   /* fluid-fluid neighbours */
+#define SPHX_CONTACT 1 /* fluid-wall neighbours */
+
+#define SPHX_FIELD_POS 0  /* n * dim */
+#define SPHX_FIELD_VEL 1  /* n * dim */
+#define SPHX_FIELD_RHO 2  /* n */
+#define SPHX_FIELD_P 3    /* n, from the EoS p = c0^2 (rho - rho0) (Eq. eqeos) */
+#define SPHX_FIELD_DRHO 4 /* n, drho/dt of the last density relaxation */
+
+typedef struct sphx_ctx sphx_ctx;
+
+typedef struct {
+    int32_t dim;         /* 2 or 3 */
+    int32_t precision;   /* SPHX_FP64 or SPHX_FP32 */
+    int32_t periodic[3]; /* periodic axes (period = hi - lo); need >= 3 cells of 2h */
+    int32_t nsub_queue;  /* acoustic sub-steps queued per advection step (0: default 6);
+                            a step that needs more is finished by the host, same result */
+    double dp;           /* initial particle spacing: fluid mass rho0 dp^dim, wall volume dp^dim */
+    double h;            /* smoothing length; Wendland C2 support radius 2h */
+    double rho0;         /* reference density */
+    double c0;           /* artificial sound speed (Eq. eqeos) */
+    double u_ref;        /* reference speed: floor of |v|max in the advection criterion */
+    double cfl_ad;       /* advection CFL number (Eq. dt-advection; 0.25) */
+    double cfl_ac;       /* acoustic CFL number (Eq. dt-relax; 0.6) */
+    double gravity[3];   /* body force per unit mass */
+    double lo[3], hi[3]; /* domain box: binning grid; fluid outside it is an escape */
+    double sigma0;       /* reference kernel sum of Eq. eqrhosum; <= 0: the lattice sum
+                            over the dp lattice, self included, computed by the library */
+} sphx_params;
+
+typedef struct {
+    double mass;        /* total fluid mass */
+    double momentum[3]; /* sum m v */
+    double e_kin;       /* sum m |v|^2 / 2 */
+    double e_pot;       /* -sum m g . x */
+    double e_int;       /* sum m c0^2 (ln(rho/rho0) + rho0/rho - 1): energy of the EoS */
+    double front;       /* surge front: max x over fluid particles */
+    double max_drho;    /* max |rho/rho0 - 1| */
+    double t;           /* clock */
+    int64_t n_substeps; /* acoustic sub-steps since sphx_set_fluid */
+    int64_t n_steps;    /* advection steps since sphx_set_fluid */
+} sphx_diag;
+
+/* Create a context. stream: a hipStream_t to queue work on, or NULL for a
+ * library-owned stream (default priority). Fails with SPHX_EINVAL for dim
+ * other than 2/3, non-positive sizes, a periodic axis with fewer than 3
+ * cells of size 2h, or an empty box. */
+int sphx_create(const sphx_params* params, void* stream, sphx_ctx** out);
+
+/* Free every device buffer, graph and the owned stream. NULL is a no-op. */
+void sphx_destroy(sphx_ctx* ctx);
+
+/* Message of the last failure on ctx (never NULL; "" if none). */
+const char* sphx_last_error(const sphx_ctx* ctx);
+
+/* Fluid particles from arrays (direct particle generator, Section 9):
+ * pos n*dim (required), vel n*dim (NULL: rest), rho n (NULL: rho0), drho n
+ * (NULL: 0, the density rate carried into the first half-step). Resets the
+ * clock to 0 and invalidates the neighbour configuration. */
+int sphx_set_fluid(sphx_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* rho,
+                   const double* drho);
+
+/* Static wall particles: pos n*dim and unit normals n*dim pointing into the
+ * fluid (Section 2.3 wall normal). Every wall particle must lie inside the
+ * domain box. Invalidates the neighbour configuration. */
+int sphx_set_walls(sphx_ctx* ctx, int64_t n, const double* pos, const double* normal);
+
+/* Configuration update (Section 2.4: at the advection frequency): wrap
+ * periodic coordinates, bin particles into cells of size >= 2h, rebuild the
+ * inner and contact neighbour lists with the FP64 predicate r^2 < (2h)^2
+ * (dx = x_i - x_j, one minimum-image wrap, left-to-right sum), and freeze
+ * the pair geometry. SPHX_EESCAPE / SPHX_ENAN / SPHX_EOVERFLOW on failure. */
+int sphx_build_neighbors(sphx_ctx* ctx);
+
+/* Neighbour lists as CSR of original ids, ascending within each row.
+ * kind: SPHX_INNER or SPHX_CONTACT. off: n_fluid + 1 entries (may be NULL);
+ * idx: cap entries (may be NULL). *n_out receives the number of entries;
+ * SPHX_ECAP if idx is given and cap < *n_out. */
+int sphx_get_neighbors(sphx_ctx* ctx, int kind, int64_t* off, int64_t* idx, int64_t cap, int64_t* n_out);
+
+/* Density re-initialisation of Eq. eqrhosum on the current configuration:
+ * rho = max(rho, rho0 sum W / sum W0), sums over self, fluid and wall
+ * neighbours. */
+int sphx_density_reinit(sphx_ctx* ctx);
+
+/* The two time-step criteria for the current state (Eqs. dt-advection
+ * without viscosity, |v|max floored at u_ref, and dt-relax). */
+int sphx_time_steps(sphx_ctx* ctx, double* dt_ad, double* dt_ac);
+
+/* The rates of one acoustic sub-step of size dt from the current state,
+ * which is left unchanged: the pressure relaxation's dv/dt (n*dim, gravity
+ * included) and the density relaxation's drho/dt (n), i.e. half-steps of
+ * Eq. verlet-first-half, Eq. riemannsph momentum, Eq. verlet-first-mediate,
+ * Eq. riemannsph continuity. Requires a configuration. */
+int sphx_compute_rates(sphx_ctx* ctx, double dt, double* dvdt, double* drhodt);
+
+/* Advance up to n_steps advection steps (each: dt_ad, density
+ * re-initialisation, acoustic sub-steps until the step is covered, the last
+ * clipped to land on it, then the configuration update), stopping early when
+ * the clock reaches t_stop (a step is clipped to end exactly on t_stop).
+ * Sub-step control stays on the device; the host synchronises once per
+ * call. *n_substeps (may be NULL) receives the acoustic sub-steps done,
+ * *t_out (may be NULL) the clock. */
+int sphx_advance(sphx_ctx* ctx, int32_t n_steps, double t_stop, int64_t* n_substeps, double* t_out);
+
+/* Field in original order as FP64 (SPHX_FIELD_*). */
+int sphx_get_field(sphx_ctx* ctx, int field, double* out);
+
+/* FP64 global observables of the current state (reduced on the device). */
+int sphx_diagnostics(sphx_ctx* ctx, sphx_diag* out);
+
+/* Average device time per launch (milliseconds) of the acoustic sub-step
+ * kernels, measured with HIP events on the context's stream over `reps`
+ * launches each of the pressure and density relaxation on the current
+ * state; the state and clock are restored afterwards. ms[0] pressure
+ * relaxation, ms[1] density relaxation, ms[2] neighbour build, ms[3] one
+ * whole advection step launch (graph), per launch. */
+int sphx_profile(sphx_ctx* ctx, int32_t reps, double* ms);
+
+/* Particle and pair counts of the current configuration: out[0] fluid,
+ * out[1] wall, out[2] inner pairs (directed), out[3] contact pairs. */
+int sphx_counts(sphx_ctx* ctx, int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPHX_H */

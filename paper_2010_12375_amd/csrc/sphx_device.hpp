@@ -1,0 +1,947 @@
+// sphx_device.hpp -- HIP kernels (gfx950) of the Riemann-based weakly
+// compressible SPH step of the SPHinXsys paper (arXiv 2010.12375):
+// cell binning and neighbour configuration (Section 9, cell-linked list and
+// neighbour relation), density re-initialisation (Eq. eqrhosum), Riemann
+// pressure and density relaxation with one-sided wall states (Eqs.
+// riemannsph, eqriepartial, eqrienoslip, eqriepright), dual-criteria time
+// steps (Eqs. dt-advection, dt-relax) and position-based Verlet (Section 7).
+//
+// Data layout (all arrays in cell-sorted particle order, structure of
+// arrays for what a thread reads only for itself, small packed records for
+// what neighbours gather):
+//   x[k]   double   position accumulators, one array per axis
+//   geo    R2/R4    FP32 (or FP64) offset of the configuration-time position
+//                   from the origin of its cell: the frozen pair geometry is
+//                   recomputed from these as (o_i - o_j) - dc L, which keeps
+//                   FP32 relative error near 1e-7 of a cell instead of 1e-7
+//                   of the domain
+//   st     R4       {v0, v1, dev, drho} in 2D, {v0, v1, v2, dev} in 3D, with
+//                   dev = rho - rho0 (the density deviation carries the
+//                   pressure p = c^2 dev without the cancellation of rho - rho0)
+//   drho3  real     drho/dt in 3D
+//   hf     R4       {vn.., dev_half}: v^{n+1} and rho^{n+1/2} - rho0 written by
+//                   the pressure relaxation for the density relaxation
+//   nbr    u32      neighbour entries, column-major (entry k of particle i at
+//                   k * cap + i): sorted index | stencil code << 26, the code
+//                   holding the cell offset dc + 1 (2 bits per axis)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sphx {
+
+constexpr int NBR_SHIFT = 26;
+constexpr uint32_t NBR_MASK = (1u << NBR_SHIFT) - 1u;
+constexpr int BLOCK = 256;
+
+enum : uint32_t {
+    ERR_ESCAPE = 1u,       // a fluid particle left the domain box
+    ERR_NAN = 2u,          // NaN in the state
+    ERR_NBR_OVERFLOW = 4u, // neighbour list capacity exceeded
+    ERR_STALL = 8u,        // an advection step needed more sub-steps than queued
+};
+
+// Device-side control block of the time loop.
+struct Ctrl {
+    double t;          // clock (time of the current state)
+    double t_end;      // end of the current advection step
+    double t_stop;     // caller's stop time
+    double dt_ad;      // current advection step size
+    double tau;        // time covered inside the advection step
+    double dt;         // size of the next acoustic sub-step
+    double vmax;       // |v|max of the current state
+    unsigned long long vmax_bits; // max |v| accumulated by the density relaxation
+    int32_t active;    // sub-steps remain in this advection step
+    int32_t last;      // the next sub-step is the last of the step
+    int32_t nsub;      // sub-steps done in this advection step
+    int32_t rebuild;   // the step is complete: rebuild the configuration
+    long long nsub_total;
+    long long steps_done;
+    uint32_t blocks_done;
+    uint32_t err;         // sticky error bits; no kernel that tests them also sets them
+    uint32_t err_pending; // bits raised by the density relaxation, folded into err by its last block
+    uint32_t pad;
+};
+
+template <typename real> struct alignas(4 * sizeof(real)) R4 { real x, y, z, w; };
+template <typename real> struct alignas(2 * sizeof(real)) R2 { real x, y; };
+template <typename real> __device__ __forceinline__ real zc(const R2<real>&) { return (real)0; }
+template <typename real> __device__ __forceinline__ real zc(const R4<real>& v) { return v.z; }
+template <int D, typename real> struct GeoSel { using T = R2<real>; };
+template <typename real> struct GeoSel<3, real> { using T = R4<real>; };
+
+// Parameters of one simulation, passed by value to every kernel.
+template <typename real> struct KP {
+    real rho0, c, c2, inv_c2, half_inv_c;     // EoS and Riemann
+    real two_m, m, two_vw, vw;                // particle mass and wall volume
+    double md;                                // particle mass in FP64 (diagnostics)
+    real inv_h, Wc, dWc;                      // Wendland: Wc = a/h^d, dWc = -5a/h^(d+1)
+    real g[3];
+    real L[3];                                // cell size per axis
+    double Ld[3], lo[3], hi[3], period[3], half_period[3];
+    int n[3], periodic[3];
+    double rc2, sigma0, rho0d;
+    double cfl_ad_h, cfl_ac_h, u_ref, c0d;
+    int nf, nw, cap, maxn, maxw;
+};
+
+// ---------------------------------------------------------------------
+// small helpers
+
+template <typename T> __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ T dmin(T a, T b) { return a < b ? a : b; }
+
+// hardware reciprocal square root (about 1 ulp), far inside the FP32 budget
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+
+__device__ __forceinline__ unsigned long long speed_bits(float s) { return (unsigned long long)__float_as_uint(s); }
+__device__ __forceinline__ unsigned long long speed_bits(double s) { return (unsigned long long)__double_as_longlong(s); }
+template <typename real> __device__ __forceinline__ double bits_speed(unsigned long long b);
+template <> __device__ __forceinline__ double bits_speed<float>(unsigned long long b) { return (double)__uint_as_float((uint32_t)b); }
+template <> __device__ __forceinline__ double bits_speed<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Cell coordinate along axis k (clamped into the grid).
+template <typename real>
+__device__ __forceinline__ int cell_coord(const KP<real>& P, int k, double xk)
+{
+    int c = (int)floor((xk - P.lo[k]) / P.Ld[k]);
+    c = c < 0 ? 0 : c;
+    c = c >= P.n[k] ? P.n[k] - 1 : c;
+    return c;
+}
+
+// FP64 neighbour predicate on absolute positions: dx = x_i - x_j with one
+// minimum-image wrap on periodic axes, r^2 summed left to right, no FMA.
+template <int D, typename real>
+__device__ __forceinline__ double pair_r2(const KP<real>& P, const double* xi, const double* xj)
+{
+#pragma clang fp contract(off)
+    double t[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double u = xi[k] - xj[k];
+        if (P.periodic[k]) {
+            if (u > P.half_period[k]) u -= P.period[k];
+            else if (u < -P.half_period[k]) u += P.period[k];
+        }
+        t[k] = u;
+    }
+    double r2 = t[0] * t[0] + t[1] * t[1];
+    if (D == 3) r2 = r2 + t[2] * t[2];
+    return r2;
+}
+
+// Frozen pair geometry from cell offsets: returns e_ij (from i to j),
+// r_ij and dW/dr of the Wendland C2 kernel with support 2h.
+template <int D, typename real> struct Pair {
+    real e[3];
+    real r;
+    real dW;
+};
+
+template <int D, typename real, typename G>
+__device__ __forceinline__ Pair<D, real> pair_geo(const KP<real>& P, const G& oi, const G& oj, uint32_t code)
+{
+    Pair<D, real> q;
+    real dx[3];
+    dx[0] = (oi.x - oj.x) - (real)((int)(code & 3u) - 1) * P.L[0];
+    dx[1] = (oi.y - oj.y) - (real)((int)((code >> 2) & 3u) - 1) * P.L[1];
+    if constexpr (D == 3) dx[2] = (oi.z - oj.z) - (real)((int)((code >> 4) & 3u) - 1) * P.L[2];
+    else dx[2] = (real)0;
+    real r2 = dx[0] * dx[0] + dx[1] * dx[1] + (D == 3 ? dx[2] * dx[2] : (real)0);
+    real rinv = rsqrt_r(r2);
+    real r = r2 * rinv;
+    real qh = r * P.inv_h;
+    real s = dmax((real)1 - (real)0.5 * qh, (real)0);
+    q.dW = P.dWc * qh * s * s * s;
+    q.r = r;
+    q.e[0] = -dx[0] * rinv;
+    q.e[1] = -dx[1] * rinv;
+    q.e[2] = -dx[2] * rinv;
+    return q;
+}
+
+template <typename real>
+__device__ __forceinline__ real kernel_W(const KP<real>& P, real r)
+{
+    real qh = r * P.inv_h;
+    real s = dmax((real)1 - (real)0.5 * qh, (real)0);
+    return P.Wc * s * s * s * s * ((real)1 + (real)2 * qh);
+}
+
+// ---------------------------------------------------------------------
+// S1: cell binning (counting sort)
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Wrap periodic coordinates, check escapes, compute the cell key and an
+// arrival rank inside the cell. `gate`: skip unless the step is complete.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_bin(KP<real> P, Ctrl* __restrict__ ctrl, int gate, int n,
+                                                double* __restrict__ x0, double* __restrict__ x1,
+                                                double* __restrict__ x2, int32_t* __restrict__ key,
+                                                int32_t* __restrict__ rank, int32_t* __restrict__ cnt,
+                                                int wrap)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* xs[3] = {x0, x1, x2};
+    int c[3] = {0, 0, 0};
+    uint32_t bad = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double xk = xs[k][i];
+        if (xk != xk) bad |= ERR_NAN;
+        if (wrap && P.periodic[k]) {
+            double w = xk;
+            if (w >= P.hi[k]) w -= P.period[k];
+            else if (w < P.lo[k]) w += P.period[k];
+            if (w != xk) { xs[k][i] = w; xk = w; }
+        }
+        if (!(xk >= P.lo[k] && xk < P.hi[k])) bad |= ERR_ESCAPE;
+        c[k] = cell_coord(P, k, xk);
+    }
+    if (bad) atomicOr(&ctrl->err, bad);
+    int kc = c[0] + P.n[0] * (c[1] + P.n[1] * c[2]);
+    key[i] = kc;
+    rank[i] = atomicAdd(&cnt[kc], 1);
+}
+
+// Exclusive scan of cell counts in three passes (block sums, scan of block
+// sums, add); SCAN_ITEMS consecutive cells per thread.
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total)
+{
+    // Hillis-Steele over the block in LDS (BLOCK = 256)
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < BLOCK; o <<= 1) {
+        int a = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    total = sh[BLOCK - 1];
+    int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(Ctrl* __restrict__ ctrl, int gate,
+                                                      const int32_t* __restrict__ cnt, int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ bsum, int n)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    __shared__ int sh[BLOCK];
+    int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        v[q] = base + q < n ? cnt[base + q] : 0;
+        s += v[q];
+    }
+    int total;
+    int ex = block_excl_scan(s, sh, total);
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        if (base + q < n) start[base + q] = ex;
+        ex += v[q];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_top(Ctrl* __restrict__ ctrl, int gate, int32_t* __restrict__ bsum, int nb)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    __shared__ int sh[BLOCK];
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += BLOCK) {
+        int i = b0 + threadIdx.x;
+        int v = i < nb ? bsum[i] : 0;
+        int total;
+        int ex = block_excl_scan(v, sh, total);
+        if (i < nb) bsum[i] = ex + carry;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_add(Ctrl* __restrict__ ctrl, int gate, int32_t* __restrict__ start,
+                                                    const int32_t* __restrict__ bsum, int n, int nb)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int off = bsum[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q)
+        if (base + q < n) start[base + q] += off;
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = bsum[nb];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scatter(Ctrl* __restrict__ ctrl, int gate, int n, const int32_t* __restrict__ key,
+                                                   const int32_t* __restrict__ rank, const int32_t* __restrict__ start,
+                                                   int32_t* __restrict__ perm)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    perm[start[key[i]] + rank[i]] = i;
+}
+
+// Order each cell's particles by their previous sorted index: together with
+// the scatter this is a stable counting sort, so the order (and every sum
+// over it) is deterministic.
+__global__ __launch_bounds__(BLOCK) void k_cell_order(Ctrl* __restrict__ ctrl, int gate, int ncell,
+                                                      const int32_t* __restrict__ start, int32_t* __restrict__ perm)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int s = start[c], e = start[c + 1];
+    for (int a = s + 1; a < e; ++a) {
+        int v = perm[a];
+        int b = a - 1;
+        while (b >= s && perm[b] > v) {
+            perm[b + 1] = perm[b];
+            --b;
+        }
+        perm[b + 1] = v;
+    }
+}
+
+// Gather the fluid state into the new order and freeze the configuration
+// geometry as offsets from the cell origin.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_gather_fluid(
+    KP<real> P, Ctrl* __restrict__ ctrl, int gate, int n, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ key, const double* __restrict__ ax0, const double* __restrict__ ax1,
+    const double* __restrict__ ax2, const R4<real>* __restrict__ ast, const real* __restrict__ adr,
+    const int32_t* __restrict__ aid, double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
+    R4<real>* __restrict__ bst, real* __restrict__ bdr, int32_t* __restrict__ bid, int32_t* __restrict__ bcell,
+    typename GeoSel<D, real>::T* __restrict__ bgeo)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+    int kc = key[i];
+    double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
+    bx0[s] = x[0];
+    bx1[s] = x[1];
+    if (D == 3) bx2[s] = x[2];
+    bst[s] = ast[i];
+    if (D == 3) bdr[s] = adr[i];
+    bid[s] = aid[i];
+    bcell[s] = kc;
+    int c0 = kc % P.n[0];
+    int c1 = (kc / P.n[0]) % P.n[1];
+    int c2 = kc / (P.n[0] * P.n[1]);
+    typename GeoSel<D, real>::T g;
+    g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
+    g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
+    if constexpr (D == 3) {
+        g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
+        g.w = (real)0;
+    }
+    bgeo[s] = g;
+}
+
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_gather_wall(
+    KP<real> P, int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ key,
+    const double* __restrict__ ax0, const double* __restrict__ ax1, const double* __restrict__ ax2,
+    const double* __restrict__ an0, const double* __restrict__ an1, const double* __restrict__ an2,
+    double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
+    typename GeoSel<D, real>::T* __restrict__ bgeo, typename GeoSel<D, real>::T* __restrict__ bnrm,
+    int32_t* __restrict__ bid)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+    int kc = key[i];
+    double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
+    bx0[s] = x[0];
+    bx1[s] = x[1];
+    if (D == 3) bx2[s] = x[2];
+    bid[s] = i;
+    int c0 = kc % P.n[0];
+    int c1 = (kc / P.n[0]) % P.n[1];
+    int c2 = kc / (P.n[0] * P.n[1]);
+    typename GeoSel<D, real>::T g, nn;
+    g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
+    g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
+    nn.x = (real)an0[i];
+    nn.y = (real)an1[i];
+    if constexpr (D == 3) {
+        g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
+        g.w = (real)0;
+        nn.z = (real)an2[i];
+        nn.w = (real)0;
+    }
+    bgeo[s] = g;
+    bnrm[s] = nn;
+}
+
+// ---------------------------------------------------------------------
+// S2: neighbour configuration. For each fluid particle scan the 3^d cells
+// around its cell in the fluid and wall cell lists and keep j != i with
+// r^2 < (2h)^2 (FP64 predicate). Entries keep the cell offset so that the
+// pair geometry can be rebuilt from cell offsets.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_neighbors(
+    KP<real> P, Ctrl* __restrict__ ctrl, int gate, const double* __restrict__ x0, const double* __restrict__ x1,
+    const double* __restrict__ x2, const int32_t* __restrict__ cell, const int32_t* __restrict__ fstart,
+    const double* __restrict__ wx0, const double* __restrict__ wx1, const double* __restrict__ wx2,
+    const int32_t* __restrict__ wstart, uint32_t* __restrict__ nbr, int32_t* __restrict__ ncnt,
+    uint32_t* __restrict__ wnb, int32_t* __restrict__ wcnt)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.nf) return;
+    double xi[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
+    int kc = cell[i];
+    int ci[3] = {kc % P.n[0], (kc / P.n[0]) % P.n[1], kc / (P.n[0] * P.n[1])};
+    int nin = 0, nwl = 0;
+    uint32_t over = 0;
+    const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+        int cz = ci[2] + dz;
+        if (D == 3) {
+            if (P.periodic[2]) cz = cz < 0 ? cz + P.n[2] : (cz >= P.n[2] ? cz - P.n[2] : cz);
+            else if (cz < 0 || cz >= P.n[2]) continue;
+        }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int cy = ci[1] + dy;
+            if (P.periodic[1]) cy = cy < 0 ? cy + P.n[1] : (cy >= P.n[1] ? cy - P.n[1] : cy);
+            else if (cy < 0 || cy >= P.n[1]) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                int cx = ci[0] + dx;
+                if (P.periodic[0]) cx = cx < 0 ? cx + P.n[0] : (cx >= P.n[0] ? cx - P.n[0] : cx);
+                else if (cx < 0 || cx >= P.n[0]) continue;
+                int c = cx + P.n[0] * (cy + P.n[1] * cz);
+                uint32_t code = (uint32_t)(dx + 1) | ((uint32_t)(dy + 1) << 2) | ((uint32_t)(dz + 1) << 4);
+                uint32_t tag = code << NBR_SHIFT;
+                for (int j = fstart[c], je = fstart[c + 1]; j < je; ++j) {
+                    if (j == i) continue;
+                    double xj[3] = {x0[j], x1[j], D == 3 ? x2[j] : 0.0};
+                    if (pair_r2<D>(P, xi, xj) < P.rc2) {
+                        if (nin < P.maxn) nbr[(size_t)nin * P.cap + i] = (uint32_t)j | tag;
+                        else over = 1;
+                        ++nin;
+                    }
+                }
+                if (P.nw > 0) {
+                    for (int w = wstart[c], we = wstart[c + 1]; w < we; ++w) {
+                        double xw[3] = {wx0[w], wx1[w], D == 3 ? wx2[w] : 0.0};
+                        if (pair_r2<D>(P, xi, xw) < P.rc2) {
+                            if (nwl < P.maxw) wnb[(size_t)nwl * P.cap + i] = (uint32_t)w | tag;
+                            else over = 1;
+                            ++nwl;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    ncnt[i] = nin < P.maxn ? nin : P.maxn;
+    wcnt[i] = nwl < P.maxw ? nwl : P.maxw;
+    if (over) atomicOr(&ctrl->err, ERR_NBR_OVERFLOW);
+}
+
+// ---------------------------------------------------------------------
+// S5 at the start of an advection step (one thread): dt_ad from |v|max
+// floored at U_ref, clipped to the stop time, and the first acoustic step.
+// A step still active here ran out of queued sub-steps: flag a stall so the
+// host finishes it. A step that does not start clears the rebuild flag.
+template <typename real>
+__global__ void k_adv_begin(KP<real> P, Ctrl* __restrict__ ctrl)
+{
+    const uint32_t err = ctrl->err;
+    const int pending = ctrl->active;
+    ctrl->rebuild = 0;
+    if (pending) {
+        if (err == 0) ctrl->err = ERR_STALL;
+        return;
+    }
+    const double t = ctrl->t, t_stop = ctrl->t_stop, vmax = ctrl->vmax;
+    if (err != 0 || !(t < t_stop)) return;
+    double dt_ad = P.cfl_ad_h / fmax(vmax, P.u_ref);
+    double t_end = t + dt_ad;
+    if (t_end >= t_stop) {
+        dt_ad = t_stop - t;
+        t_end = t_stop;
+    }
+    double dt_ac = P.cfl_ac_h / (P.c0d + vmax);
+    int last = 0;
+    double dt = dt_ac;
+    if (dt >= dt_ad) {
+        dt = dt_ad;
+        last = 1;
+    }
+    ctrl->dt_ad = dt_ad;
+    ctrl->t_end = t_end;
+    ctrl->tau = 0.0;
+    ctrl->dt = dt;
+    ctrl->last = last;
+    ctrl->nsub = 0;
+    ctrl->blocks_done = 0;
+    ctrl->vmax_bits = 0ull;
+    ctrl->active = 1;
+}
+
+// S4: density re-initialisation rho = max(rho*, rho0 sum W / sum W0) with
+// the sum over the particle itself, its fluid and its wall neighbours.
+// `gate`: run only at the start of an active advection step.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_reinit(
+    KP<real> P, Ctrl* __restrict__ ctrl, int gate, const typename GeoSel<D, real>::T* __restrict__ geo,
+    const typename GeoSel<D, real>::T* __restrict__ wgeo, const uint32_t* __restrict__ nbr,
+    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
+    R4<real>* __restrict__ st)
+{
+    if (gate && (!ctrl->active || ctrl->err)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.nf) return;
+    using G = typename GeoSel<D, real>::T;
+    G oi = geo[i];
+    double sigma = (double)P.Wc;  // W(0)
+    int n = ncnt[i];
+    for (int k = 0; k < n; ++k) {
+        uint32_t e = nbr[(size_t)k * P.cap + i];
+        Pair<D, real> q = pair_geo<D, real>(P, oi, geo[e & NBR_MASK], e >> NBR_SHIFT);
+        sigma += (double)kernel_W(P, q.r);
+    }
+    n = wcnt[i];
+    for (int k = 0; k < n; ++k) {
+        uint32_t e = wnb[(size_t)k * P.cap + i];
+        Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[e & NBR_MASK], e >> NBR_SHIFT);
+        sigma += (double)kernel_W(P, q.r);
+    }
+    real dev_sum = (real)(P.rho0d * (sigma / P.sigma0 - 1.0));
+    R4<real> s = st[i];
+    if (D == 2) {
+        if (dev_sum > s.z) { s.z = dev_sum; st[i] = s; }
+    } else {
+        if (dev_sum > s.w) { s.w = dev_sum; st[i] = s; }
+    }
+}
+
+// ---------------------------------------------------------------------
+// S6: pressure relaxation. First Verlet half-step of density (position
+// half-steps are applied together in S7), EoS, Riemann momentum equation
+// with fluid and wall neighbours and gravity, velocity update.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_pressure(
+    KP<real> P, Ctrl* __restrict__ ctrl, const typename GeoSel<D, real>::T* __restrict__ geo,
+    const typename GeoSel<D, real>::T* __restrict__ wgeo, const typename GeoSel<D, real>::T* __restrict__ wnrm,
+    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
+    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, const real* __restrict__ dr3,
+    R4<real>* __restrict__ hf, real* __restrict__ acc_out)
+{
+    if (!ctrl->active || ctrl->err) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.nf) return;
+    using G = typename GeoSel<D, real>::T;
+    const real dt = (real)ctrl->dt;
+    const real half = (real)0.5 * dt;
+    const R4<real> si = st[i];
+    real vi[3], dev_i;
+    if (D == 2) {
+        vi[0] = si.x; vi[1] = si.y; vi[2] = 0;
+        dev_i = si.z + half * si.w;
+    } else {
+        vi[0] = si.x; vi[1] = si.y; vi[2] = si.z;
+        dev_i = si.w + half * dr3[i];
+    }
+    const real rho_i = P.rho0 + dev_i;
+    const real p_i = P.c2 * dev_i;
+    const real inv_rho_i = (real)1 / rho_i;
+    const G oi = geo[i];
+    real acc[3] = {0, 0, 0};
+    int n = ncnt[i];
+    for (int k = 0; k < n; ++k) {
+        uint32_t e = nbr[(size_t)k * P.cap + i];
+        uint32_t j = e & NBR_MASK;
+        Pair<D, real> q = pair_geo<D, real>(P, oi, geo[j], e >> NBR_SHIFT);
+        R4<real> sj = st[j];
+        real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * dr3[j];
+        real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
+        real UR = sj.x * q.e[0] + sj.y * q.e[1] + (D == 3 ? sj.z * q.e[2] : (real)0);
+        real rho_j = P.rho0 + dev_j;
+        real p_j = P.c2 * dev_j;
+        real du = UL - UR;
+        real beta = dmin((real)3 * dmax(du, (real)0), P.c);
+        real ps = (real)0.5 * (p_i + p_j) + (real)0.25 * beta * (rho_i + rho_j) * du;
+        real coef = P.two_m * ps * inv_rho_i / rho_j * q.dW;
+        acc[0] += coef * q.e[0];
+        acc[1] += coef * q.e[1];
+        if (D == 3) acc[2] += coef * q.e[2];
+    }
+    n = wcnt[i];
+    for (int k = 0; k < n; ++k) {
+        uint32_t e = wnb[(size_t)k * P.cap + i];
+        uint32_t w = e & NBR_MASK;
+        Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[w], e >> NBR_SHIFT);
+        G nw = wnrm[w];
+        real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
+        real du = (real)2 * UL;  // U_R = -U_L for a static wall
+        real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
+        real pR = p_i + rho_i * gr;
+        real rhoR = P.rho0 + pR * P.inv_c2;
+        real beta = dmin((real)3 * dmax(du, (real)0), P.c);
+        real ps = (real)0.5 * (p_i + pR) + (real)0.25 * beta * (rho_i + rhoR) * du;
+        real coef = P.two_vw * ps * inv_rho_i * q.dW;
+        acc[0] += coef * q.e[0];
+        acc[1] += coef * q.e[1];
+        if (D == 3) acc[2] += coef * q.e[2];
+    }
+    acc[0] += P.g[0];
+    acc[1] += P.g[1];
+    acc[2] += P.g[2];
+    R4<real> o;
+    o.x = vi[0] + dt * acc[0];
+    o.y = vi[1] + dt * acc[1];
+    if (D == 2) {
+        o.z = dev_i;
+        o.w = 0;
+    } else {
+        o.z = vi[2] + dt * acc[2];
+        o.w = dev_i;
+    }
+    hf[i] = o;
+    if (acc_out) {
+        acc_out[(size_t)i * D + 0] = acc[0];
+        acc_out[(size_t)i * D + 1] = acc[1];
+        if (D == 3) acc_out[(size_t)i * D + 2] = acc[2];
+    }
+}
+
+// ---------------------------------------------------------------------
+// S7: density relaxation. Riemann continuity equation with fluid and wall
+// neighbours using v^{n+1}, second Verlet half-steps of position (both
+// position half-steps land here, in the paper's order) and density, and the
+// |v|max reduction for the next acoustic step; the last block to finish
+// advances the sub-step clock (S5).
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_density(
+    KP<real> P, Ctrl* __restrict__ ctrl, int finalize, const typename GeoSel<D, real>::T* __restrict__ geo,
+    const typename GeoSel<D, real>::T* __restrict__ wgeo, const typename GeoSel<D, real>::T* __restrict__ wnrm,
+    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
+    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ hf, R4<real>* __restrict__ st,
+    real* __restrict__ dr3, double* __restrict__ x0, double* __restrict__ x1, double* __restrict__ x2,
+    real* __restrict__ drho_out)
+{
+    if (!ctrl->active || ctrl->err) return;
+    __shared__ double smax[BLOCK / 64];
+    __shared__ int s_last;
+    using G = typename GeoSel<D, real>::T;
+    const double dtd = ctrl->dt;
+    const real dt = (real)dtd;
+    const real half = (real)0.5 * dt;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    real speed = 0;
+    uint32_t bad = 0;
+    if (i < P.nf) {
+        const R4<real> hi_ = hf[i];
+        real vi[3];
+        vi[0] = hi_.x; vi[1] = hi_.y;
+        vi[2] = D == 3 ? hi_.z : (real)0;
+        const real dev_i = D == 2 ? hi_.z : hi_.w;
+        const real rho_i = P.rho0 + dev_i;
+        const real p_i = P.c2 * dev_i;
+        const G oi = geo[i];
+        real sum = 0;
+        int n = ncnt[i];
+        for (int k = 0; k < n; ++k) {
+            uint32_t e = nbr[(size_t)k * P.cap + i];
+            uint32_t j = e & NBR_MASK;
+            Pair<D, real> q = pair_geo<D, real>(P, oi, geo[j], e >> NBR_SHIFT);
+            R4<real> hj = hf[j];
+            real dev_j = D == 2 ? hj.z : hj.w;
+            real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
+            real UR = hj.x * q.e[0] + hj.y * q.e[1] + (D == 3 ? hj.z * q.e[2] : (real)0);
+            real rho_j = P.rho0 + dev_j;
+            real p_j = P.c2 * dev_j;
+            real inv_rho_j = (real)1 / rho_j;
+            real rho_bar = (real)0.5 * (rho_i + rho_j);
+            real us = (real)0.5 * (UL + UR) + (p_i - p_j) * P.half_inv_c / rho_bar;
+            sum += P.m * inv_rho_j * (us - UL) * q.dW;
+        }
+        n = wcnt[i];
+        for (int k = 0; k < n; ++k) {
+            uint32_t e = wnb[(size_t)k * P.cap + i];
+            uint32_t w = e & NBR_MASK;
+            Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[w], e >> NBR_SHIFT);
+            G nw = wnrm[w];
+            real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
+            real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
+            real pR = p_i + rho_i * gr;
+            real rhoR = P.rho0 + pR * P.inv_c2;
+            real rho_bar = (real)0.5 * (rho_i + rhoR);
+            real us = (p_i - pR) * P.half_inv_c / rho_bar;  // (U_L + U_R)/2 = 0
+            sum += P.vw * (us - UL) * q.dW;
+        }
+        const real drho = (real)2 * rho_i * sum;
+        const R4<real> so = st[i];
+        const double hd = 0.5 * dtd;
+        x0[i] = x0[i] + hd * (double)so.x;
+        x1[i] = x1[i] + hd * (double)so.y;
+        if (D == 3) x2[i] = x2[i] + hd * (double)so.z;
+        x0[i] = x0[i] + hd * (double)vi[0];
+        x1[i] = x1[i] + hd * (double)vi[1];
+        if (D == 3) x2[i] = x2[i] + hd * (double)vi[2];
+        R4<real> sn;
+        sn.x = vi[0];
+        sn.y = vi[1];
+        if (D == 2) {
+            sn.z = dev_i + half * drho;
+            sn.w = drho;
+        } else {
+            sn.z = vi[2];
+            sn.w = dev_i + half * drho;
+            dr3[i] = drho;
+        }
+        st[i] = sn;
+        if (drho_out) drho_out[i] = drho;
+        speed = sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+        if (drho != drho || speed != speed) bad = ERR_NAN;
+    }
+    if (bad) atomicOr(&ctrl->err_pending, bad);
+    if (!finalize) return;
+    // block max of |v^{n+1}|, one atomic per block
+    double m = wave_max((double)speed);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) smax[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = smax[0];
+        for (int q = 1; q < BLOCK / 64; ++q) b = fmax(b, smax[q]);
+        atomicMax(&ctrl->vmax_bits, speed_bits((real)b));
+        __threadfence();
+        unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+    __threadfence();
+    // last block: advance the sub-step clock and choose the next step size
+    uint32_t pend = atomicOr(&ctrl->err_pending, 0u);
+    if (pend) {
+        ctrl->err_pending = 0u;
+        atomicOr(&ctrl->err, pend);
+    }
+    unsigned long long vb = atomicAdd(&ctrl->vmax_bits, 0ull);
+    double vmax = bits_speed<real>(vb);
+    ctrl->vmax = vmax;
+    ctrl->vmax_bits = 0ull;
+    ctrl->blocks_done = 0u;
+    double tau = ctrl->tau + dtd;
+    ctrl->tau = tau;
+    ctrl->nsub += 1;
+    ctrl->nsub_total += 1;
+    int done = ctrl->last;
+    if (!done) {
+        double rem = ctrl->dt_ad - tau;
+        if (!(rem > 0.0)) {
+            done = 1;
+        } else {
+            double dt_ac = P.cfl_ac_h / (P.c0d + vmax);
+            if (dt_ac >= rem) {
+                ctrl->dt = rem;
+                ctrl->last = 1;
+            } else {
+                ctrl->dt = dt_ac;
+                ctrl->last = 0;
+            }
+        }
+    }
+    if (done) {
+        ctrl->active = 0;
+        ctrl->t = ctrl->t_end;
+        ctrl->steps_done += 1;
+        ctrl->rebuild = 1;
+    }
+    __threadfence();
+}
+
+// ---------------------------------------------------------------------
+// |v|max of the current state (outside the time loop).
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_vmax(KP<real> P, Ctrl* __restrict__ ctrl, const R4<real>* __restrict__ st)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    real sp = 0;
+    if (i < P.nf) {
+        R4<real> s = st[i];
+        sp = D == 2 ? sqrt(s.x * s.x + s.y * s.y) : sqrt(s.x * s.x + s.y * s.y + s.z * s.z);
+    }
+    double m = wave_max((double)sp);
+    if ((threadIdx.x & 63) == 0) atomicMax(&ctrl->vmax_bits, speed_bits((real)m));
+}
+
+template <typename real>
+__global__ void k_vmax_fin(Ctrl* __restrict__ ctrl)
+{
+    ctrl->vmax = bits_speed<real>(ctrl->vmax_bits);
+    ctrl->vmax_bits = 0ull;
+}
+
+// ---------------------------------------------------------------------
+// S8: FP64 diagnostics. Per block partial sums; k_diag_fin reduces them in a
+// fixed order so the result is deterministic.
+constexpr int NDIAG = 8;  // mom0..2, e_kin, e_pot, e_int, front (max), max |dev|/rho0 (max)
+
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_diag(KP<real> P, const double* __restrict__ x0, const double* __restrict__ x1,
+                                                const double* __restrict__ x2, const R4<real>* __restrict__ st,
+                                                double* __restrict__ part)
+{
+    __shared__ double sh[NDIAG][BLOCK / 64];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[NDIAG] = {0, 0, 0, 0, 0, 0, -1e300, 0};
+    if (i < P.nf) {
+        R4<real> s = st[i];
+        double m = P.md;
+        double vel[3] = {(double)s.x, (double)s.y, D == 3 ? (double)s.z : 0.0};
+        double dev = D == 2 ? (double)s.z : (double)s.w;
+        double x[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
+        v[0] = m * vel[0];
+        v[1] = m * vel[1];
+        v[2] = m * vel[2];
+        v[3] = 0.5 * m * (vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]);
+        v[4] = -m * ((double)P.g[0] * x[0] + (double)P.g[1] * x[1] + (double)P.g[2] * x[2]);
+        double a = dev / P.rho0d;                 // rho/rho0 - 1
+        v[5] = m * (double)P.c0d * P.c0d * (log1p(a) - a / (1.0 + a));
+        v[6] = x[0];
+        v[7] = fabs(a);
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NDIAG; ++q) {
+        double r = (q == 6 || q == 7) ? wave_max(v[q]) : wave_sum(v[q]);
+        if (lane == 0) sh[q][wid] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < NDIAG) {
+        int q = threadIdx.x;
+        double r = sh[q][0];
+        for (int w = 1; w < BLOCK / 64; ++w) r = (q == 6 || q == 7) ? fmax(r, sh[q][w]) : r + sh[q][w];
+        part[(size_t)blockIdx.x * NDIAG + q] = r;
+    }
+}
+
+__global__ void k_diag_fin(const double* __restrict__ part, int nb, double* __restrict__ out)
+{
+    int q = threadIdx.x;
+    if (q >= NDIAG) return;
+    double r = (q == 6) ? -1e300 : 0.0;
+    for (int b = 0; b < nb; ++b) {
+        double v = part[(size_t)b * NDIAG + q];
+        r = (q == 6 || q == 7) ? fmax(r, v) : r + v;
+    }
+    out[q] = r;
+}
+
+// ---------------------------------------------------------------------
+// Output helpers: fields back to original id order, as FP64.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_unsort_field(KP<real> P, int which, const int32_t* __restrict__ id,
+                                                        const double* __restrict__ x0, const double* __restrict__ x1,
+                                                        const double* __restrict__ x2, const R4<real>* __restrict__ st,
+                                                        const real* __restrict__ dr3, double* __restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.nf) return;
+    int o = id[i];
+    R4<real> s = st[i];
+    double dev = D == 2 ? (double)s.z : (double)s.w;
+    switch (which) {
+    case 0:
+        out[(size_t)o * D + 0] = x0[i];
+        out[(size_t)o * D + 1] = x1[i];
+        if (D == 3) out[(size_t)o * D + 2] = x2[i];
+        break;
+    case 1:
+        out[(size_t)o * D + 0] = (double)s.x;
+        out[(size_t)o * D + 1] = (double)s.y;
+        if (D == 3) out[(size_t)o * D + 2] = (double)s.z;
+        break;
+    case 2: out[o] = P.rho0d + dev; break;
+    case 3: out[o] = (double)P.c0d * P.c0d * dev; break;
+    case 4: out[o] = D == 2 ? (double)s.w : (double)dr3[i]; break;
+    default: break;
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_unsort_vec(int n, int width, const int32_t* __restrict__ id,
+                                                      const real* __restrict__ in, double* __restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = id[i];
+    for (int k = 0; k < width; ++k) out[(size_t)o * width + k] = (double)in[(size_t)i * width + k];
+}
+
+// Load particles given in original order into the (unsorted) state set.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_load_fluid(KP<real> P, const double* __restrict__ pos,
+                                                      const double* __restrict__ vel, const double* __restrict__ rho,
+                                                      const double* __restrict__ drho, double* __restrict__ x0,
+                                                      double* __restrict__ x1, double* __restrict__ x2,
+                                                      R4<real>* __restrict__ st, real* __restrict__ dr3,
+                                                      int32_t* __restrict__ id)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.nf) return;
+    x0[i] = pos[(size_t)i * D + 0];
+    x1[i] = pos[(size_t)i * D + 1];
+    if (D == 3) x2[i] = pos[(size_t)i * D + 2];
+    double v[3] = {0, 0, 0};
+    if (vel)
+        for (int k = 0; k < D; ++k) v[k] = vel[(size_t)i * D + k];
+    double dev = rho ? rho[i] - P.rho0d : 0.0;
+    double dr = drho ? drho[i] : 0.0;
+    R4<real> s;
+    s.x = (real)v[0];
+    s.y = (real)v[1];
+    if (D == 2) {
+        s.z = (real)dev;
+        s.w = (real)dr;
+    } else {
+        s.z = (real)v[2];
+        s.w = (real)dev;
+        dr3[i] = (real)dr;
+    }
+    st[i] = s;
+    id[i] = i;
+}
+
+}  // namespace sphx

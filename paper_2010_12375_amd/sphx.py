@@ -1,0 +1,236 @@
+"""Thin ctypes binding of libsphx_hip.so (the C ABI in include/sphx.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. There is no CPU fallback: if the library is missing or fails to
+load, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libsphx_hip.so")
+
+SPHX_OK = 0
+SPHX_EINVAL, SPHX_ENOMEM, SPHX_EHIP, SPHX_EESCAPE = -1, -2, -3, -4
+SPHX_ENAN, SPHX_ECAP, SPHX_EOVERFLOW, SPHX_ESTATE = -5, -6, -7, -8
+SPHX_FP64, SPHX_FP32 = 0, 1
+SPHX_INNER, SPHX_CONTACT = 0, 1
+SPHX_FIELD_POS, SPHX_FIELD_VEL, SPHX_FIELD_RHO, SPHX_FIELD_P, SPHX_FIELD_DRHO = 0, 1, 2, 3, 4
+
+ERROR_NAMES = {SPHX_EINVAL: "EINVAL", SPHX_ENOMEM: "ENOMEM", SPHX_EHIP: "EHIP", SPHX_EESCAPE: "EESCAPE",
+               SPHX_ENAN: "ENAN", SPHX_ECAP: "ECAP", SPHX_EOVERFLOW: "EOVERFLOW", SPHX_ESTATE: "ESTATE"}
+
+EXPORTED = ("sphx_create", "sphx_destroy", "sphx_last_error", "sphx_set_fluid", "sphx_set_walls",
+            "sphx_build_neighbors", "sphx_get_neighbors", "sphx_density_reinit", "sphx_time_steps",
+            "sphx_compute_rates", "sphx_advance", "sphx_get_field", "sphx_diagnostics", "sphx_profile",
+            "sphx_counts")
+
+
+class SphxError(RuntimeError):
+    def __init__(self, code, what, msg=""):
+        super().__init__(f"{what} failed: {ERROR_NAMES.get(code, code)} {msg}".strip())
+        self.code = code
+
+
+class sphx_params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("periodic", C.c_int32 * 3),
+                ("nsub_queue", C.c_int32), ("dp", C.c_double), ("h", C.c_double), ("rho0", C.c_double),
+                ("c0", C.c_double), ("u_ref", C.c_double), ("cfl_ad", C.c_double), ("cfl_ac", C.c_double),
+                ("gravity", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("sigma0", C.c_double)]
+
+
+class sphx_diag(C.Structure):
+    _fields_ = [("mass", C.c_double), ("momentum", C.c_double * 3), ("e_kin", C.c_double),
+                ("e_pot", C.c_double), ("e_int", C.c_double), ("front", C.c_double),
+                ("max_drho", C.c_double), ("t", C.c_double), ("n_substeps", C.c_int64),
+                ("n_steps", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load the HIP library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"HIP library not built: {p} (run __graft_entry__.build())")
+    L = C.CDLL(p)
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    pd, pi64 = C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    L.sphx_create.restype = C.c_int
+    L.sphx_create.argtypes = [C.POINTER(sphx_params), vp, C.POINTER(vp)]
+    L.sphx_destroy.restype = None
+    L.sphx_destroy.argtypes = [vp]
+    L.sphx_last_error.restype = C.c_char_p
+    L.sphx_last_error.argtypes = [vp]
+    L.sphx_set_fluid.restype = C.c_int
+    L.sphx_set_fluid.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.sphx_set_walls.restype = C.c_int
+    L.sphx_set_walls.argtypes = [vp, i64, vp, vp]
+    L.sphx_build_neighbors.restype = C.c_int
+    L.sphx_build_neighbors.argtypes = [vp]
+    L.sphx_get_neighbors.restype = C.c_int
+    L.sphx_get_neighbors.argtypes = [vp, C.c_int, vp, vp, i64, pi64]
+    L.sphx_density_reinit.restype = C.c_int
+    L.sphx_density_reinit.argtypes = [vp]
+    L.sphx_time_steps.restype = C.c_int
+    L.sphx_time_steps.argtypes = [vp, pd, pd]
+    L.sphx_compute_rates.restype = C.c_int
+    L.sphx_compute_rates.argtypes = [vp, d, vp, vp]
+    L.sphx_advance.restype = C.c_int
+    L.sphx_advance.argtypes = [vp, i32, d, pi64, pd]
+    L.sphx_get_field.restype = C.c_int
+    L.sphx_get_field.argtypes = [vp, C.c_int, vp]
+    L.sphx_diagnostics.restype = C.c_int
+    L.sphx_diagnostics.argtypes = [vp, C.POINTER(sphx_diag)]
+    L.sphx_profile.restype = C.c_int
+    L.sphx_profile.argtypes = [vp, i32, pd]
+    L.sphx_counts.restype = C.c_int
+    L.sphx_counts.argtypes = [vp, pi64]
+    if path is None:
+        _lib = L
+    return L
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def params_from_case(case, precision=None, nsub_queue=0, sigma0=0.0):
+    p = sphx_params()
+    p.dim = case.dim
+    p.precision = case.precision if precision is None else precision
+    for k in range(3):
+        p.periodic[k] = int(case.periodic[k])
+        p.gravity[k] = float(case.gravity[k])
+        p.lo[k] = float(case.lo[k])
+        p.hi[k] = float(case.hi[k])
+    p.nsub_queue = nsub_queue
+    p.dp, p.h, p.rho0, p.c0 = case.dp, case.h, case.rho0, case.c0
+    p.u_ref, p.cfl_ad, p.cfl_ac = case.u_ref, case.cfl_ad, case.cfl_ac
+    p.sigma0 = sigma0
+    return p
+
+
+class Simulation:
+    """One library context: a fluid body and a static wall body."""
+
+    def __init__(self, params, stream=None, lib=None):
+        self._L = lib or load()
+        self.params = params
+        self.dim = params.dim
+        h = C.c_void_p()
+        s = None
+        if stream is not None:
+            s = getattr(stream, "cuda_stream", stream) or None
+        rc = self._L.sphx_create(C.byref(params), s, C.byref(h))
+        if rc != SPHX_OK:
+            raise SphxError(rc, "sphx_create")
+        self._h = h
+        self.nf = 0
+
+    @classmethod
+    def from_case(cls, case, precision=None, nsub_queue=0, stream=None, with_walls=True):
+        sim = cls(params_from_case(case, precision, nsub_queue), stream=stream)
+        sim.set_fluid(case.fluid_pos)
+        if with_walls and case.n_wall:
+            sim.set_walls(case.wall_pos, case.wall_normal)
+        return sim
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sphx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != SPHX_OK:
+            msg = self._L.sphx_last_error(self._h)
+            raise SphxError(rc, what, msg.decode() if msg else "")
+
+    def set_fluid(self, pos, vel=None, rho=None, drho=None):
+        pos, vel, rho, drho = _f64(pos), _f64(vel), _f64(rho), _f64(drho)
+        self._check(self._L.sphx_set_fluid(self._h, pos.shape[0], _ptr(pos), _ptr(vel), _ptr(rho), _ptr(drho)),
+                    "sphx_set_fluid")
+        self.nf = pos.shape[0]
+
+    def set_walls(self, pos, normal):
+        pos, normal = _f64(pos), _f64(normal)
+        self._check(self._L.sphx_set_walls(self._h, pos.shape[0], _ptr(pos), _ptr(normal)), "sphx_set_walls")
+
+    def build_neighbors(self):
+        self._check(self._L.sphx_build_neighbors(self._h), "sphx_build_neighbors")
+
+    def get_neighbors(self, kind=SPHX_INNER):
+        n = C.c_int64()
+        off = np.zeros(self.nf + 1, dtype=np.int64)
+        self._check(self._L.sphx_get_neighbors(self._h, kind, _ptr(off), None, 0, C.byref(n)), "sphx_get_neighbors")
+        idx = np.zeros(max(n.value, 1), dtype=np.int64)
+        self._check(self._L.sphx_get_neighbors(self._h, kind, None, _ptr(idx), n.value, C.byref(n)),
+                    "sphx_get_neighbors")
+        return off, idx[:n.value]
+
+    def density_reinit(self):
+        self._check(self._L.sphx_density_reinit(self._h), "sphx_density_reinit")
+
+    def time_steps(self):
+        a, b = C.c_double(), C.c_double()
+        self._check(self._L.sphx_time_steps(self._h, C.byref(a), C.byref(b)), "sphx_time_steps")
+        return a.value, b.value
+
+    def compute_rates(self, dt):
+        dvdt = np.zeros((self.nf, self.dim), dtype=np.float64)
+        drho = np.zeros(self.nf, dtype=np.float64)
+        self._check(self._L.sphx_compute_rates(self._h, float(dt), _ptr(dvdt), _ptr(drho)), "sphx_compute_rates")
+        return dvdt, drho
+
+    def advance(self, n_steps=1, t_stop=float("inf")):
+        n = C.c_int64()
+        t = C.c_double()
+        self._check(self._L.sphx_advance(self._h, int(n_steps), float(t_stop), C.byref(n), C.byref(t)),
+                    "sphx_advance")
+        return n.value
+
+    def get_field(self, which):
+        shape = (self.nf, self.dim) if which in (SPHX_FIELD_POS, SPHX_FIELD_VEL) else (self.nf,)
+        out = np.zeros(shape, dtype=np.float64)
+        self._check(self._L.sphx_get_field(self._h, which, _ptr(out)), "sphx_get_field")
+        return out
+
+    def diagnostics(self):
+        d = sphx_diag()
+        self._check(self._L.sphx_diagnostics(self._h, C.byref(d)), "sphx_diagnostics")
+        return dict(mass=d.mass, momentum=np.array(d.momentum[:]), e_kin=d.e_kin, e_pot=d.e_pot,
+                    e_int=d.e_int, front=d.front, max_drho=d.max_drho, t=d.t, n_substeps=d.n_substeps,
+                    n_steps=d.n_steps)
+
+    @property
+    def t(self):
+        return self.diagnostics()["t"]
+
+    def profile(self, reps=20):
+        ms = (C.c_double * 4)()
+        self._check(self._L.sphx_profile(self._h, int(reps), ms), "sphx_profile")
+        return dict(pressure=ms[0], density=ms[1], neighbors=ms[2], reinit=ms[3])
+
+    def counts(self):
+        out = (C.c_int64 * 4)()
+        self._check(self._L.sphx_counts(self._h, out), "sphx_counts")
+        return dict(fluid=out[0], wall=out[1], inner_pairs=out[2], contact_pairs=out[3])

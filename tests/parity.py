@@ -1,0 +1,65 @@
+"""Shared pieces of the GPU-vs-oracle parity tests: identical seeded inputs
+for both sides and the comparison norms (written in the tests that use them).
+"""
+import json
+import os
+
+import numpy as np
+
+import oracle as O
+from paper_2010_12375_amd import sphx
+from paper_2010_12375_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def developed_state(case, seed=0, speed=0.5, noise=1e-4, drho_amp=0.1):
+    """A seeded, non-trivial flow state on the case's particles: hydrostatic
+    density of the column plus small noise, a smooth random velocity field
+    and a random density rate. Nothing here is the method's arithmetic."""
+    rng = np.random.Generator(np.random.PCG64(1000 + seed))
+    x = case.fluid_pos
+    n, d = x.shape
+    H = case.column[1]
+    rho = case.rho0 + case.rho0 * 1.0 * np.clip(H - x[:, 1], 0, None) / case.c0 ** 2
+    rho = rho + rng.uniform(-noise, noise, n)
+    vel = np.zeros((n, d))
+    for _ in range(3):
+        k = rng.normal(0, 2.0, size=d)
+        ph = rng.uniform(0, 2 * np.pi)
+        amp = rng.normal(0, speed / 2, size=d)
+        vel += np.sin(x @ k + ph)[:, None] * amp[None, :]
+    drho = rng.uniform(-drho_amp, drho_amp, n)
+    return vel, rho, drho
+
+
+def make_pair(case, precision, state=None, nsub_queue=0, walls=True):
+    """A GPU simulation and an oracle fed the same particles."""
+    g = sphx.Simulation(sphx.params_from_case(case, precision, nsub_queue))
+    o = O.Oracle(case, with_walls=walls)
+    vel = rho = drho = None
+    if state is not None:
+        vel, rho, drho = state
+    g.set_fluid(case.fluid_pos, vel, rho, drho)
+    o.set_fluid(case.fluid_pos, vel, rho, drho)
+    if walls and case.n_wall:
+        g.set_walls(case.wall_pos, case.wall_normal)
+    return g, o
+
+
+def rate_errors(a_g, a_o, d_g, d_o, gmag=1.0):
+    """Per-particle normalised errors: |da| / (|a| + g) and
+    |ddrho| / (|drho| + rms(drho))."""
+    ea = np.linalg.norm(a_g - a_o, axis=1) / (np.linalg.norm(a_o, axis=1) + gmag)
+    rms = float(np.sqrt(np.mean(d_o ** 2))) if d_o.size else 0.0
+    ed = np.abs(d_g - d_o) / (np.abs(d_o) + rms + 1e-300)
+    return ea, ed
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def energy(row):
+    return row["e_kin"] + row["e_pot"] + row["e_int"]

@@ -1,0 +1,336 @@
+"""HIP path against the FP64 oracle, through the C ABI, on identical seeded
+inputs. Tolerances (the bar the method is held to):
+  neighbour lists: bit-exact (same FP64 predicate on the same positions);
+  FP64 path: rates within 1e-9 (summation order only);
+  FP32 path: |da_i| <= 1e-4 (|a_i| + g), |ddrho_i| <= 1e-4 (|drho_i| + rms drho);
+  runs: surge front and total energy within 1 %.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle_cases import jitter, lattice
+from paper_2010_12375_amd import sphx
+from paper_2010_12375_amd import workloads as wl
+from parity import developed_state, energy, load_golden, make_pair, rate_errors
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = sphx.SPHX_FP64, sphx.SPHX_FP32
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tiny_case(dim, n, seed, periodic=(0, 0, 0), walls=True, dp=0.1, box=None):
+    """n uniform random particles at the lattice number density 1/dp^dim."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if box is None:
+        box = (n * dp ** dim) ** (1.0 / dim)
+    lo = [-0.4, -0.4, -0.4 if dim == 3 else 0.0]
+    hi = [box + 0.4, box + 0.4, box + 0.4 if dim == 3 else 0.0]
+    for k in range(3):
+        if periodic[k]:
+            lo[k], hi[k] = 0.0, box
+    pos = rng.uniform(0.0, box, size=(n, dim))
+    if walls:
+        nw = n // 5
+        wpos = rng.uniform(0.0, box, size=(nw, dim))
+        wpos[:, 1] = rng.uniform(-0.35, -0.01, nw)
+        wn = np.zeros((nw, dim))
+        wn[:, 1] = 1.0
+    else:
+        wpos = np.zeros((0, dim))
+        wn = np.zeros((0, dim))
+    c0 = 10.0
+    return wl.Case(name=f"tiny{dim}d_{seed}", dim=dim, dp=dp, h=1.3 * dp, rho0=1.0, c0=c0, u_ref=c0 / 10,
+                   cfl_ad=0.25, cfl_ac=0.6, gravity=(0.0, -1.0, 0.0), lo=tuple(lo), hi=tuple(hi),
+                   periodic=tuple(periodic), fluid_pos=pos, wall_pos=wpos, wall_normal=wn, column=(box, box))
+
+
+def lists_equal(g, o, kind):
+    og, ig = g.get_neighbors(kind)
+    oo, io = o.neighbors(kind)
+    return np.array_equal(og, oo) and np.array_equal(ig, io)
+
+
+# ---------------------------------------------------------------------------
+# S1-S2: neighbour configuration, bit-exact
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("dim,periodic,seed", [(2, (0, 0, 0), 0), (2, (1, 0, 0), 1), (3, (0, 0, 1), 2),
+                                               (3, (1, 1, 1), 3)])
+def test_neighbors_bitexact_tiny(precision, dim, periodic, seed):
+    walls = not periodic[1]
+    case = tiny_case(dim, 700 if dim == 2 else 900, seed, periodic, walls=walls)
+    say("tiny lists", dim, periodic, seed, precision)
+    g, o = make_pair(case, precision, walls=walls)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o, sphx.SPHX_INNER)
+    assert lists_equal(g, o, sphx.SPHX_CONTACT)
+
+
+def test_neighbors_bitexact_ties_at_support():
+    """Lattice with 2h a multiple of dp: pairs at r = 2h up to rounding."""
+    dp = 0.1
+    pos = lattice((14, 14), dp)
+    case = wl.Case(name="ties", dim=2, dp=dp, h=dp, rho0=1.0, c0=10.0, u_ref=1.0, cfl_ad=0.25, cfl_ac=0.6,
+                   gravity=(0, 0, 0), lo=(-1.0, -1.0, 0), hi=(2.5, 2.5, 0), periodic=(0, 0, 0), fluid_pos=pos,
+                   wall_pos=np.zeros((0, 2)), wall_normal=np.zeros((0, 2)), column=(1.4, 1.4))
+    g, o = make_pair(case, FP32)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o, sphx.SPHX_INNER)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_neighbors_bitexact_dambreak_small(seed):
+    case = wl.config_small(seed)
+    g, o = make_pair(case, FP64)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o, sphx.SPHX_INNER)
+    assert lists_equal(g, o, sphx.SPHX_CONTACT)
+
+
+def test_neighbors_bitexact_dambreak_medium():
+    case = wl.config_medium(0)
+    say("lists medium", case.n_fluid, case.n_wall)
+    g, o = make_pair(case, FP32, developed_state(case))
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o, sphx.SPHX_INNER)
+    assert lists_equal(g, o, sphx.SPHX_CONTACT)
+
+
+# ---------------------------------------------------------------------------
+# S4-S7: re-initialisation, time steps, rates of one sub-step
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-9), (FP32, 1e-4)])
+@pytest.mark.parametrize("which", ["small", "medium", "tiny3d"])
+def test_rates_parity(precision, tol, which):
+    if which == "small":
+        case = wl.config_small(1)
+    elif which == "medium":
+        case = wl.config_medium(0)
+    else:
+        case = tiny_case(3, 1500, 7, (0, 0, 1))
+    say("rates", which, precision, case.n_fluid)
+    g, o = make_pair(case, precision, developed_state(case))
+    g.build_neighbors()
+    o.build_config()
+    dt_ad, dt_ac = o.time_steps()
+    ag, dg = g.compute_rates(dt_ac)
+    ao, do = o.compute_rates(dt_ac)
+    ea, ed = rate_errors(ag, ao, dg, do)
+    say("max err a", ea.max(), "drho", ed.max())
+    assert ea.max() <= tol
+    assert ed.max() <= tol
+    # the state is left unchanged by compute_rates
+    ag2, dg2 = g.compute_rates(dt_ac)
+    assert np.array_equal(ag, ag2) and np.array_equal(dg, dg2)
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-13), (FP32, 1e-6)])
+def test_density_reinit_parity(precision, tol):
+    case = wl.config_small(2)
+    vel, rho, drho = developed_state(case)
+    rho = rho - 0.004  # below the kernel-sum density in the interior
+    g, o = make_pair(case, precision, (vel, rho, drho))
+    g.build_neighbors()
+    o.build_config()
+    g.density_reinit()
+    o.density_reinit()
+    rg = g.get_field(sphx.SPHX_FIELD_RHO)
+    ro = o.field(O.FIELD_RHO)
+    changed = ro != rho
+    assert changed.sum() > 100
+    assert np.abs(rg - ro).max() <= tol
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_time_steps_parity(precision):
+    case = wl.config_small(3)
+    g, o = make_pair(case, precision, developed_state(case, speed=3.0))
+    a = g.time_steps()
+    b = o.time_steps()
+    rel = 1e-15 if precision == FP64 else 1e-6
+    assert a[0] == pytest.approx(b[0], rel=rel) and a[1] == pytest.approx(b[1], rel=rel)
+
+
+# ---------------------------------------------------------------------------
+# Whole advection steps
+
+def run_observed(sim, t_end, every=0.1):
+    rows = []
+    k = 0
+    while True:
+        d = sim.diagnostics()
+        rows.append(d)
+        k += 1
+        T = round(every * k, 10)
+        if T > t_end + 1e-12:
+            return rows
+        sim.advance(100000, T)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_dambreak_small_fp64_tracks_oracle(seed):
+    """FP64 path: the whole run to t = 1 follows the oracle to rounding."""
+    case = wl.config_small(seed)
+    gold = load_golden("oracle_dambreak2d_800.json")["seeds"][str(seed)]
+    g, o = make_pair(case, FP64)
+    rows = run_observed(g, 1.0)
+    assert len(rows) == len(gold)
+    E0 = energy(gold[0])
+    for r, go in zip(rows, gold):
+        assert r["t"] == pytest.approx(go["t"], abs=1e-12)
+        assert r["n_substeps"] == go["nsub"]
+        assert abs(r["front"] - go["front"]) <= 1e-9 * go["front"]
+        assert abs(energy(r) - energy(go)) <= 1e-9 * E0
+    # positions at the end, particle by particle (same observer stops)
+    o.build_config()
+    for k in range(1, 11):
+        T = round(0.1 * k, 10)
+        while o.t < T:
+            o.advance(T)
+    xo = o.field(O.FIELD_POS)
+    xg = g.get_field(sphx.SPHX_FIELD_POS)
+    assert np.abs(xg - xo).max() < 1e-8
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_dambreak_small_fp32_within_one_percent(seed):
+    case = wl.config_small(seed)
+    gold = load_golden("oracle_dambreak2d_800.json")["seeds"][str(seed)]
+    g, _ = make_pair(case, FP32)
+    rows = run_observed(g, 1.0)
+    E0 = energy(gold[0])
+    for r, go in zip(rows, gold):
+        assert abs(r["front"] - go["front"]) <= 0.01 * go["front"]
+        assert abs(energy(r) - energy(go)) <= 0.01 * E0
+
+
+def test_runs_are_deterministic():
+    case = wl.config_medium(0)
+    out = []
+    for _ in range(2):
+        g, _ = make_pair(case, FP32)
+        g.advance(20)
+        out.append(g.get_field(sphx.SPHX_FIELD_POS).tobytes() + g.get_field(sphx.SPHX_FIELD_RHO).tobytes())
+        g.close()
+    assert out[0] == out[1]
+
+
+def test_short_substep_queue_gives_identical_results():
+    """An advection step that needs more sub-steps than the graph queues is
+    finished from the host: same arithmetic, same bits."""
+    case = wl.config_small(4)
+    res = []
+    for q in (2, 0):
+        g, _ = make_pair(case, FP32, nsub_queue=q)
+        n = g.advance(15)
+        res.append((n, g.get_field(sphx.SPHX_FIELD_POS).tobytes(), g.diagnostics()["t"]))
+    assert res[0] == res[1]
+
+
+def test_advance_counts_and_clock():
+    case = wl.config_small(0)
+    g, o = make_pair(case, FP64)
+    n1 = g.advance(3)
+    d = g.diagnostics()
+    assert d["n_steps"] == 3 and d["n_substeps"] == n1
+    o.build_config()
+    n2 = sum(o.advance(10.0) for _ in range(3))
+    assert n1 == n2
+    assert d["t"] == o.t
+    # stop time: lands exactly
+    g.advance(1000, 0.05)
+    assert g.diagnostics()["t"] == 0.05
+
+
+def test_diagnostics_parity():
+    case = wl.config_small(1)
+    st = developed_state(case)
+    g, o = make_pair(case, FP64, st)
+    dg = g.diagnostics()
+    do = o.diagnostics()
+    assert dg["mass"] == do["mass"]
+    for k in ("e_kin", "e_pot", "front", "max_drho"):
+        assert dg[k] == pytest.approx(do[k], rel=1e-12)
+    assert dg["e_int"] == pytest.approx(do["e_int"], rel=1e-9)
+    assert np.allclose(dg["momentum"], do["momentum"], rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+
+def test_free_fall_single_particle_is_exact():
+    case = tiny_case(2, 1, 0, walls=False)
+    case.fluid_pos = np.array([[0.5, 0.5]])
+    case.lo, case.hi = (-5.0, -50.0, 0.0), (5.0, 5.0, 0.0)
+    g = sphx.Simulation.from_case(case, precision=FP64, with_walls=False)
+    g.advance(30)
+    t = g.diagnostics()["t"]
+    x = g.get_field(sphx.SPHX_FIELD_POS)
+    assert x[0, 1] == pytest.approx(0.5 - 0.5 * t * t, rel=1e-13)
+
+
+def test_escape_is_reported():
+    case = tiny_case(2, 50, 1, walls=False)
+    case.fluid_pos[3] = [5.0, 0.5]
+    g = sphx.Simulation.from_case(case, precision=FP32, with_walls=False)
+    with pytest.raises(sphx.SphxError) as e:
+        g.build_neighbors()
+    assert e.value.code == sphx.SPHX_EESCAPE
+
+
+def test_neighbour_overflow_is_reported():
+    case = tiny_case(2, 60, 2, walls=False)
+    case.fluid_pos = 0.5 + 1e-3 * np.random.Generator(np.random.PCG64(0)).uniform(size=(60, 2))
+    g = sphx.Simulation.from_case(case, precision=FP32, with_walls=False)
+    with pytest.raises(sphx.SphxError) as e:
+        g.build_neighbors()
+    assert e.value.code == sphx.SPHX_EOVERFLOW
+
+
+def test_calls_out_of_order_and_bad_arguments():
+    case = wl.config_small(0)
+    g = sphx.Simulation(sphx.params_from_case(case, FP32))
+    with pytest.raises(sphx.SphxError) as e:
+        g.build_neighbors()
+    assert e.value.code == sphx.SPHX_ESTATE
+    g.set_fluid(case.fluid_pos)
+    with pytest.raises(sphx.SphxError) as e:
+        g.compute_rates(1e-3)
+    assert e.value.code == sphx.SPHX_ESTATE
+    with pytest.raises(sphx.SphxError) as e:
+        g.set_walls(case.wall_pos + 100.0, case.wall_normal)
+    assert e.value.code == sphx.SPHX_EINVAL
+    p = sphx.params_from_case(case, FP32)
+    p.dim = 4
+    with pytest.raises(sphx.SphxError):
+        sphx.Simulation(p)
+
+
+def test_no_walls_and_refill():
+    """A context can be refilled with a different particle count."""
+    case = tiny_case(2, 400, 5, walls=False, periodic=(1, 1, 0))
+    g, o = make_pair(case, FP64, walls=False)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o, sphx.SPHX_INNER)
+    off, idx = g.get_neighbors(sphx.SPHX_CONTACT)
+    assert off[-1] == 0 and idx.size == 0
+    small = case.fluid_pos[:123]
+    g.set_fluid(small)
+    o.set_fluid(small)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o, sphx.SPHX_INNER)
