@@ -76,7 +76,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--profile-reps", type=int, default=50)
+    ap.add_argument("--no-torch", action="store_true", help="let the library create its own stream")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="MiB: only run a plain device-to-device copy of this size five times (the "
+                         "reference kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 2 ** 20) // 4
+        a = torch.ones(n, device="cuda", dtype=torch.float32)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
               "described in DESIGN.md, not built.", file=sys.stderr)
@@ -97,6 +111,8 @@ def main():
     stream = None
     torch = None
     try:
+        if args.no_torch:
+            raise ImportError
         import torch  # noqa: F401
         if torch.cuda.is_available():
             stream = torch.cuda.Stream()

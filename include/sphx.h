@@ -58,7 +58,7 @@ typedef struct {
     int32_t dim;         /* 2 or 3 */
     int32_t precision;   /* SPHX_FP64 or SPHX_FP32 */
     int32_t periodic[3]; /* periodic axes (period = hi - lo); need >= 3 cells of 2h */
-    int32_t nsub_queue;  /* acoustic sub-steps queued per advection step (0: default 6);
+    int32_t nsub_queue;  /* acoustic sub-steps queued per advection step (0: default 5);
                             a step that needs more is finished by the host, same result */
     double dp;           /* initial particle spacing: fluid mass rho0 dp^dim, wall volume dp^dim */
     double h;            /* smoothing length; Wendland C2 support radius 2h */

@@ -253,7 +253,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total)
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_tiles(Ctrl* __restrict__ ctrl, int gate,
-                                                      const int32_t* __restrict__ cnt, int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ cnt, int32_t* __restrict__ start,
                                                       int32_t* __restrict__ bsum, int n)
 {
     if (gate && (!ctrl->rebuild || ctrl->err)) return;
@@ -266,6 +266,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_tiles(Ctrl* __restrict__ ctrl, i
         v[q] = base + q < n ? cnt[base + q] : 0;
         s += v[q];
     }
+    // the counts are consumed here: leave them zeroed for the next binning
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q)
+        if (base + q < n) cnt[base + q] = 0;
     int total;
     int ex = block_excl_scan(s, sh, total);
 #pragma unroll
@@ -312,7 +316,8 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Ctrl* __restrict__ ctrl, int 
     if (gate && (!ctrl->rebuild || ctrl->err)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    perm[start[key[i]] + rank[i]] = i;
+    int p = start[key[i]] + rank[i];
+    if (p < n) perm[p] = i;  // always true for consistent counts
 }
 
 // Order each cell's particles by their previous sorted index: together with
@@ -352,6 +357,49 @@ __global__ __launch_bounds__(BLOCK) void k_gather_fluid(
     if (s >= n) return;
     int i = perm[s];
     int kc = key[i];
+    double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
+    bx0[s] = x[0];
+    bx1[s] = x[1];
+    if (D == 3) bx2[s] = x[2];
+    bst[s] = ast[i];
+    if (D == 3) bdr[s] = adr[i];
+    bid[s] = aid[i];
+    bcell[s] = kc;
+    int c0 = kc % P.n[0];
+    int c1 = (kc / P.n[0]) % P.n[1];
+    int c2 = kc / (P.n[0] * P.n[1]);
+    typename GeoSel<D, real>::T g;
+    g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
+    g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
+    if constexpr (D == 3) {
+        g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
+        g.w = (real)0;
+    }
+    bgeo[s] = g;
+}
+
+// Stable placement: a particle's slot in its new cell is the number of
+// particles of that cell with a smaller previous index (counted over the
+// cell's arrival-order list from k_scatter), which is the order of a stable
+// counting sort. The particle's state moves there and the configuration
+// geometry is frozen as offsets from the cell origin.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_place_fluid(
+    KP<real> P, Ctrl* __restrict__ ctrl, int gate, int n, const int32_t* __restrict__ arrival,
+    const int32_t* __restrict__ key, const int32_t* __restrict__ start, const double* __restrict__ ax0,
+    const double* __restrict__ ax1, const double* __restrict__ ax2, const R4<real>* __restrict__ ast,
+    const real* __restrict__ adr, const int32_t* __restrict__ aid, double* __restrict__ bx0,
+    double* __restrict__ bx1, double* __restrict__ bx2, R4<real>* __restrict__ bst, real* __restrict__ bdr,
+    int32_t* __restrict__ bid, int32_t* __restrict__ bcell, typename GeoSel<D, real>::T* __restrict__ bgeo)
+{
+    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int kc = key[i];
+    int s0 = start[kc], s1 = min(start[kc + 1], n);
+    int s = s0;
+    for (int q = s0; q < s1; ++q) s += arrival[q] < i;
+    if (s >= n) return;  // never for consistent counts
     double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
     bx0[s] = x[0];
     bx1[s] = x[1];
@@ -413,8 +461,11 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
 // S2: neighbour configuration. For each fluid particle scan the 3^d cells
 // around its cell in the fluid and wall cell lists and keep j != i with
 // r^2 < (2h)^2 (FP64 predicate). Entries keep the cell offset so that the
-// pair geometry can be rebuilt from cell offsets.
-template <int D, typename real>
+// pair geometry can be rebuilt from cell offsets. T lanes share one
+// particle: they test T candidates at a time and append the hits in
+// candidate order through a ballot, so the list (and every later sum over
+// it) does not depend on T.
+template <int D, typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_neighbors(
     KP<real> P, Ctrl* __restrict__ ctrl, int gate, const double* __restrict__ x0, const double* __restrict__ x1,
     const double* __restrict__ x2, const int32_t* __restrict__ cell, const int32_t* __restrict__ fstart,
@@ -422,9 +473,15 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(
     const int32_t* __restrict__ wstart, uint32_t* __restrict__ nbr, int32_t* __restrict__ ncnt,
     uint32_t* __restrict__ wnb, int32_t* __restrict__ wcnt)
 {
+    static_assert(64 % T == 0, "lane groups must tile a wavefront");
     if (gate && (!ctrl->rebuild || ctrl->err)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P.nf) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / T;
+    const int l = gid % T;
+    if (i >= P.nf) return;  // whole lane groups leave together
+    const int gbase = (int)(threadIdx.x & 63) & ~(T - 1);
+    const unsigned long long gmask = T == 64 ? ~0ull : ((1ull << T) - 1ull);
+    const unsigned long long below = (1ull << l) - 1ull;
     double xi[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
     int kc = cell[i];
     int ci[3] = {kc % P.n[0], (kc / P.n[0]) % P.n[1], kc / (P.n[0] * P.n[1])};
@@ -448,31 +505,62 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(
                 int c = cx + P.n[0] * (cy + P.n[1] * cz);
                 uint32_t code = (uint32_t)(dx + 1) | ((uint32_t)(dy + 1) << 2) | ((uint32_t)(dz + 1) << 4);
                 uint32_t tag = code << NBR_SHIFT;
-                for (int j = fstart[c], je = fstart[c + 1]; j < je; ++j) {
-                    if (j == i) continue;
-                    double xj[3] = {x0[j], x1[j], D == 3 ? x2[j] : 0.0};
-                    if (pair_r2<D>(P, xi, xj) < P.rc2) {
-                        if (nin < P.maxn) nbr[(size_t)nin * P.cap + i] = (uint32_t)j | tag;
-                        else over = 1;
-                        ++nin;
+                for (int j0 = fstart[c], je = min(fstart[c + 1], P.nf); j0 < je; j0 += T) {
+                    int j = j0 + l;
+                    bool in = false;
+                    if (j < je && j != i) {
+                        double xj[3] = {x0[j], x1[j], D == 3 ? x2[j] : 0.0};
+                        in = pair_r2<D>(P, xi, xj) < P.rc2;
                     }
+                    unsigned long long m = (__ballot(in) >> gbase) & gmask;
+                    if (in) {
+                        int slot = nin + __popcll(m & below);
+                        if (slot < P.maxn) nbr[(size_t)slot * P.cap + i] = (uint32_t)j | tag;
+                        else over = 1;
+                    }
+                    nin += __popcll(m);
                 }
                 if (P.nw > 0) {
-                    for (int w = wstart[c], we = wstart[c + 1]; w < we; ++w) {
-                        double xw[3] = {wx0[w], wx1[w], D == 3 ? wx2[w] : 0.0};
-                        if (pair_r2<D>(P, xi, xw) < P.rc2) {
-                            if (nwl < P.maxw) wnb[(size_t)nwl * P.cap + i] = (uint32_t)w | tag;
-                            else over = 1;
-                            ++nwl;
+                    for (int w0 = wstart[c], we = min(wstart[c + 1], P.nw); w0 < we; w0 += T) {
+                        int w = w0 + l;
+                        bool in = false;
+                        if (w < we) {
+                            double xw[3] = {wx0[w], wx1[w], D == 3 ? wx2[w] : 0.0};
+                            in = pair_r2<D>(P, xi, xw) < P.rc2;
                         }
+                        unsigned long long m = (__ballot(in) >> gbase) & gmask;
+                        if (in) {
+                            int slot = nwl + __popcll(m & below);
+                            if (slot < P.maxw) wnb[(size_t)slot * P.cap + i] = (uint32_t)w | tag;
+                            else over = 1;
+                        }
+                        nwl += __popcll(m);
                     }
                 }
             }
         }
     }
-    ncnt[i] = nin < P.maxn ? nin : P.maxn;
-    wcnt[i] = nwl < P.maxw ? nwl : P.maxw;
+    if (l == 0) {
+        ncnt[i] = nin < P.maxn ? nin : P.maxn;
+        wcnt[i] = nwl < P.maxw ? nwl : P.maxw;
+    }
     if (over) atomicOr(&ctrl->err, ERR_NBR_OVERFLOW);
+}
+
+// Sum over the T lanes of a group (groups are aligned inside the wavefront).
+template <int T>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+template <int T>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
 // ---------------------------------------------------------------------
@@ -518,8 +606,9 @@ __global__ void k_adv_begin(KP<real> P, Ctrl* __restrict__ ctrl)
 
 // S4: density re-initialisation rho = max(rho*, rho0 sum W / sum W0) with
 // the sum over the particle itself, its fluid and its wall neighbours.
-// `gate`: run only at the start of an active advection step.
-template <int D, typename real>
+// `gate`: run only at the start of an active advection step. T lanes share a
+// particle and split its neighbour list.
+template <int D, typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_reinit(
     KP<real> P, Ctrl* __restrict__ ctrl, int gate, const typename GeoSel<D, real>::T* __restrict__ geo,
     const typename GeoSel<D, real>::T* __restrict__ wgeo, const uint32_t* __restrict__ nbr,
@@ -527,23 +616,27 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
     R4<real>* __restrict__ st)
 {
     if (gate && (!ctrl->active || ctrl->err)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / T;
+    const int l = gid % T;
     if (i >= P.nf) return;
     using G = typename GeoSel<D, real>::T;
-    G oi = geo[i];
-    double sigma = (double)P.Wc;  // W(0)
+    const G oi = geo[i];
+    double sigma = 0.0;
     int n = ncnt[i];
-    for (int k = 0; k < n; ++k) {
+    for (int k = l; k < n; k += T) {
         uint32_t e = nbr[(size_t)k * P.cap + i];
         Pair<D, real> q = pair_geo<D, real>(P, oi, geo[e & NBR_MASK], e >> NBR_SHIFT);
         sigma += (double)kernel_W(P, q.r);
     }
     n = wcnt[i];
-    for (int k = 0; k < n; ++k) {
+    for (int k = l; k < n; k += T) {
         uint32_t e = wnb[(size_t)k * P.cap + i];
         Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[e & NBR_MASK], e >> NBR_SHIFT);
         sigma += (double)kernel_W(P, q.r);
     }
+    sigma = group_sum<T>(sigma) + (double)P.Wc;  // + W(0), the particle itself
+    if (l != 0) return;
     real dev_sum = (real)(P.rho0d * (sigma / P.sigma0 - 1.0));
     R4<real> s = st[i];
     if (D == 2) {
@@ -556,8 +649,10 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
 // ---------------------------------------------------------------------
 // S6: pressure relaxation. First Verlet half-step of density (position
 // half-steps are applied together in S7), EoS, Riemann momentum equation
-// with fluid and wall neighbours and gravity, velocity update.
-template <int D, typename real>
+// with fluid and wall neighbours and gravity, velocity update. T lanes share
+// a particle: each takes every T-th neighbour, partial sums are combined
+// with shuffles and lane 0 writes.
+template <int D, typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_pressure(
     KP<real> P, Ctrl* __restrict__ ctrl, const typename GeoSel<D, real>::T* __restrict__ geo,
     const typename GeoSel<D, real>::T* __restrict__ wgeo, const typename GeoSel<D, real>::T* __restrict__ wnrm,
@@ -566,7 +661,9 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     R4<real>* __restrict__ hf, real* __restrict__ acc_out)
 {
     if (!ctrl->active || ctrl->err) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / T;
+    const int l = gid % T;
     if (i >= P.nf) return;
     using G = typename GeoSel<D, real>::T;
     const real dt = (real)ctrl->dt;
@@ -586,7 +683,7 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     const G oi = geo[i];
     real acc[3] = {0, 0, 0};
     int n = ncnt[i];
-    for (int k = 0; k < n; ++k) {
+    for (int k = l; k < n; k += T) {
         uint32_t e = nbr[(size_t)k * P.cap + i];
         uint32_t j = e & NBR_MASK;
         Pair<D, real> q = pair_geo<D, real>(P, oi, geo[j], e >> NBR_SHIFT);
@@ -605,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
         if (D == 3) acc[2] += coef * q.e[2];
     }
     n = wcnt[i];
-    for (int k = 0; k < n; ++k) {
+    for (int k = l; k < n; k += T) {
         uint32_t e = wnb[(size_t)k * P.cap + i];
         uint32_t w = e & NBR_MASK;
         Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[w], e >> NBR_SHIFT);
@@ -622,6 +719,10 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
         acc[1] += coef * q.e[1];
         if (D == 3) acc[2] += coef * q.e[2];
     }
+    acc[0] = group_sum<T>(acc[0]);
+    acc[1] = group_sum<T>(acc[1]);
+    if (D == 3) acc[2] = group_sum<T>(acc[2]);
+    if (l != 0) return;
     acc[0] += P.g[0];
     acc[1] += P.g[1];
     acc[2] += P.g[2];
@@ -648,24 +749,25 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
 // neighbours using v^{n+1}, second Verlet half-steps of position (both
 // position half-steps land here, in the paper's order) and density, and the
 // |v|max reduction for the next acoustic step; the last block to finish
-// advances the sub-step clock (S5).
-template <int D, typename real>
+// advances the sub-step clock (S5). T lanes share a particle as in S6.
+template <int D, typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_density(
     KP<real> P, Ctrl* __restrict__ ctrl, int finalize, const typename GeoSel<D, real>::T* __restrict__ geo,
     const typename GeoSel<D, real>::T* __restrict__ wgeo, const typename GeoSel<D, real>::T* __restrict__ wnrm,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
     const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ hf, R4<real>* __restrict__ st,
     real* __restrict__ dr3, double* __restrict__ x0, double* __restrict__ x1, double* __restrict__ x2,
-    real* __restrict__ drho_out)
+    real* __restrict__ drho_out, double* __restrict__ bmax)
 {
     if (!ctrl->active || ctrl->err) return;
     __shared__ double smax[BLOCK / 64];
-    __shared__ int s_last;
     using G = typename GeoSel<D, real>::T;
     const double dtd = ctrl->dt;
     const real dt = (real)dtd;
     const real half = (real)0.5 * dt;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / T;
+    const int l = gid % T;
     real speed = 0;
     uint32_t bad = 0;
     if (i < P.nf) {
@@ -679,7 +781,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
         const G oi = geo[i];
         real sum = 0;
         int n = ncnt[i];
-        for (int k = 0; k < n; ++k) {
+        for (int k = l; k < n; k += T) {
             uint32_t e = nbr[(size_t)k * P.cap + i];
             uint32_t j = e & NBR_MASK;
             Pair<D, real> q = pair_geo<D, real>(P, oi, geo[j], e >> NBR_SHIFT);
@@ -695,7 +797,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
             sum += P.m * inv_rho_j * (us - UL) * q.dW;
         }
         n = wcnt[i];
-        for (int k = 0; k < n; ++k) {
+        for (int k = l; k < n; k += T) {
             uint32_t e = wnb[(size_t)k * P.cap + i];
             uint32_t w = e & NBR_MASK;
             Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[w], e >> NBR_SHIFT);
@@ -708,60 +810,75 @@ __global__ __launch_bounds__(BLOCK) void k_density(
             real us = (p_i - pR) * P.half_inv_c / rho_bar;  // (U_L + U_R)/2 = 0
             sum += P.vw * (us - UL) * q.dW;
         }
-        const real drho = (real)2 * rho_i * sum;
-        const R4<real> so = st[i];
-        const double hd = 0.5 * dtd;
-        x0[i] = x0[i] + hd * (double)so.x;
-        x1[i] = x1[i] + hd * (double)so.y;
-        if (D == 3) x2[i] = x2[i] + hd * (double)so.z;
-        x0[i] = x0[i] + hd * (double)vi[0];
-        x1[i] = x1[i] + hd * (double)vi[1];
-        if (D == 3) x2[i] = x2[i] + hd * (double)vi[2];
-        R4<real> sn;
-        sn.x = vi[0];
-        sn.y = vi[1];
-        if (D == 2) {
-            sn.z = dev_i + half * drho;
-            sn.w = drho;
-        } else {
-            sn.z = vi[2];
-            sn.w = dev_i + half * drho;
-            dr3[i] = drho;
+        sum = group_sum<T>(sum);
+        if (l == 0) {
+            const real drho = (real)2 * rho_i * sum;
+            const R4<real> so = st[i];
+            const double hd = 0.5 * dtd;
+            x0[i] = x0[i] + hd * (double)so.x;
+            x1[i] = x1[i] + hd * (double)so.y;
+            if (D == 3) x2[i] = x2[i] + hd * (double)so.z;
+            x0[i] = x0[i] + hd * (double)vi[0];
+            x1[i] = x1[i] + hd * (double)vi[1];
+            if (D == 3) x2[i] = x2[i] + hd * (double)vi[2];
+            R4<real> sn;
+            sn.x = vi[0];
+            sn.y = vi[1];
+            if (D == 2) {
+                sn.z = dev_i + half * drho;
+                sn.w = drho;
+            } else {
+                sn.z = vi[2];
+                sn.w = dev_i + half * drho;
+                dr3[i] = drho;
+            }
+            st[i] = sn;
+            if (drho_out) drho_out[i] = drho;
+            speed = sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+            if (drho != drho || speed != speed) bad = ERR_NAN;
         }
-        st[i] = sn;
-        if (drho_out) drho_out[i] = drho;
-        speed = sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
-        if (drho != drho || speed != speed) bad = ERR_NAN;
     }
     if (bad) atomicOr(&ctrl->err_pending, bad);
     if (!finalize) return;
-    // block max of |v^{n+1}|, one atomic per block
+    // block maximum of |v^{n+1}|; k_substep_end reduces them (no cross-block
+    // signalling here: a device-wide fence per block would write back L2)
     double m = wave_max((double)speed);
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) smax[wid] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double b = smax[0];
-        for (int q = 1; q < BLOCK / 64; ++q) b = fmax(b, smax[q]);
-        atomicMax(&ctrl->vmax_bits, speed_bits((real)b));
-        __threadfence();
-        unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
-        s_last = prev == gridDim.x - 1;
+        double bm = smax[0];
+        for (int q = 1; q < BLOCK / 64; ++q) bm = fmax(bm, smax[q]);
+        bmax[blockIdx.x] = bm;
     }
+}
+
+// S5 after each density relaxation (one block): |v|max from the block maxima,
+// the sub-step clock, and the size of the next acoustic step, min(dt_ac,
+// remaining part of the advection step); ends the advection step when it is
+// covered.
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_substep_end(KP<real> P, Ctrl* __restrict__ ctrl,
+                                                       const double* __restrict__ bmax, int nb)
+{
+    if (!ctrl->active || ctrl->err) return;  // same test as the density relaxation
+    __shared__ double smax[BLOCK / 64];
+    double w = 0.0;
+    for (int q = threadIdx.x; q < nb; q += BLOCK) w = fmax(w, bmax[q]);
+    w = wave_max(w);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) smax[wid] = w;
     __syncthreads();
-    if (!s_last || threadIdx.x != 0) return;
-    __threadfence();
-    // last block: advance the sub-step clock and choose the next step size
-    uint32_t pend = atomicOr(&ctrl->err_pending, 0u);
+    if (threadIdx.x != 0) return;
+    double vmax = smax[0];
+    for (int q = 1; q < BLOCK / 64; ++q) vmax = fmax(vmax, smax[q]);
+    const double dtd = ctrl->dt;
+    uint32_t pend = ctrl->err_pending;
     if (pend) {
         ctrl->err_pending = 0u;
-        atomicOr(&ctrl->err, pend);
+        ctrl->err |= pend;
     }
-    unsigned long long vb = atomicAdd(&ctrl->vmax_bits, 0ull);
-    double vmax = bits_speed<real>(vb);
     ctrl->vmax = vmax;
-    ctrl->vmax_bits = 0ull;
-    ctrl->blocks_done = 0u;
     double tau = ctrl->tau + dtd;
     ctrl->tau = tau;
     ctrl->nsub += 1;
@@ -788,7 +905,6 @@ __global__ __launch_bounds__(BLOCK) void k_density(
         ctrl->steps_done += 1;
         ctrl->rebuild = 1;
     }
-    __threadfence();
 }
 
 // ---------------------------------------------------------------------
@@ -857,16 +973,33 @@ __global__ __launch_bounds__(BLOCK) void k_diag(KP<real> P, const double* __rest
     }
 }
 
-__global__ void k_diag_fin(const double* __restrict__ part, int nb, double* __restrict__ out)
+// One block, fixed reduction order (strided partials, then shuffle trees),
+// so the result does not depend on timing.
+__global__ __launch_bounds__(BLOCK) void k_diag_fin(const double* __restrict__ part, int nb, double* __restrict__ out)
 {
-    int q = threadIdx.x;
-    if (q >= NDIAG) return;
-    double r = (q == 6) ? -1e300 : 0.0;
-    for (int b = 0; b < nb; ++b) {
-        double v = part[(size_t)b * NDIAG + q];
-        r = (q == 6 || q == 7) ? fmax(r, v) : r + v;
+    __shared__ double sh[NDIAG][BLOCK / 64];
+    double v[NDIAG];
+#pragma unroll
+    for (int q = 0; q < NDIAG; ++q) v[q] = q == 6 ? -1e300 : 0.0;
+    for (int b = threadIdx.x; b < nb; b += BLOCK)
+#pragma unroll
+        for (int q = 0; q < NDIAG; ++q) {
+            double x = part[(size_t)b * NDIAG + q];
+            v[q] = (q == 6 || q == 7) ? fmax(v[q], x) : v[q] + x;
+        }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NDIAG; ++q) {
+        double r = (q == 6 || q == 7) ? wave_max(v[q]) : wave_sum(v[q]);
+        if (lane == 0) sh[q][wid] = r;
     }
-    out[q] = r;
+    __syncthreads();
+    if (threadIdx.x < NDIAG) {
+        int q = threadIdx.x;
+        double r = sh[q][0];
+        for (int w = 1; w < BLOCK / 64; ++w) r = (q == 6 || q == 7) ? fmax(r, sh[q][w]) : r + sh[q][w];
+        out[q] = r;
+    }
 }
 
 // ---------------------------------------------------------------------

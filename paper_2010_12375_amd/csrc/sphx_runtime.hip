@@ -72,7 +72,8 @@ struct Engine final : EngineBase {
     sphx_ctx* ctx;
     hipStream_t s;
     KP<real> P{};
-    int ncell = 0, nsub_q = 6, steps_per_graph = 2;
+    static constexpr int LN = D == 2 ? 4 : 8;  // lanes per particle in the pair kernels
+    int ncell = 0, nsub_q = 5, steps_per_graph = 2;
     int maxn = 0, maxw = 0;
     // fluid: two state sets (current and gather target)
     int nf = 0, cap = 0;
@@ -91,6 +92,7 @@ struct Engine final : EngineBase {
     int32_t *cnt = nullptr, *fstart = nullptr, *bsum = nullptr;
     real* acc_out = nullptr;
     real* drho_out = nullptr;
+    double* red_bmax = nullptr;     // per-block |v| maxima of the density relaxation
     double* outbuf = nullptr;
     double* stage = nullptr;
     size_t stage_n = 0;
@@ -241,7 +243,7 @@ struct Engine final : EngineBase {
         maxw = D == 2 ? 32 : 96;
         P.maxn = maxn;
         P.maxw = maxw;
-        nsub_q = q.nsub_queue > 0 ? q.nsub_queue : 6;
+        nsub_q = q.nsub_queue > 0 ? q.nsub_queue : 5;
         if (nsub_q > 64) nsub_q = 64;
         HIPCHK(hipMalloc((void**)&ctrl, sizeof(Ctrl)));
         HIPCHK(hipHostMalloc((void**)&hctrl, sizeof(Ctrl), hipHostMallocDefault));
@@ -253,6 +255,7 @@ struct Engine final : EngineBase {
         HIPCHK(hipMalloc((void**)&bsum, sizeof(int32_t) * ((size_t)nblk_scan() + 1)));
         HIPCHK(hipMalloc((void**)&diag_out, sizeof(double) * NDIAG));
         HIPCHK(hipMemsetAsync(wstart, 0, sizeof(int32_t) * ((size_t)ncell + 1), s));
+        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));
         HIPCHK(hipStreamSynchronize(s));
         P.nf = 0;
         P.nw = 0;
@@ -314,6 +317,7 @@ struct Engine final : EngineBase {
         RETCHK(dalloc(L, rank, n));
         RETCHK(dalloc(L, perm, n));
         RETCHK(dalloc(L, acc_out, (size_t)n * D));
+        RETCHK(dalloc(L, red_bmax, (size_t)nblk((long long)n * LN)));
         RETCHK(dalloc(L, drho_out, n));
         RETCHK(dalloc(L, outbuf, (size_t)n * D));
         RETCHK(dalloc(L, diag_part, (size_t)nblk(n) * NDIAG));
@@ -366,6 +370,7 @@ struct Engine final : EngineBase {
         }
         std::memset(hctrl, 0, sizeof(Ctrl));
         RETCHK(push_ctrl());
+        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));  // after a failed rebuild
         cur_steps = 0;
         if (n > 0) {
             k_vmax<D, real><<<nblk(n), BLOCK, 0, s>>>(P, ctrl, st[0]);
@@ -418,7 +423,7 @@ struct Engine final : EngineBase {
         HIPCHK(hipMemcpyAsync(stage, soa.data(), nn * 6 * sizeof(double), hipMemcpyHostToDevice, s));
         double* sx[3] = {stage, stage + nn, stage + 2 * nn};
         double* sn[3] = {stage + 3 * nn, stage + 4 * nn, stage + 5 * nn};
-        k_fill_i32<<<nblk(ncell), BLOCK, 0, s>>>(cnt, ncell, 0);
+        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));
         k_bin<D, real><<<nblk(n), BLOCK, 0, s>>>(P, ctrl, 0, (int)n, sx[0], sx[1], sx[2], wkey, wrank, cnt, 0);
         RETCHK(enqueue_scan(0, wstart));
         k_scatter<<<nblk(n), BLOCK, 0, s>>>(ctrl, 0, (int)n, wkey, wrank, wstart, wperm);
@@ -440,30 +445,32 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
-    // S1-S3 from state set a into set b.
+    // S1-S3 from state set a into set b. The cell counters are zero on entry
+    // (zeroed at allocation and by every scan that consumes them).
     int enqueue_rebuild(int gate, int a)
     {
         int b = 1 - a;
-        k_fill_i32<<<nblk(ncell), BLOCK, 0, s>>>(cnt, ncell, 0);
         k_bin<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, gate, nf, x[a][0], x[a][1], x[a][2], key, rank, cnt, 1);
         RETCHK(enqueue_scan(gate, fstart));
         k_scatter<<<nblk(nf), BLOCK, 0, s>>>(ctrl, gate, nf, key, rank, fstart, perm);
-        k_cell_order<<<nblk(ncell), BLOCK, 0, s>>>(ctrl, gate, ncell, fstart, perm);
-        k_gather_fluid<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, gate, nf, perm, key, x[a][0], x[a][1], x[a][2],
-                                                            st[a], dr3[a], id[a], x[b][0], x[b][1], x[b][2], st[b],
-                                                            dr3[b], id[b], cell[b], geo[b]);
-        k_neighbors<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, gate, x[b][0], x[b][1], x[b][2], cell[b], fstart,
-                                                         wx[0], wx[1], wx[2], wstart, nbr, ncnt, wnb, wcnt);
+        k_place_fluid<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, gate, nf, perm, key, fstart, x[a][0], x[a][1],
+                                                           x[a][2], st[a], dr3[a], id[a], x[b][0], x[b][1], x[b][2],
+                                                           st[b], dr3[b], id[b], cell[b], geo[b]);
+        k_neighbors<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, gate, x[b][0], x[b][1], x[b][2],
+                                                                             cell[b], fstart, wx[0], wx[1], wx[2],
+                                                                             wstart, nbr, ncnt, wnb, wcnt);
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
 
     int enqueue_substep(int a, int finalize, real* acc, real* dro)
     {
-        k_pressure<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a],
+        k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a],
                                                         dr3[a], hf, acc);
-        k_density<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                       hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro);
+        k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+                                                       hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro,
+                                                                         red_bmax);
+        if (finalize) k_substep_end<real><<<1, BLOCK, 0, s>>>(P, ctrl, red_bmax, nblk((long long)nf * LN));
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -472,7 +479,7 @@ struct Engine final : EngineBase {
     int enqueue_step(int a)
     {
         k_adv_begin<real><<<1, 1, 0, s>>>(P, ctrl);
-        k_reinit<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, 1, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
+        k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
         for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, 1, nullptr, nullptr));
         RETCHK(enqueue_rebuild(1, a));
         return SPHX_OK;
@@ -515,6 +522,7 @@ struct Engine final : EngineBase {
         RETCHK(sync_ctrl());
         hctrl->err = 0;
         RETCHK(push_ctrl());
+        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));  // a failed rebuild may leave counts
         RETCHK(enqueue_rebuild(0, cur));
         RETCHK(sync_ctrl());
         cur ^= 1;
@@ -566,7 +574,7 @@ struct Engine final : EngineBase {
     int density_reinit() override
     {
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
-        k_reinit<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, 0, geo[cur], wgeo, nbr, ncnt, wnb, wcnt, st[cur]);
+        k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 0, geo[cur], wgeo, nbr, ncnt, wnb, wcnt, st[cur]);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         return SPHX_OK;
@@ -726,7 +734,7 @@ struct Engine final : EngineBase {
         double r[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (nf > 0) {
             k_diag<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, x[cur][0], x[cur][1], x[cur][2], st[cur], diag_part);
-            k_diag_fin<<<1, 64, 0, s>>>(diag_part, nblk(nf), diag_out);
+            k_diag_fin<<<1, BLOCK, 0, s>>>(diag_part, nblk(nf), diag_out);
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(r, diag_out, sizeof(r), hipMemcpyDeviceToHost, s));
         }
@@ -768,7 +776,7 @@ struct Engine final : EngineBase {
         // pressure relaxation
         HIPCHK(hipEventRecord(ev[0], s));
         for (int r = 0; r < reps; ++r)
-            k_pressure<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+            k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
                                                             st[cur], dr3[cur], hf, nullptr);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
@@ -777,8 +785,9 @@ struct Engine final : EngineBase {
         // density relaxation (with its |v|max reduction and clock update)
         HIPCHK(hipEventRecord(ev[0], s));
         for (int r = 0; r < reps; ++r)
-            k_density<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, 1, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf,
-                                                           st[cur], dr3[cur], x[cur][0], x[cur][1], x[cur][2], nullptr);
+            k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf,
+                                                           st[cur], dr3[cur], x[cur][0], x[cur][1], x[cur][2], nullptr,
+                                                                         red_bmax);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
@@ -786,7 +795,7 @@ struct Engine final : EngineBase {
         // neighbour build (idempotent on the current set)
         HIPCHK(hipEventRecord(ev[0], s));
         for (int r = 0; r < reps; ++r)
-            k_neighbors<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, 0, x[cur][0], x[cur][1], x[cur][2], cell[cur],
+            k_neighbors<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 0, x[cur][0], x[cur][1], x[cur][2], cell[cur],
                                                              fstart, wx[0], wx[1], wx[2], wstart, nbr, ncnt, wnb, wcnt);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
@@ -795,7 +804,7 @@ struct Engine final : EngineBase {
         // density re-initialisation (gate off; restored below)
         HIPCHK(hipEventRecord(ev[0], s));
         for (int r = 0; r < reps; ++r)
-            k_reinit<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, 0, geo[cur], wgeo, nbr, ncnt, wnb, wcnt, st[cur]);
+            k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 0, geo[cur], wgeo, nbr, ncnt, wnb, wcnt, st[cur]);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
