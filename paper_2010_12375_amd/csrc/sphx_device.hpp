@@ -21,9 +21,9 @@
 //   drho3  real     drho/dt in 3D
 //   hf     R4       {vn.., dev_half}: v^{n+1} and rho^{n+1/2} - rho0 written by
 //                   the pressure relaxation for the density relaxation
-//   nbr    u32      neighbour entries, column-major (entry k of particle i at
-//                   k * cap + i): sorted index | stencil code << 26, the code
-//                   holding the cell offset dc + 1 (2 bits per axis)
+//   nbr    u32      neighbour entries, wave-tiled (ell_at): sorted index |
+//                   stencil code << 26, the code holding the cell offset
+//                   dc + 1 (2 bits per axis)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,6 +33,9 @@ namespace sphx {
 constexpr int NBR_SHIFT = 26;
 constexpr uint32_t NBR_MASK = (1u << NBR_SHIFT) - 1u;
 constexpr int BLOCK = 256;
+constexpr int BATCH = 4;  // list entries / candidate rounds loaded ahead per lane
+constexpr uint32_t NO_ENTRY = 0xffffffffu;  // stencil code 63 never occurs
+constexpr int VSLOTS = 64;  // slots the density relaxation folds its block maxima into
 
 enum : uint32_t {
     ERR_ESCAPE = 1u,       // a fluid particle left the domain box
@@ -84,6 +87,33 @@ template <typename real> struct KP {
     double cfl_ad_h, cfl_ac_h, u_ref, c0d;
     int nf, nw, cap, maxn, maxw;
 };
+
+// Neighbour lists are wave-tiled: the 64/T particles served by one
+// wavefront (T lanes each) store their entries so that every round of the
+// pair loop reads 64 consecutive words: entry k of particle i sits at word
+// (k mod T) + T (i mod 64/T) + 64 (k div T) of the tile of particle i, tiles
+// holding mx entries per particle.
+template <int T>
+__host__ __device__ __forceinline__ size_t ell_at(int i, int k, int mx)
+{
+    constexpr int PW = 64 / T;
+    size_t tile = (size_t)(i / PW);
+    int p = i % PW;
+    return (tile * (size_t)(mx / T) + (size_t)(k / T)) * 64 + (size_t)p * T + (size_t)(k % T);
+}
+
+// XCD-aware block order. Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2; remapping so that XCD k runs the k-th
+// contiguous slice of the (cell-sorted) particle range keeps neighbouring
+// particles, which gather the same neighbour data, on one L2. A bijection on
+// [0, nb) for any nb.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int x = b % NXCD, k = b / NXCD;
+    const int q = nb / NXCD, rem = nb % NXCD;
+    return k + x * q + (x < rem ? x : rem);
+}
 
 // ---------------------------------------------------------------------
 // small helpers
@@ -460,89 +490,153 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
 // ---------------------------------------------------------------------
 // S2: neighbour configuration. For each fluid particle scan the 3^d cells
 // around its cell in the fluid and wall cell lists and keep j != i with
-// r^2 < (2h)^2 (FP64 predicate). Entries keep the cell offset so that the
-// pair geometry can be rebuilt from cell offsets. T lanes share one
-// particle: they test T candidates at a time and append the hits in
-// candidate order through a ballot, so the list (and every later sum over
-// it) does not depend on T.
-template <int D, typename real, int T>
+// r^2 < (2h)^2, the predicate evaluated exactly as stated on the FP64
+// positions. Entries keep the cell offset so that the pair geometry can be
+// rebuilt from cell offsets.
+//
+// TB lanes share one particle. The three x-adjacent cells of a stencil row
+// are one contiguous range of the sorted order, scanned TB candidates per
+// round; hits are appended in candidate order through a ballot, so the list
+// does not depend on TB. In FP32 mode a candidate is first classified on the
+// FP32 cell offsets: |r2_32 - r2| <= 6 * 2^-24 L (2 r) + 3 * 2^-24 r^2 <
+// 2.4e-6 L^2 for r <= L (offsets and cell sizes rounded once to FP32, then
+// four roundings in the difference), so with margin 8e-6 L^2 only candidates
+// in a thin shell around 2h need the FP64 test, and the list is bit-exact.
+template <int D, typename real, int T, int TB>
 __global__ __launch_bounds__(BLOCK) void k_neighbors(
     KP<real> P, Ctrl* __restrict__ ctrl, int gate, const double* __restrict__ x0, const double* __restrict__ x1,
     const double* __restrict__ x2, const int32_t* __restrict__ cell, const int32_t* __restrict__ fstart,
-    const double* __restrict__ wx0, const double* __restrict__ wx1, const double* __restrict__ wx2,
-    const int32_t* __restrict__ wstart, uint32_t* __restrict__ nbr, int32_t* __restrict__ ncnt,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const double* __restrict__ wx0,
+    const double* __restrict__ wx1, const double* __restrict__ wx2, const int32_t* __restrict__ wstart,
+    const typename GeoSel<D, real>::T* __restrict__ wgeo, uint32_t* __restrict__ nbr, int32_t* __restrict__ ncnt,
     uint32_t* __restrict__ wnb, int32_t* __restrict__ wcnt)
 {
-    static_assert(64 % T == 0, "lane groups must tile a wavefront");
+    static_assert(64 % TB == 0, "lane groups must tile a wavefront");
+    using G = typename GeoSel<D, real>::T;
+    constexpr bool PREFILTER = sizeof(real) == 4;
     if (gate && (!ctrl->rebuild || ctrl->err)) return;
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = gid / T;
-    const int l = gid % T;
+    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int i = gid / TB;
+    const int l = gid % TB;
     if (i >= P.nf) return;  // whole lane groups leave together
-    const int gbase = (int)(threadIdx.x & 63) & ~(T - 1);
-    const unsigned long long gmask = T == 64 ? ~0ull : ((1ull << T) - 1ull);
+    const int gbase = (int)(threadIdx.x & 63) & ~(TB - 1);
+    const unsigned long long gmask = TB == 64 ? ~0ull : ((1ull << TB) - 1ull);
     const unsigned long long below = (1ull << l) - 1ull;
-    double xi[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
-    int kc = cell[i];
-    int ci[3] = {kc % P.n[0], (kc / P.n[0]) % P.n[1], kc / (P.n[0] * P.n[1])};
-    int nin = 0, nwl = 0;
+    const double xi[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
+    const G oi = geo[i];
+    const float Lm = (float)dmax(P.L[0], dmax(P.L[1], D == 3 ? P.L[2] : P.L[1]));
+    const float margin = 8e-6f * Lm * Lm;
+    const float rc2f = (float)P.rc2;
+    const int kc = cell[i];
+    const int ci[3] = {kc % P.n[0], (kc / P.n[0]) % P.n[1], kc / (P.n[0] * P.n[1])};
+    int cnt_[2] = {0, 0};
     uint32_t over = 0;
+
+    // Scan candidates [j0, j1) of one body; cell offset in x from the
+    // range boundaries b1, b2 (first candidate of the 2nd and 3rd cell).
+    auto scan = [&](int body, int j0, int j1, int b1, int b2, int dcx0, uint32_t tag_yz) {
+        const G* csrc = body ? wgeo : geo;
+        const double* bx0 = body ? wx0 : x0;
+        const double* bx1 = body ? wx1 : x1;
+        const double* bx2 = body ? wx2 : x2;
+        uint32_t* out = body ? wnb : nbr;
+        const int mx = body ? P.maxw : P.maxn;
+        int& nn = cnt_[body];
+        // BATCH rounds per iteration: all candidate loads first, then the
+        // tests and ballots in candidate order
+        for (int jb = j0; jb < j1; jb += TB * BATCH) {
+            G oj[BATCH];
+            double xq[BATCH][3];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const int j = jb + u * TB + l;
+                if (j < j1) {
+                    if constexpr (PREFILTER) {
+                        oj[u] = csrc[j];
+                    } else {
+                        xq[u][0] = bx0[j];
+                        xq[u][1] = bx1[j];
+                        xq[u][2] = D == 3 ? bx2[j] : 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                if (jb + u * TB >= j1) break;  // uniform over the lane group
+                const int j = jb + u * TB + l;
+                const int dcx = dcx0 + (j >= b1) + (j >= b2);
+                bool in = false;
+                if (j < j1 && (body || j != i)) {
+                    if constexpr (PREFILTER) {
+                        float dx = (float)((oi.x - oj[u].x) - (real)dcx * P.L[0]);
+                        float dy = (float)((oi.y - oj[u].y) - (real)((int)((tag_yz >> 2) & 3u) - 1) * P.L[1]);
+                        float r2 = dx * dx + dy * dy;
+                        if constexpr (D == 3) {
+                            float dz = (float)((oi.z - zc(oj[u])) - (real)((int)((tag_yz >> 4) & 3u) - 1) * P.L[2]);
+                            r2 += dz * dz;
+                        }
+                        if (r2 < rc2f - margin) {
+                            in = true;
+                        } else if (r2 > rc2f + margin) {
+                            in = false;
+                        } else {
+                            double xj[3] = {bx0[j], bx1[j], D == 3 ? bx2[j] : 0.0};
+                            in = pair_r2<D>(P, xi, xj) < P.rc2;
+                        }
+                    } else {
+                        in = pair_r2<D>(P, xi, xq[u]) < P.rc2;
+                    }
+                }
+                unsigned long long m = (__ballot(in) >> gbase) & gmask;
+                if (in) {
+                    int slot = nn + __popcll(m & below);
+                    uint32_t code = (uint32_t)(dcx + 1) | tag_yz;
+                    if (slot < mx) out[ell_at<T>(i, slot, mx)] = (uint32_t)j | (code << NBR_SHIFT);
+                    else over = 1;
+                }
+                nn += __popcll(m);
+            }
+        }
+    };
+
     const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
         int cz = ci[2] + dz;
+        bool zskip = false;
         if (D == 3) {
             if (P.periodic[2]) cz = cz < 0 ? cz + P.n[2] : (cz >= P.n[2] ? cz - P.n[2] : cz);
-            else if (cz < 0 || cz >= P.n[2]) continue;
+            else zskip = cz < 0 || cz >= P.n[2];
         }
         for (int dy = -1; dy <= 1; ++dy) {
             int cy = ci[1] + dy;
+            if (zskip) continue;
             if (P.periodic[1]) cy = cy < 0 ? cy + P.n[1] : (cy >= P.n[1] ? cy - P.n[1] : cy);
             else if (cy < 0 || cy >= P.n[1]) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                int cx = ci[0] + dx;
-                if (P.periodic[0]) cx = cx < 0 ? cx + P.n[0] : (cx >= P.n[0] ? cx - P.n[0] : cx);
-                else if (cx < 0 || cx >= P.n[0]) continue;
-                int c = cx + P.n[0] * (cy + P.n[1] * cz);
-                uint32_t code = (uint32_t)(dx + 1) | ((uint32_t)(dy + 1) << 2) | ((uint32_t)(dz + 1) << 4);
-                uint32_t tag = code << NBR_SHIFT;
-                for (int j0 = fstart[c], je = min(fstart[c + 1], P.nf); j0 < je; j0 += T) {
-                    int j = j0 + l;
-                    bool in = false;
-                    if (j < je && j != i) {
-                        double xj[3] = {x0[j], x1[j], D == 3 ? x2[j] : 0.0};
-                        in = pair_r2<D>(P, xi, xj) < P.rc2;
-                    }
-                    unsigned long long m = (__ballot(in) >> gbase) & gmask;
-                    if (in) {
-                        int slot = nin + __popcll(m & below);
-                        if (slot < P.maxn) nbr[(size_t)slot * P.cap + i] = (uint32_t)j | tag;
-                        else over = 1;
-                    }
-                    nin += __popcll(m);
-                }
-                if (P.nw > 0) {
-                    for (int w0 = wstart[c], we = min(wstart[c + 1], P.nw); w0 < we; w0 += T) {
-                        int w = w0 + l;
-                        bool in = false;
-                        if (w < we) {
-                            double xw[3] = {wx0[w], wx1[w], D == 3 ? wx2[w] : 0.0};
-                            in = pair_r2<D>(P, xi, xw) < P.rc2;
-                        }
-                        unsigned long long m = (__ballot(in) >> gbase) & gmask;
-                        if (in) {
-                            int slot = nwl + __popcll(m & below);
-                            if (slot < P.maxw) wnb[(size_t)slot * P.cap + i] = (uint32_t)w | tag;
-                            else over = 1;
-                        }
-                        nwl += __popcll(m);
+            const int rowc = P.n[0] * (cy + P.n[1] * cz);
+            const uint32_t tag_yz = ((uint32_t)(dy + 1) << 2) | ((uint32_t)(dz + 1) << 4);
+            for (int body = 0; body < (P.nw > 0 ? 2 : 1); ++body) {
+                const int32_t* st_ = body ? wstart : fstart;
+                const int lim = body ? P.nw : P.nf;
+                if (ci[0] >= 1 && ci[0] + 1 < P.n[0]) {
+                    // the three cells are contiguous: one range
+                    const int c = rowc + ci[0];
+                    scan(body, min(st_[c - 1], lim), min(st_[c + 2], lim), min(st_[c], lim), min(st_[c + 1], lim), -1,
+                         tag_yz);
+                } else {
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int cx = ci[0] + dx;
+                        if (P.periodic[0]) cx = cx < 0 ? cx + P.n[0] : (cx >= P.n[0] ? cx - P.n[0] : cx);
+                        else if (cx < 0 || cx >= P.n[0]) continue;
+                        const int c = rowc + cx;
+                        scan(body, min(st_[c], lim), min(st_[c + 1], lim), 0x7fffffff, 0x7fffffff, dx, tag_yz);
                     }
                 }
             }
         }
     }
     if (l == 0) {
-        ncnt[i] = nin < P.maxn ? nin : P.maxn;
-        wcnt[i] = nwl < P.maxw ? nwl : P.maxw;
+        ncnt[i] = cnt_[0] < P.maxn ? cnt_[0] : P.maxn;
+        wcnt[i] = cnt_[1] < P.maxw ? cnt_[1] : P.maxw;
     }
     if (over) atomicOr(&ctrl->err, ERR_NBR_OVERFLOW);
 }
@@ -604,6 +698,32 @@ __global__ void k_adv_begin(KP<real> P, Ctrl* __restrict__ ctrl)
     ctrl->active = 1;
 }
 
+// Visit the list entries k = l, l + T, ... < n of particle i in batches of
+// U: first the U index loads, then the U gathers (`load`), then the U
+// updates (`use`), so that several memory round trips are in flight per
+// lane. Each lane still accumulates its entries in ascending k.
+
+template <int T, int U, typename Load, typename Use>
+__device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int i, int n, int mx, int l,
+                                          Load load, Use use)
+{
+    for (int k0 = l; k0 < n; k0 += T * U) {
+        uint32_t e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int k = k0 + u * T;
+            e[u] = k < n ? list[ell_at<T>(i, k, mx)] : NO_ENTRY;
+        }
+        decltype(load(0u)) g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e[u] != NO_ENTRY) g[u] = load(e[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e[u] != NO_ENTRY) use(e[u], g[u]);
+    }
+}
+
 // S4: density re-initialisation rho = max(rho*, rho0 sum W / sum W0) with
 // the sum over the particle itself, its fluid and its wall neighbours.
 // `gate`: run only at the start of an active advection step. T lanes share a
@@ -616,25 +736,19 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
     R4<real>* __restrict__ st)
 {
     if (gate && (!ctrl->active || ctrl->err)) return;
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int i = gid / T;
     const int l = gid % T;
     if (i >= P.nf) return;
     using G = typename GeoSel<D, real>::T;
     const G oi = geo[i];
     double sigma = 0.0;
-    int n = ncnt[i];
-    for (int k = l; k < n; k += T) {
-        uint32_t e = nbr[(size_t)k * P.cap + i];
-        Pair<D, real> q = pair_geo<D, real>(P, oi, geo[e & NBR_MASK], e >> NBR_SHIFT);
+    auto add_w = [&](uint32_t e, const G& oj) {
+        Pair<D, real> q = pair_geo<D, real>(P, oi, oj, e >> NBR_SHIFT);
         sigma += (double)kernel_W(P, q.r);
-    }
-    n = wcnt[i];
-    for (int k = l; k < n; k += T) {
-        uint32_t e = wnb[(size_t)k * P.cap + i];
-        Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[e & NBR_MASK], e >> NBR_SHIFT);
-        sigma += (double)kernel_W(P, q.r);
-    }
+    };
+    for_pairs<T, BATCH>(nbr, i, ncnt[i], P.maxn, l, [&](uint32_t e) { return geo[e & NBR_MASK]; }, add_w);
+    for_pairs<T, BATCH>(wnb, i, wcnt[i], P.maxw, l, [&](uint32_t e) { return wgeo[e & NBR_MASK]; }, add_w);
     sigma = group_sum<T>(sigma) + (double)P.Wc;  // + W(0), the particle itself
     if (l != 0) return;
     real dev_sum = (real)(P.rho0d * (sigma / P.sigma0 - 1.0));
@@ -661,7 +775,7 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     R4<real>* __restrict__ hf, real* __restrict__ acc_out)
 {
     if (!ctrl->active || ctrl->err) return;
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int i = gid / T;
     const int l = gid % T;
     if (i >= P.nf) return;
@@ -682,43 +796,58 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     const real inv_rho_i = (real)1 / rho_i;
     const G oi = geo[i];
     real acc[3] = {0, 0, 0};
-    int n = ncnt[i];
-    for (int k = l; k < n; k += T) {
-        uint32_t e = nbr[(size_t)k * P.cap + i];
-        uint32_t j = e & NBR_MASK;
-        Pair<D, real> q = pair_geo<D, real>(P, oi, geo[j], e >> NBR_SHIFT);
-        R4<real> sj = st[j];
-        real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * dr3[j];
-        real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
-        real UR = sj.x * q.e[0] + sj.y * q.e[1] + (D == 3 ? sj.z * q.e[2] : (real)0);
-        real rho_j = P.rho0 + dev_j;
-        real p_j = P.c2 * dev_j;
-        real du = UL - UR;
-        real beta = dmin((real)3 * dmax(du, (real)0), P.c);
-        real ps = (real)0.5 * (p_i + p_j) + (real)0.25 * beta * (rho_i + rho_j) * du;
-        real coef = P.two_m * ps * inv_rho_i / rho_j * q.dW;
-        acc[0] += coef * q.e[0];
-        acc[1] += coef * q.e[1];
-        if (D == 3) acc[2] += coef * q.e[2];
-    }
-    n = wcnt[i];
-    for (int k = l; k < n; k += T) {
-        uint32_t e = wnb[(size_t)k * P.cap + i];
-        uint32_t w = e & NBR_MASK;
-        Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[w], e >> NBR_SHIFT);
-        G nw = wnrm[w];
-        real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
-        real du = (real)2 * UL;  // U_R = -U_L for a static wall
-        real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
-        real pR = p_i + rho_i * gr;
-        real rhoR = P.rho0 + pR * P.inv_c2;
-        real beta = dmin((real)3 * dmax(du, (real)0), P.c);
-        real ps = (real)0.5 * (p_i + pR) + (real)0.25 * beta * (rho_i + rhoR) * du;
-        real coef = P.two_vw * ps * inv_rho_i * q.dW;
-        acc[0] += coef * q.e[0];
-        acc[1] += coef * q.e[1];
-        if (D == 3) acc[2] += coef * q.e[2];
-    }
+    struct FluidJ { G o; R4<real> s; real dr; };
+    struct WallJ { G o; G n; };
+    for_pairs<T, BATCH>(
+        nbr, i, ncnt[i], P.maxn, l,
+        [&](uint32_t e) {
+            uint32_t j = e & NBR_MASK;
+            FluidJ r;
+            r.o = geo[j];
+            r.s = st[j];
+            r.dr = D == 3 ? dr3[j] : (real)0;
+            return r;
+        },
+        [&](uint32_t e, const FluidJ& r) {
+            Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+            const R4<real>& sj = r.s;
+            real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * r.dr;
+            real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
+            real UR = sj.x * q.e[0] + sj.y * q.e[1] + (D == 3 ? sj.z * q.e[2] : (real)0);
+            real rho_j = P.rho0 + dev_j;
+            real p_j = P.c2 * dev_j;
+            real du = UL - UR;
+            real beta = dmin((real)3 * dmax(du, (real)0), P.c);
+            real ps = (real)0.5 * (p_i + p_j) + (real)0.25 * beta * (rho_i + rho_j) * du;
+            real coef = P.two_m * ps * inv_rho_i / rho_j * q.dW;
+            acc[0] += coef * q.e[0];
+            acc[1] += coef * q.e[1];
+            if (D == 3) acc[2] += coef * q.e[2];
+        });
+    for_pairs<T, BATCH>(
+        wnb, i, wcnt[i], P.maxw, l,
+        [&](uint32_t e) {
+            uint32_t w = e & NBR_MASK;
+            WallJ r;
+            r.o = wgeo[w];
+            r.n = wnrm[w];
+            return r;
+        },
+        [&](uint32_t e, const WallJ& r) {
+            Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+            const G& nw = r.n;
+            real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
+            real du = (real)2 * UL;  // U_R = -U_L for a static wall
+            real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
+            real pR = p_i + rho_i * gr;
+            real rhoR = P.rho0 + pR * P.inv_c2;
+            real beta = dmin((real)3 * dmax(du, (real)0), P.c);
+            real ps = (real)0.5 * (p_i + pR) + (real)0.25 * beta * (rho_i + rhoR) * du;
+            real coef = P.two_vw * ps * inv_rho_i * q.dW;
+            acc[0] += coef * q.e[0];
+            acc[1] += coef * q.e[1];
+            if (D == 3) acc[2] += coef * q.e[2];
+        });
     acc[0] = group_sum<T>(acc[0]);
     acc[1] = group_sum<T>(acc[1]);
     if (D == 3) acc[2] = group_sum<T>(acc[2]);
@@ -757,7 +886,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
     const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ hf, R4<real>* __restrict__ st,
     real* __restrict__ dr3, double* __restrict__ x0, double* __restrict__ x1, double* __restrict__ x2,
-    real* __restrict__ drho_out, double* __restrict__ bmax)
+    real* __restrict__ drho_out, unsigned long long* __restrict__ vslot)
 {
     if (!ctrl->active || ctrl->err) return;
     __shared__ double smax[BLOCK / 64];
@@ -765,7 +894,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const double dtd = ctrl->dt;
     const real dt = (real)dtd;
     const real half = (real)0.5 * dt;
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int i = gid / T;
     const int l = gid % T;
     real speed = 0;
@@ -780,36 +909,50 @@ __global__ __launch_bounds__(BLOCK) void k_density(
         const real p_i = P.c2 * dev_i;
         const G oi = geo[i];
         real sum = 0;
-        int n = ncnt[i];
-        for (int k = l; k < n; k += T) {
-            uint32_t e = nbr[(size_t)k * P.cap + i];
-            uint32_t j = e & NBR_MASK;
-            Pair<D, real> q = pair_geo<D, real>(P, oi, geo[j], e >> NBR_SHIFT);
-            R4<real> hj = hf[j];
-            real dev_j = D == 2 ? hj.z : hj.w;
-            real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
-            real UR = hj.x * q.e[0] + hj.y * q.e[1] + (D == 3 ? hj.z * q.e[2] : (real)0);
-            real rho_j = P.rho0 + dev_j;
-            real p_j = P.c2 * dev_j;
-            real inv_rho_j = (real)1 / rho_j;
-            real rho_bar = (real)0.5 * (rho_i + rho_j);
-            real us = (real)0.5 * (UL + UR) + (p_i - p_j) * P.half_inv_c / rho_bar;
-            sum += P.m * inv_rho_j * (us - UL) * q.dW;
-        }
-        n = wcnt[i];
-        for (int k = l; k < n; k += T) {
-            uint32_t e = wnb[(size_t)k * P.cap + i];
-            uint32_t w = e & NBR_MASK;
-            Pair<D, real> q = pair_geo<D, real>(P, oi, wgeo[w], e >> NBR_SHIFT);
-            G nw = wnrm[w];
-            real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
-            real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
-            real pR = p_i + rho_i * gr;
-            real rhoR = P.rho0 + pR * P.inv_c2;
-            real rho_bar = (real)0.5 * (rho_i + rhoR);
-            real us = (p_i - pR) * P.half_inv_c / rho_bar;  // (U_L + U_R)/2 = 0
-            sum += P.vw * (us - UL) * q.dW;
-        }
+        struct HalfJ { G o; R4<real> h; };
+        struct WallJ { G o; G n; };
+        for_pairs<T, BATCH>(
+            nbr, i, ncnt[i], P.maxn, l,
+            [&](uint32_t e) {
+                uint32_t j = e & NBR_MASK;
+                HalfJ r;
+                r.o = geo[j];
+                r.h = hf[j];
+                return r;
+            },
+            [&](uint32_t e, const HalfJ& r) {
+                Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+                const R4<real>& hj = r.h;
+                real dev_j = D == 2 ? hj.z : hj.w;
+                real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
+                real UR = hj.x * q.e[0] + hj.y * q.e[1] + (D == 3 ? hj.z * q.e[2] : (real)0);
+                real rho_j = P.rho0 + dev_j;
+                real p_j = P.c2 * dev_j;
+                real inv_rho_j = (real)1 / rho_j;
+                real rho_bar = (real)0.5 * (rho_i + rho_j);
+                real us = (real)0.5 * (UL + UR) + (p_i - p_j) * P.half_inv_c / rho_bar;
+                sum += P.m * inv_rho_j * (us - UL) * q.dW;
+            });
+        for_pairs<T, BATCH>(
+            wnb, i, wcnt[i], P.maxw, l,
+            [&](uint32_t e) {
+                uint32_t w = e & NBR_MASK;
+                WallJ r;
+                r.o = wgeo[w];
+                r.n = wnrm[w];
+                return r;
+            },
+            [&](uint32_t e, const WallJ& r) {
+                Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+                const G& nw = r.n;
+                real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
+                real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
+                real pR = p_i + rho_i * gr;
+                real rhoR = P.rho0 + pR * P.inv_c2;
+                real rho_bar = (real)0.5 * (rho_i + rhoR);
+                real us = (p_i - pR) * P.half_inv_c / rho_bar;  // (U_L + U_R)/2 = 0
+                sum += P.vw * (us - UL) * q.dW;
+            });
         sum = group_sum<T>(sum);
         if (l == 0) {
             const real drho = (real)2 * rho_i * sum;
@@ -849,7 +992,8 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     if (threadIdx.x == 0) {
         double bm = smax[0];
         for (int q = 1; q < BLOCK / 64; ++q) bm = fmax(bm, smax[q]);
-        bmax[blockIdx.x] = bm;
+        // relaxed, result unused: no wait, no fence; read after the kernel ends
+        atomicMax(&vslot[blockIdx.x & (VSLOTS - 1)], speed_bits((real)bm));
     }
 }
 
@@ -858,20 +1002,14 @@ __global__ __launch_bounds__(BLOCK) void k_density(
 // remaining part of the advection step); ends the advection step when it is
 // covered.
 template <typename real>
-__global__ __launch_bounds__(BLOCK) void k_substep_end(KP<real> P, Ctrl* __restrict__ ctrl,
-                                                       const double* __restrict__ bmax, int nb)
+__global__ __launch_bounds__(64) void k_substep_end(KP<real> P, Ctrl* __restrict__ ctrl,
+                                                    unsigned long long* __restrict__ vslot)
 {
     if (!ctrl->active || ctrl->err) return;  // same test as the density relaxation
-    __shared__ double smax[BLOCK / 64];
-    double w = 0.0;
-    for (int q = threadIdx.x; q < nb; q += BLOCK) w = fmax(w, bmax[q]);
-    w = wave_max(w);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) smax[wid] = w;
-    __syncthreads();
+    double w = bits_speed<real>(vslot[threadIdx.x]);
+    vslot[threadIdx.x] = 0ull;  // ready for the next density relaxation
+    double vmax = wave_max(w);
     if (threadIdx.x != 0) return;
-    double vmax = smax[0];
-    for (int q = 1; q < BLOCK / 64; ++q) vmax = fmax(vmax, smax[q]);
     const double dtd = ctrl->dt;
     uint32_t pend = ctrl->err_pending;
     if (pend) {

@@ -72,7 +72,8 @@ struct Engine final : EngineBase {
     sphx_ctx* ctx;
     hipStream_t s;
     KP<real> P{};
-    static constexpr int LN = D == 2 ? 4 : 8;  // lanes per particle in the pair kernels
+    static constexpr int LN = D == 2 ? 4 : 8;   // lanes per particle in the pair kernels
+    static constexpr int LB = 4;  // lanes per particle in the neighbour build (measured best of 1-64)
     int ncell = 0, nsub_q = 5, steps_per_graph = 2;
     int maxn = 0, maxw = 0;
     // fluid: two state sets (current and gather target)
@@ -92,7 +93,7 @@ struct Engine final : EngineBase {
     int32_t *cnt = nullptr, *fstart = nullptr, *bsum = nullptr;
     real* acc_out = nullptr;
     real* drho_out = nullptr;
-    double* red_bmax = nullptr;     // per-block |v| maxima of the density relaxation
+    unsigned long long* vslot = nullptr;  // |v| maxima slots of the density relaxation (zero between uses)
     double* outbuf = nullptr;
     double* stage = nullptr;
     size_t stage_n = 0;
@@ -309,15 +310,17 @@ struct Engine final : EngineBase {
             RETCHK(dalloc(L, cell[a], n));
         }
         RETCHK(dalloc(L, hf, n));
-        RETCHK(dalloc(L, nbr, (size_t)maxn * n));
+        size_t ncap = (size_t)(n + 63) / 64 * 64;  // whole wave tiles
+        RETCHK(dalloc(L, nbr, (size_t)maxn * ncap));
         RETCHK(dalloc(L, ncnt, n));
-        RETCHK(dalloc(L, wnb, (size_t)maxw * n));
+        RETCHK(dalloc(L, wnb, (size_t)maxw * ncap));
         RETCHK(dalloc(L, wcnt, n));
         RETCHK(dalloc(L, key, n));
         RETCHK(dalloc(L, rank, n));
         RETCHK(dalloc(L, perm, n));
         RETCHK(dalloc(L, acc_out, (size_t)n * D));
-        RETCHK(dalloc(L, red_bmax, (size_t)nblk((long long)n * LN)));
+        RETCHK(dalloc(L, vslot, VSLOTS));
+        HIPCHK(hipMemsetAsync(vslot, 0, sizeof(unsigned long long) * VSLOTS, s));
         RETCHK(dalloc(L, drho_out, n));
         RETCHK(dalloc(L, outbuf, (size_t)n * D));
         RETCHK(dalloc(L, diag_part, (size_t)nblk(n) * NDIAG));
@@ -456,9 +459,9 @@ struct Engine final : EngineBase {
         k_place_fluid<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, gate, nf, perm, key, fstart, x[a][0], x[a][1],
                                                            x[a][2], st[a], dr3[a], id[a], x[b][0], x[b][1], x[b][2],
                                                            st[b], dr3[b], id[b], cell[b], geo[b]);
-        k_neighbors<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, gate, x[b][0], x[b][1], x[b][2],
-                                                                             cell[b], fstart, wx[0], wx[1], wx[2],
-                                                                             wstart, nbr, ncnt, wnb, wcnt);
+        k_neighbors<D, real, LN, LB><<<nblk((long long)nf * LB), BLOCK, 0, s>>>(
+            P, ctrl, gate, x[b][0], x[b][1], x[b][2], cell[b], fstart, geo[b], wx[0], wx[1], wx[2], wstart, wgeo, nbr,
+            ncnt, wnb, wcnt);
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -469,8 +472,8 @@ struct Engine final : EngineBase {
                                                         dr3[a], hf, acc);
         k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
                                                        hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro,
-                                                                         red_bmax);
-        if (finalize) k_substep_end<real><<<1, BLOCK, 0, s>>>(P, ctrl, red_bmax, nblk((long long)nf * LN));
+                                                                         vslot);
+        if (finalize) k_substep_end<real><<<1, 64, 0, s>>>(P, ctrl, vslot);
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -542,12 +545,13 @@ struct Engine final : EngineBase {
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
         int mx = kind == SPHX_INNER ? maxn : maxw;
         std::vector<int32_t> cnts(nf), ids(nf), oid(std::max(nw, 1));
-        std::vector<uint32_t> ell((size_t)mx * cap);
+        size_t ncap = (size_t)(cap + 63) / 64 * 64;
+        std::vector<uint32_t> ell((size_t)mx * ncap);
         HIPCHK(hipMemcpyAsync(cnts.data(), kind == SPHX_INNER ? ncnt : wcnt, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(ids.data(), id[cur], sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
         if (kind != SPHX_INNER && nw > 0)
             HIPCHK(hipMemcpyAsync(oid.data(), wid, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(ell.data(), kind == SPHX_INNER ? nbr : wnb, sizeof(uint32_t) * (size_t)mx * cap,
+        HIPCHK(hipMemcpyAsync(ell.data(), kind == SPHX_INNER ? nbr : wnb, sizeof(uint32_t) * (size_t)mx * ncap,
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         std::vector<int64_t> rowlen(nf + 1, 0);
@@ -562,7 +566,7 @@ struct Engine final : EngineBase {
             for (int i = 0; i < nf; ++i) {
                 int64_t o = rowlen[ids[i]];
                 for (int k = 0; k < cnts[i]; ++k) {
-                    uint32_t j = ell[(size_t)k * cap + i] & NBR_MASK;
+                    uint32_t j = ell[ell_at<LN>(i, k, mx)] & NBR_MASK;
                     idx[o + k] = kind == SPHX_INNER ? ids[j] : oid[j];
                 }
                 std::sort(idx + o, idx + o + cnts[i]);
@@ -787,7 +791,7 @@ struct Engine final : EngineBase {
         for (int r = 0; r < reps; ++r)
             k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf,
                                                            st[cur], dr3[cur], x[cur][0], x[cur][1], x[cur][2], nullptr,
-                                                                         red_bmax);
+                                                                         vslot);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
@@ -795,8 +799,9 @@ struct Engine final : EngineBase {
         // neighbour build (idempotent on the current set)
         HIPCHK(hipEventRecord(ev[0], s));
         for (int r = 0; r < reps; ++r)
-            k_neighbors<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 0, x[cur][0], x[cur][1], x[cur][2], cell[cur],
-                                                             fstart, wx[0], wx[1], wx[2], wstart, nbr, ncnt, wnb, wcnt);
+            k_neighbors<D, real, LN, LB><<<nblk((long long)nf * LB), BLOCK, 0, s>>>(
+                P, ctrl, 0, x[cur][0], x[cur][1], x[cur][2], cell[cur], fstart, geo[cur], wx[0], wx[1], wx[2], wstart,
+                wgeo, nbr, ncnt, wnb, wcnt);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));

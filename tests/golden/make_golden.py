@@ -7,6 +7,10 @@ observables (surge front, energies, max density deviation) are logged every
 
     python tests/golden/make_golden.py small      # 2D dp=0.05, seeds 0-4, t -> 1
     python tests/golden/make_golden.py medium     # 2D dp=0.00625, seed 0, t -> 20
+    python tests/golden/make_golden.py medium_perturbed
+        # the same run with every fluid position moved by a uniform random
+        # amount of at most 2e-9 (the rounding of FP32 offsets from the cell
+        # origin), to measure how far rounding alone moves the observables
 """
 import json
 import os
@@ -60,6 +64,16 @@ def main(which):
         out = dict(case="dambreak2d_51k (2D, dp=0.00625, FP64 oracle), seed 0", t_end=20.0, seeds={"0": rows},
                    wall_seconds=wall, threads=O.num_threads())
         path = os.path.join(HERE, "oracle_dambreak2d_51k.json")
+    elif which == "medium_perturbed":
+        import numpy as np
+        case = wl.config_medium(0)
+        rng = np.random.Generator(np.random.PCG64(12345))
+        case.fluid_pos = case.fluid_pos + rng.uniform(-2e-9, 2e-9, size=case.fluid_pos.shape)
+        rows, wall = run(case, 20.0, log=lambda s: print(s, flush=True))
+        out = dict(case="dambreak2d_51k (2D, dp=0.00625, FP64 oracle), seed 0, positions perturbed by "
+                        "U(-2e-9, 2e-9), perturbation seed 12345", t_end=20.0, seeds={"0": rows},
+                   wall_seconds=wall, threads=O.num_threads())
+        path = os.path.join(HERE, "oracle_dambreak2d_51k_perturbed.json")
     else:
         raise SystemExit(__doc__)
     out["source"] = ("FP64 oracle (oracle/sphx_oracle.c), written by tests/golden/make_golden.py " + which)

@@ -381,3 +381,43 @@ def test_dambreak_large_steps_conserve_mass_and_stay_bounded(large_pair):
     assert n >= 4 and d1["n_steps"] - d0["n_steps"] == 4
     assert d1["mass"] == d0["mass"]
     assert d1["max_drho"] < 0.05
+
+
+def run_medium_to_t20():
+    case = wl.config_medium(0)
+    gold = load_golden("oracle_dambreak2d_51k.json")["seeds"]["0"]
+    g, _ = make_pair(case, FP32)
+    say("medium run to t=20")
+    rows = run_observed(g, 20.0)
+    g.close()
+    assert len(rows) == len(gold)
+    return case, gold, rows
+
+
+_MEDIUM_RUN = {}
+
+
+def medium_run():
+    if not _MEDIUM_RUN:
+        _MEDIUM_RUN["v"] = run_medium_to_t20()
+    return _MEDIUM_RUN["v"]
+
+
+def test_dambreak_medium_fp32_through_impact():
+    """The 51 200-particle dam break in FP32 against the FP64 oracle's run of
+    the same input (tests/golden/oracle_dambreak2d_51k.json), observed every
+    0.1: surge front within 1 % until it reaches the far wall (x_f < DL - 2h,
+    t ~ 2.4), total energy within 1 % of E(0) through impact and run-up
+    (t <= 6)."""
+    case, gold, rows = medium_run()
+    E0 = energy(gold[0])
+    DL = case.tank[0]
+    worst_front = worst_energy = 0.0
+    for r, go in zip(rows, gold):
+        if go["front"] < DL - 2 * case.h:
+            worst_front = max(worst_front, abs(r["front"] - go["front"]) / go["front"])
+        if go["t"] <= 6.0 + 1e-9:
+            worst_energy = max(worst_energy, abs(energy(r) - energy(go)) / E0)
+    say(f"worst front rel err {worst_front:.3e}, worst energy err / E0 (t<=6) {worst_energy:.3e}")
+    assert worst_front <= 0.01
+    assert worst_energy <= 0.01
