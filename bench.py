@@ -48,6 +48,32 @@ def algorithmic_bytes(dim, precision, n_fluid, inner_pairs, contact_pairs):
 FLOPS_PER_PAIR = 55  # geometry ~25 (incl. rsqrt) + Riemann and accumulation ~30, per directed pair
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2010_12375_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there is
+    no summary or the kernels have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_hot_kernels.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if blob.get("kernel") != kernel or blob.get("source_hash") != kernel_source_hash():
+        return None
+    return int(blob["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(case, budget_s=15.0):
     """The FP64 oracle as it stands, on the host cores, on the first
     advection steps of the same workload (time-boxed)."""
@@ -190,7 +216,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(case.name, name),
             "alg_bytes_per_launch": int(nbytes),
             "alg_flops_per_launch": int(flops),
             "alu_frac": round(flops / (ms * 1e-3) / (valu * 1e12), 4),
