@@ -44,26 +44,34 @@ enum : uint32_t {
     ERR_STALL = 8u,        // an advection step needed more sub-steps than queued
 };
 
+// State of one acoustic sub-step; sub-step q of an advection step lives in
+// Ctrl::ss[q & 1]. The pressure relaxation of sub-step q derives it from
+// sub-step q - 1 (every block computes the same values, block 0 stores
+// them), so no kernel reads a slot that the same launch writes.
+struct SubState {
+    double tau;      // time covered inside the advection step before this sub-step
+    double dt;       // size of this sub-step
+    int32_t last;    // this sub-step ends the advection step
+    int32_t active;  // this sub-step is to be done
+    int32_t nsub;    // sub-steps done in the advection step before this one
+    int32_t pad;
+};
+
 // Device-side control block of the time loop.
 struct Ctrl {
     double t;          // clock (time of the current state)
     double t_end;      // end of the current advection step
     double t_stop;     // caller's stop time
     double dt_ad;      // current advection step size
-    double tau;        // time covered inside the advection step
-    double dt;         // size of the next acoustic sub-step
     double vmax;       // |v|max of the current state
-    unsigned long long vmax_bits; // max |v| accumulated by the density relaxation
-    int32_t active;    // sub-steps remain in this advection step
-    int32_t last;      // the next sub-step is the last of the step
-    int32_t nsub;      // sub-steps done in this advection step
+    unsigned long long vmax_bits;  // scratch of k_vmax
+    SubState ss[2];
     int32_t rebuild;   // the step is complete: rebuild the configuration
+    int32_t pad0;
     long long nsub_total;
     long long steps_done;
-    uint32_t blocks_done;
     uint32_t err;         // sticky error bits; no kernel that tests them also sets them
-    uint32_t err_pending; // bits raised by the density relaxation, folded into err by its last block
-    uint32_t pad;
+    uint32_t err_pending; // bits raised by the density relaxation, folded into err later
 };
 
 template <typename real> struct alignas(4 * sizeof(real)) R4 { real x, y, z, w; };
@@ -658,51 +666,111 @@ __device__ __forceinline__ double group_sum(double v)
 }
 
 // ---------------------------------------------------------------------
-// S5 at the start of an advection step (one thread): dt_ad from |v|max
-// floored at U_ref, clipped to the stop time, and the first acoustic step.
-// A step still active here ran out of queued sub-steps: flag a stall so the
-// host finishes it. A step that does not start clears the rebuild flag.
+// S5: the dual-criteria clock (Eqs. dt-advection, dt-relax).
+
+// Sub-step 0 of a new advection step (one thread): dt_ad from |v|max floored
+// at U_ref, clipped to the stop time, and the first acoustic step
+// min(dt_ac, dt_ad). Inactive when the clock has reached the stop time or an
+// error is pending.
+template <typename real>
+__device__ void prepare_step(const KP<real>& P, Ctrl* __restrict__ ctrl)
+{
+    SubState s0 = {0.0, 0.0, 0, 0, 0, 0};
+    const double t = ctrl->t, t_stop = ctrl->t_stop, vmax = ctrl->vmax;
+    if (ctrl->err == 0 && t < t_stop) {
+        double dt_ad = P.cfl_ad_h / fmax(vmax, P.u_ref);
+        double t_end = t + dt_ad;
+        if (t_end >= t_stop) {
+            dt_ad = t_stop - t;
+            t_end = t_stop;
+        }
+        double dt_ac = P.cfl_ac_h / (P.c0d + vmax);
+        s0.dt = dt_ac;
+        if (s0.dt >= dt_ad) {
+            s0.dt = dt_ad;
+            s0.last = 1;
+        }
+        s0.active = 1;
+        ctrl->dt_ad = dt_ad;
+        ctrl->t_end = t_end;
+    }
+    ctrl->ss[0] = s0;
+    ctrl->ss[1].active = 0;
+}
+
+// The sub-step after S given |v|max of the state S produced: the clock
+// advances by S.dt; the next step is min(dt_ac, remaining), the last one
+// clipped to land on dt_ad; `finished` when the advection step is covered.
+template <typename real>
+__device__ __forceinline__ SubState next_substep(const KP<real>& P, double dt_ad, const SubState& S, double vmax,
+                                                 bool& finished)
+{
+    SubState n;
+    n.tau = S.tau + S.dt;
+    n.nsub = S.nsub + 1;
+    n.pad = 0;
+    n.dt = S.dt;
+    n.last = S.last;
+    int done = S.last;
+    if (!done) {
+        double rem = dt_ad - n.tau;
+        if (!(rem > 0.0)) {
+            done = 1;
+        } else {
+            double dt_ac = P.cfl_ac_h / (P.c0d + vmax);
+            if (dt_ac >= rem) {
+                n.dt = rem;
+                n.last = 1;
+            } else {
+                n.dt = dt_ac;
+                n.last = 0;
+            }
+        }
+    }
+    n.active = !done;
+    finished = done;
+    return n;
+}
+
+// Bookkeeping of one completed sub-step (one thread).
+__device__ __forceinline__ void close_substep(Ctrl* __restrict__ ctrl, int slot, const SubState& n, double vmax,
+                                              bool finished)
+{
+    ctrl->ss[slot] = n;
+    ctrl->vmax = vmax;
+    ctrl->nsub_total += 1;
+    uint32_t pend = ctrl->err_pending;
+    if (pend) {
+        ctrl->err_pending = 0u;
+        ctrl->err |= pend;
+    }
+    if (finished) {
+        ctrl->t = ctrl->t_end;
+        ctrl->steps_done += 1;
+        ctrl->rebuild = 1;
+    }
+}
+
+// |v|max of the state a density relaxation produced, from its 64 slots
+// (one wavefront; every lane gets the result).
+template <typename real>
+__device__ __forceinline__ double slot_max(const unsigned long long* __restrict__ vs)
+{
+    return wave_max(bits_speed<real>(vs[threadIdx.x & 63]));
+}
+
+// Start of the advection steps queued by one call (one thread).
 template <typename real>
 __global__ void k_adv_begin(KP<real> P, Ctrl* __restrict__ ctrl)
 {
-    const uint32_t err = ctrl->err;
-    const int pending = ctrl->active;
     ctrl->rebuild = 0;
-    if (pending) {
-        if (err == 0) ctrl->err = ERR_STALL;
-        return;
-    }
-    const double t = ctrl->t, t_stop = ctrl->t_stop, vmax = ctrl->vmax;
-    if (err != 0 || !(t < t_stop)) return;
-    double dt_ad = P.cfl_ad_h / fmax(vmax, P.u_ref);
-    double t_end = t + dt_ad;
-    if (t_end >= t_stop) {
-        dt_ad = t_stop - t;
-        t_end = t_stop;
-    }
-    double dt_ac = P.cfl_ac_h / (P.c0d + vmax);
-    int last = 0;
-    double dt = dt_ac;
-    if (dt >= dt_ad) {
-        dt = dt_ad;
-        last = 1;
-    }
-    ctrl->dt_ad = dt_ad;
-    ctrl->t_end = t_end;
-    ctrl->tau = 0.0;
-    ctrl->dt = dt;
-    ctrl->last = last;
-    ctrl->nsub = 0;
-    ctrl->blocks_done = 0;
-    ctrl->vmax_bits = 0ull;
-    ctrl->active = 1;
+    prepare_step(P, ctrl);
 }
 
 // Visit the list entries k = l, l + T, ... < n of particle i in batches of
 // U: first the U index loads, then the U gathers (`load`), then the U
 // updates (`use`), so that several memory round trips are in flight per
 // lane. Each lane still accumulates its entries in ascending k.
-
 template <int T, int U, typename Load, typename Use>
 __device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int i, int n, int mx, int l,
                                           Load load, Use use)
@@ -735,7 +803,7 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     R4<real>* __restrict__ st)
 {
-    if (gate && (!ctrl->active || ctrl->err)) return;
+    if (gate && (!ctrl->ss[0].active || ctrl->err)) return;
     const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int i = gid / T;
     const int l = gid % T;
@@ -772,15 +840,41 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     const typename GeoSel<D, real>::T* __restrict__ wgeo, const typename GeoSel<D, real>::T* __restrict__ wnrm,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
     const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, const real* __restrict__ dr3,
-    R4<real>* __restrict__ hf, real* __restrict__ acc_out)
+    R4<real>* __restrict__ hf, real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot)
 {
-    if (!ctrl->active || ctrl->err) return;
+    // Sub-step q: with `adv`, first close sub-step q - 1 (every block derives
+    // the same state from slot (q - 1) & 1 and the maxima of the last density
+    // relaxation; block 0 stores it in slot q & 1). Block 0 also clears the
+    // |v| slots the density relaxation of this sub-step will fill.
+    // While an error or a stall is pending nothing is written: the host
+    // finishes a stalled step from the preserved slots.
+    const uint32_t err = ctrl->err;
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0 && !err;
+    SubState S;
+    if (adv) {
+        const SubState Sp = ctrl->ss[(q - 1) & 1];
+        if (Sp.active && !err) {
+            const double vmax = slot_max<real>(vslot + ((q - 1) & 1) * VSLOTS);
+            bool finished;
+            S = next_substep(P, ctrl->dt_ad, Sp, vmax, finished);
+            if (leader) close_substep(ctrl, q & 1, S, vmax, finished);
+        } else {
+            S = Sp;
+            S.active = 0;
+            if (leader) ctrl->ss[q & 1] = S;
+        }
+    } else {
+        S = ctrl->ss[q & 1];
+        if (leader) ctrl->rebuild = 0;  // a new advection step
+    }
+    if (blockIdx.x == 0 && threadIdx.x < VSLOTS) vslot[(q & 1) * VSLOTS + threadIdx.x] = 0ull;
+    if (!S.active || err) return;
     const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int i = gid / T;
     const int l = gid % T;
     if (i >= P.nf) return;
     using G = typename GeoSel<D, real>::T;
-    const real dt = (real)ctrl->dt;
+    const real dt = (real)S.dt;
     const real half = (real)0.5 * dt;
     const R4<real> si = st[i];
     real vi[3], dev_i;
@@ -886,12 +980,13 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
     const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ hf, R4<real>* __restrict__ st,
     real* __restrict__ dr3, double* __restrict__ x0, double* __restrict__ x1, double* __restrict__ x2,
-    real* __restrict__ drho_out, unsigned long long* __restrict__ vslot)
+    real* __restrict__ drho_out, unsigned long long* __restrict__ vslot, int q)
 {
-    if (!ctrl->active || ctrl->err) return;
+    const SubState S = ctrl->ss[q & 1];
+    if (!S.active || ctrl->err) return;
     __shared__ double smax[BLOCK / 64];
     using G = typename GeoSel<D, real>::T;
-    const double dtd = ctrl->dt;
+    const double dtd = S.dt;
     const real dt = (real)dtd;
     const real half = (real)0.5 * dt;
     const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -983,8 +1078,9 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     }
     if (bad) atomicOr(&ctrl->err_pending, bad);
     if (!finalize) return;
-    // block maximum of |v^{n+1}|; k_substep_end reduces them (no cross-block
-    // signalling here: a device-wide fence per block would write back L2)
+    // block maximum of |v^{n+1}| into the slots of this sub-step, read by the
+    // next pressure relaxation or the step end (no cross-block signalling
+    // here: a device-wide fence per block would write back L2)
     double m = wave_max((double)speed);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) smax[wid] = m;
@@ -993,56 +1089,36 @@ __global__ __launch_bounds__(BLOCK) void k_density(
         double bm = smax[0];
         for (int q = 1; q < BLOCK / 64; ++q) bm = fmax(bm, smax[q]);
         // relaxed, result unused: no wait, no fence; read after the kernel ends
-        atomicMax(&vslot[blockIdx.x & (VSLOTS - 1)], speed_bits((real)bm));
+        atomicMax(&vslot[(q & 1) * VSLOTS + (blockIdx.x & (VSLOTS - 1))], speed_bits((real)bm));
     }
 }
 
-// S5 after each density relaxation (one block): |v|max from the block maxima,
-// the sub-step clock, and the size of the next acoustic step, min(dt_ac,
-// remaining part of the advection step); ends the advection step when it is
-// covered.
+// S5 after the last queued density relaxation (one wavefront): close
+// sub-step q; if the advection step is not covered, flag a stall (`stall`)
+// for the host to finish it; clear both |v| slot sets; with `prepare`,
+// prepare sub-step 0 of the next advection step.
 template <typename real>
-__global__ __launch_bounds__(64) void k_substep_end(KP<real> P, Ctrl* __restrict__ ctrl,
-                                                    unsigned long long* __restrict__ vslot)
+__global__ __launch_bounds__(64) void k_step_end(KP<real> P, Ctrl* __restrict__ ctrl,
+                                                 unsigned long long* __restrict__ vslot, int q, int prepare,
+                                                 int stall)
 {
-    if (!ctrl->active || ctrl->err) return;  // same test as the density relaxation
-    double w = bits_speed<real>(vslot[threadIdx.x]);
-    vslot[threadIdx.x] = 0ull;  // ready for the next density relaxation
-    double vmax = wave_max(w);
-    if (threadIdx.x != 0) return;
-    const double dtd = ctrl->dt;
-    uint32_t pend = ctrl->err_pending;
-    if (pend) {
-        ctrl->err_pending = 0u;
-        ctrl->err |= pend;
-    }
-    ctrl->vmax = vmax;
-    double tau = ctrl->tau + dtd;
-    ctrl->tau = tau;
-    ctrl->nsub += 1;
-    ctrl->nsub_total += 1;
-    int done = ctrl->last;
-    if (!done) {
-        double rem = ctrl->dt_ad - tau;
-        if (!(rem > 0.0)) {
-            done = 1;
-        } else {
-            double dt_ac = P.cfl_ac_h / (P.c0d + vmax);
-            if (dt_ac >= rem) {
-                ctrl->dt = rem;
-                ctrl->last = 1;
-            } else {
-                ctrl->dt = dt_ac;
-                ctrl->last = 0;
-            }
+    const SubState Sp = ctrl->ss[q & 1];
+    const uint32_t err = ctrl->err;
+    bool stalled = false;
+    if (Sp.active && !err) {
+        const double vmax = slot_max<real>(vslot + (q & 1) * VSLOTS);
+        bool finished;
+        SubState n = next_substep(P, ctrl->dt_ad, Sp, vmax, finished);
+        stalled = !finished && stall;
+        if (threadIdx.x == 0) {
+            close_substep(ctrl, (q + 1) & 1, n, vmax, finished);
+            if (stalled) ctrl->err |= ERR_STALL;
         }
     }
-    if (done) {
-        ctrl->active = 0;
-        ctrl->t = ctrl->t_end;
-        ctrl->steps_done += 1;
-        ctrl->rebuild = 1;
-    }
+    vslot[threadIdx.x] = 0ull;
+    vslot[VSLOTS + threadIdx.x] = 0ull;
+    // with an error or a stall pending the slots are left for the host
+    if (threadIdx.x == 0 && prepare && !stalled && !err && ctrl->err == 0) prepare_step(P, ctrl);
 }
 
 // ---------------------------------------------------------------------

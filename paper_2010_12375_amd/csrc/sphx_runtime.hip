@@ -319,8 +319,8 @@ struct Engine final : EngineBase {
         RETCHK(dalloc(L, rank, n));
         RETCHK(dalloc(L, perm, n));
         RETCHK(dalloc(L, acc_out, (size_t)n * D));
-        RETCHK(dalloc(L, vslot, VSLOTS));
-        HIPCHK(hipMemsetAsync(vslot, 0, sizeof(unsigned long long) * VSLOTS, s));
+        RETCHK(dalloc(L, vslot, 2 * VSLOTS));
+        HIPCHK(hipMemsetAsync(vslot, 0, sizeof(unsigned long long) * 2 * VSLOTS, s));
         RETCHK(dalloc(L, drho_out, n));
         RETCHK(dalloc(L, outbuf, (size_t)n * D));
         RETCHK(dalloc(L, diag_part, (size_t)nblk(n) * NDIAG));
@@ -466,24 +466,27 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
-    int enqueue_substep(int a, int finalize, real* acc, real* dro)
+    // Pressure and density relaxation of sub-step q on set a; `adv`: close
+    // sub-step q - 1 first (inside the pressure relaxation).
+    int enqueue_substep(int a, int q, int adv, int finalize, real* acc, real* dro)
     {
-        k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a],
-                                                        dr3[a], hf, acc);
-        k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                       hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro,
-                                                                         vslot);
-        if (finalize) k_substep_end<real><<<1, 64, 0, s>>>(P, ctrl, vslot);
+        k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb,
+                                                                          wcnt, st[a], dr3[a], hf, acc, q, adv, vslot);
+        k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, finalize, geo[a], wgeo, wnrm, nbr,
+                                                                         ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
+                                                                         x[a][1], x[a][2], dro, vslot, q);
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
 
-    // One advection step on set a (graph body).
+    // One advection step on set a (graph body): re-init, the queued
+    // sub-steps, the step end (which prepares the next step), the rebuild.
     int enqueue_step(int a)
     {
-        k_adv_begin<real><<<1, 1, 0, s>>>(P, ctrl);
-        k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
-        for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, 1, nullptr, nullptr));
+        k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[a], wgeo, nbr, ncnt, wnb, wcnt,
+                                                                        st[a]);
+        for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr));
+        k_step_end<real><<<1, 64, 0, s>>>(P, ctrl, vslot, nsub_q - 1, 1, 1);
         RETCHK(enqueue_rebuild(1, a));
         return SPHX_OK;
     }
@@ -631,11 +634,10 @@ struct Engine final : EngineBase {
         RETCHK(sync_ctrl());
         Ctrl saved = *hctrl;
         RETCHK(backup_state());
-        hctrl->active = 1;
+        hctrl->ss[0] = SubState{0.0, dt, 0, 1, 0, 0};
         hctrl->err = 0;
-        hctrl->dt = dt;
         RETCHK(push_ctrl());
-        RETCHK(enqueue_substep(cur, 0, acc_out, drho_out));
+        RETCHK(enqueue_substep(cur, 0, 0, 0, acc_out, drho_out));
         if (dvdt) {
             k_unsort_vec<real><<<nblk(nf), BLOCK, 0, s>>>(nf, D, id[cur], acc_out, outbuf);
             HIPCHK(hipGetLastError());
@@ -655,19 +657,25 @@ struct Engine final : EngineBase {
     }
 
     // Finish an advection step that ran out of queued sub-steps, from the
-    // host, then rebuild its configuration.
+    // host, one sub-step per synchronisation; then rebuild its configuration
+    // and prepare the next step.
     int finish_stalled_step()
     {
         hctrl->err &= ~ERR_STALL;
         RETCHK(push_ctrl());
-        for (int it = 0; it < 100000; ++it) {
-            RETCHK(enqueue_substep(cur, 1, nullptr, nullptr));
+        int q = nsub_q;
+        for (int it = 0; it < 100000; ++it, ++q) {
+            RETCHK(enqueue_substep(cur, q, 0, 1, nullptr, nullptr));
+            k_step_end<real><<<1, 64, 0, s>>>(P, ctrl, vslot, q, 0, 0);
+            HIPCHK(hipGetLastError());
             RETCHK(sync_ctrl());
-            if (hctrl->err & ~ERR_STALL) return err_code(hctrl->err);
-            if (!hctrl->active) break;
+            if (hctrl->err) return err_code(hctrl->err);
+            if (hctrl->rebuild) break;
         }
-        if (hctrl->active) return ctx->fail(SPHX_ESTATE, "advection step did not finish");
+        if (!hctrl->rebuild) return ctx->fail(SPHX_ESTATE, "advection step did not finish");
         RETCHK(enqueue_rebuild(1, cur));
+        k_adv_begin<real><<<1, 1, 0, s>>>(P, ctrl);
+        HIPCHK(hipGetLastError());
         RETCHK(sync_ctrl());
         cur ^= 1;
         cur_steps = hctrl->steps_done;
@@ -684,7 +692,9 @@ struct Engine final : EngineBase {
         long long start = hctrl->steps_done;
         cur_steps = start;
         HIPCHK(hipMemcpyAsync(&ctrl->t_stop, &t_stop, sizeof(double), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
+        k_adv_begin<real><<<1, 1, 0, s>>>(P, ctrl);
+        HIPCHK(hipGetLastError());
+        RETCHK(sync_ctrl());
         long long remaining = n_steps;
         while (remaining > 0 && hctrl->t < t_stop) {
             // up to 64 steps per batch, one host synchronisation per batch
@@ -769,19 +779,15 @@ struct Engine final : EngineBase {
         HIPCHK(hipEventCreate(&ev[0]));
         HIPCHK(hipEventCreate(&ev[1]));
         double dt_ac = P.cfl_ac_h / (P.c0d + hctrl->vmax);
-        hctrl->active = 1;
+        hctrl->ss[0] = SubState{0.0, dt_ac, 0, 1, 0, 0};
         hctrl->err = 0;
-        hctrl->dt = dt_ac;
-        hctrl->last = 0;
-        hctrl->tau = 0;
-        hctrl->dt_ad = 1e300;
         RETCHK(push_ctrl());
         float t;
         // pressure relaxation
         HIPCHK(hipEventRecord(ev[0], s));
         for (int r = 0; r < reps; ++r)
-            k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                            st[cur], dr3[cur], hf, nullptr);
+            k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(
+                P, ctrl, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[cur], dr3[cur], hf, nullptr, 0, 0, vslot);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
@@ -791,7 +797,7 @@ struct Engine final : EngineBase {
         for (int r = 0; r < reps; ++r)
             k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf,
                                                            st[cur], dr3[cur], x[cur][0], x[cur][1], x[cur][2], nullptr,
-                                                                         vslot);
+                                                                         vslot, 0);
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipEventSynchronize(ev[1]));
         HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
