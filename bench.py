@@ -7,10 +7,11 @@ neighbour lists); the timed region ends with the FP64 diagnostics reduction.
 Inputs are seeded synthetic dam breaks (no dataset), resident in device
 memory before the timed region starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload medium|small|large]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload medium|small|large|ensemble]
 
 Prints one JSON line. value = fluid particles x acoustic sub-steps / wall
-time, in millions per second.
+time, in millions per second (summed over the cases for the ensemble of 64
+uneven dam breaks, which all advance in the same launches).
 """
 import argparse
 import json
@@ -93,12 +94,38 @@ def cpu_baseline(case, budget_s=15.0):
                       f"{wall:.1f} s, FP64 oracle, OpenMP"}
 
 
+def cpu_baseline_ensemble(cases, budget_s=15.0):
+    """The FP64 oracle on the ensemble's cases one after another, one
+    advection step each from t=0 (configuration build included), until the
+    time budget is spent."""
+    import oracle as O
+    t0 = time.perf_counter()
+    work = 0
+    nsub = 0
+    used = 0
+    for c in cases:
+        if time.perf_counter() - t0 >= budget_s:
+            break
+        o = O.Oracle(c)
+        o.build_config()
+        n = o.advance(1e9)
+        o.close()
+        work += c.n_fluid * n
+        nsub += n
+        used += 1
+    wall = time.perf_counter() - t0
+    return {"value": work / wall / 1e6, "unit": "M particle-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"first advection step ({nsub} acoustic sub-steps in all) of the first {used} of "
+                      f"{len(cases)} ensemble cases from t=0, one after another, {wall:.1f} s, FP64 oracle, OpenMP"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large"])
+    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large", "ensemble"])
+    ap.add_argument("--autotune", action="store_true", help="pick the pair-kernel lanes per particle first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--profile-reps", type=int, default=50)
@@ -125,13 +152,17 @@ def main():
     from paper_2010_12375_amd import sphx
     from paper_2010_12375_amd import workloads as wl
 
+    cases = None
     if args.workload == "small":
         case = wl.config_small(0)
         case.precision = wl.FP32
     elif args.workload == "medium":
         case = wl.config_medium(0)
-    else:
+    elif args.workload == "large":
         case = wl.config_large(0)
+    else:
+        cases = wl.ensemble_cases(64, seed=0)
+        case = cases[0]
     precision = case.precision
 
     stream = None
@@ -147,35 +178,52 @@ def main():
     except Exception:
         torch = None
 
-    sim = sphx.Simulation(sphx.params_from_case(case, precision), stream=stream)
-    sim.set_fluid(case.fluid_pos)
-    if case.n_wall:
-        sim.set_walls(case.wall_pos, case.wall_normal)
+    if cases is None:
+        sim = sphx.Simulation(sphx.params_from_case(case, precision), stream=stream)
+        sim.set_fluid(case.fluid_pos)
+        if case.n_wall:
+            sim.set_walls(case.wall_pos, case.wall_normal)
+        n_fluid, n_wall, name = case.n_fluid, case.n_wall, case.name
+    else:
+        sim = sphx.Simulation.from_cases(cases, precision, stream=stream)
+        n_fluid = sum(c.n_fluid for c in cases)
+        n_wall = sum(c.n_wall for c in cases)
+        name = f"ensemble64_dambreak2d ({n_fluid} fluid particles in 64 cases)"
     sim.build_neighbors()
+    lanes = sim.autotune(10) if args.autotune else None
     sim.advance(args.warmup)
     if torch is not None:
         torch.cuda.synchronize()
-    d0 = sim.diagnostics()
+    d0 = sim.diagnostics_all()
 
     t0 = time.perf_counter()
-    nsub = sim.advance(args.steps)
-    d1 = sim.diagnostics()
+    sim.advance(args.steps)
+    d1 = sim.diagnostics_all()
     if torch is not None:
         torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    steps_done = d1["n_steps"] - d0["n_steps"]
+    nf = [c.n_fluid for c in cases] if cases is not None else [case.n_fluid]
+    steps_done = d1[0]["n_steps"] - d0[0]["n_steps"]
+    steps_all = sum(b["n_steps"] - a["n_steps"] for a, b in zip(d0, d1))
+    nsub = sum(b["n_substeps"] - a["n_substeps"] for a, b in zip(d0, d1))
+    work = sum(n * (b["n_substeps"] - a["n_substeps"]) for n, a, b in zip(nf, d0, d1))
     cnt = sim.counts()
     pairs = cnt["inner_pairs"] + cnt["contact_pairs"]
-    value = case.n_fluid * nsub / wall / 1e6
-    pair_evals = 2.0 * pairs * nsub / wall
+    value = work / wall / 1e6
+    # directed pair evaluations: two relaxations per sub-step, each case its own sub-steps
+    pair_evals = 0.0
+    for k, (a, b) in enumerate(zip(d0, d1)):
+        ck = sim.counts(case=k) if cases is not None else cnt
+        pair_evals += 2.0 * (ck["inner_pairs"] + ck["contact_pairs"]) * (b["n_substeps"] - a["n_substeps"])
+    pair_evals /= wall
 
     prof = sim.profile(args.profile_reps)
-    k1_bytes, k2_bytes = algorithmic_bytes(case.dim, precision, case.n_fluid, cnt["inner_pairs"],
+    k1_bytes, k2_bytes = algorithmic_bytes(case.dim, precision, n_fluid, cnt["inner_pairs"],
                                            cnt["contact_pairs"])
     kern = {"pressure_relaxation": (prof["pressure"], k1_bytes), "density_relaxation": (prof["density"], k2_bytes)}
-    name = max(kern, key=lambda k: kern[k][0])
-    ms, nbytes = kern[name]
+    kname = max(kern, key=lambda k: kern[k][0])
+    ms, nbytes = kern[kname]
     achieved = nbytes / (ms * 1e-3) / 1e9
     flops = FLOPS_PER_PAIR * pairs
     valu = FP32_VALU_TFLOPS if precision == 1 else FP64_VALU_TFLOPS
@@ -195,35 +243,37 @@ def main():
         "dtype": "f32" if precision == 1 else "f64",
         "data": "synthetic",
         "config": {
-            "workload": case.name,
+            "workload": name,
             "dim": case.dim,
-            "n_fluid": case.n_fluid,
-            "n_wall": case.n_wall,
-            "dp": case.dp,
+            "n_fluid": n_fluid,
+            "n_wall": n_wall,
+            "dp": case.dp if cases is None else sorted({c.dp for c in cases}),
             "precision": "FP32 fields and pair arithmetic; FP64 positions, clock, diagnostics"
             if precision == 1 else "FP64",
             "acoustic_substeps": int(nsub),
-            "substeps_per_step": round(nsub / max(steps_done, 1), 3),
+            "substeps_per_step": round(nsub / max(steps_all, 1), 3),
             "pair_evals_per_s": round(pair_evals, 1),
-            "t_start": d0["t"],
-            "t_end": d1["t"],
+            "t_start": d0[0]["t"],
+            "t_end": d1[0]["t"],
             "kernel_ms": {k: round(v, 5) for k, v in prof.items()},
+            "pair_lanes": lanes,
         },
         "roofline": {
-            "kernel": name,
+            "kernel": kname,
             "bound": "hbm" if t_hbm >= t_alu else "alu",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(case.name, name),
+            "traffic": measured_traffic(case.name if cases is None else "ensemble64", kname),
             "alg_bytes_per_launch": int(nbytes),
             "alg_flops_per_launch": int(flops),
             "alu_frac": round(flops / (ms * 1e-3) / (valu * 1e12), 4),
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
+        out["cpu_baseline"] = (cpu_baseline(case, args.cpu_budget) if cases is None
+                               else cpu_baseline_ensemble(cases, args.cpu_budget))
     sim.close()
     print(json.dumps(out), flush=True)
 

@@ -1,23 +1,29 @@
 /*
  * sphx.h -- C ABI of the MI355X (gfx950) Riemann-WCSPH library.
  *
- * One library context holds one fluid body and one static wall body
- * (bodies made of particles with inner and contact interactions, Section 9
- * overview of the SPHinXsys paper, arXiv 2010.12375) and advances them with
+ * A library context holds a batch of one or more independent cases; each
+ * case is one fluid body and one static wall body (bodies made of particles
+ * with inner and contact interactions, Section 9 overview of the SPHinXsys
+ * paper, arXiv 2010.12375) with its own parameters and clock, advanced with
  * the paper's fluid scheme: Riemann-based continuity and momentum equations
  * (Section 2.2, Eq. riemannsph) with the one-sided wall condition (Section
  * 2.3), density re-initialisation (Eq. eqrhosum), dual-criteria time
- * stepping (Section 2.4) and position-based Verlet (Section 7).
+ * stepping (Section 2.4) and position-based Verlet (Section 7). All cases of
+ * a batch run in the same kernel launches.
  *
  * Conventions, for every call:
  *  - Return 0 on success or a negative SPHX_E* code; sphx_last_error() gives
- *    a message for the last failure on the context.
+ *    a message for the last failure on the context (prefixed "case k: " in a
+ *    batch of several cases).
  *  - All host pointers belong to the caller and are only read or written
  *    during the call. Device memory belongs to the library.
  *  - Arrays at the boundary are FP64 and in original particle order (the
- *    order of the arrays passed to sphx_set_fluid / sphx_set_walls), however
+ *    order of the arrays passed to sphx_set_fluid* / sphx_set_walls*), however
  *    the library orders particles internally. Vectors are packed n * dim.
- *  - Work is queued on the stream given to sphx_create (or one the library
+ *  - Calls without a case index act on case 0, except sphx_build_neighbors,
+ *    sphx_density_reinit, sphx_advance, sphx_profile and sphx_counts, which
+ *    act on the whole batch. Case indices out of range give SPHX_EINVAL.
+ *  - Work is queued on the stream given at creation (or one the library
  *    creates); calls that return data synchronise that stream.
  *  - A context is not thread-safe; separate contexts are independent.
  */
@@ -58,8 +64,9 @@ typedef struct {
     int32_t dim;         /* 2 or 3 */
     int32_t precision;   /* SPHX_FP64 or SPHX_FP32 */
     int32_t periodic[3]; /* periodic axes (period = hi - lo); need >= 3 cells of 2h */
-    int32_t nsub_queue;  /* acoustic sub-steps queued per advection step (0: default 5);
-                            a step that needs more is finished by the host, same result */
+    int32_t nsub_queue;  /* acoustic sub-steps per queued graph launch (0: default 5; the
+                            batch takes case 0's); a step that needs more continues in
+                            the next queue, with the same result */
     double dp;           /* initial particle spacing: fluid mass rho0 dp^dim, wall volume dp^dim */
     double h;            /* smoothing length; Wendland C2 support radius 2h */
     double rho0;         /* reference density */
@@ -86,11 +93,20 @@ typedef struct {
     int64_t n_steps;    /* advection steps since sphx_set_fluid */
 } sphx_diag;
 
-/* Create a context. stream: a hipStream_t to queue work on, or NULL for a
- * library-owned stream (default priority). Fails with SPHX_EINVAL for dim
- * other than 2/3, non-positive sizes, a periodic axis with fewer than 3
- * cells of size 2h, or an empty box. */
+/* Create a context with one case. stream: a hipStream_t to queue work on,
+ * or NULL for a library-owned stream (default priority). Fails with
+ * SPHX_EINVAL for dim other than 2/3, non-positive sizes, a periodic axis
+ * with fewer than 3 cells of size 2h, or an empty box. */
 int sphx_create(const sphx_params* params, void* stream, sphx_ctx** out);
+
+/* Create a context with a batch of n_cases >= 1 cases, params[c] for case c
+ * (an array of n_cases). Every case must have the same dim and precision;
+ * sizes, boxes, sound speeds and every other parameter may differ. The cases
+ * start empty; each needs sphx_set_fluid_case before it can run. */
+int sphx_create_batch(const sphx_params* params, int32_t n_cases, void* stream, sphx_ctx** out);
+
+/* Number of cases of the context (or SPHX_EINVAL for NULL). */
+int sphx_num_cases(const sphx_ctx* ctx);
 
 /* Free every device buffer, graph and the owned stream. NULL is a no-op. */
 void sphx_destroy(sphx_ctx* ctx);
@@ -105,16 +121,28 @@ const char* sphx_last_error(const sphx_ctx* ctx);
 int sphx_set_fluid(sphx_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* rho,
                    const double* drho);
 
+/* The same for case c. Resets that case's clock and counters only; the
+ * other cases keep their state (the device layout may grow, moving them).
+ * Invalidates the neighbour configuration of the batch. */
+int sphx_set_fluid_case(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* vel,
+                        const double* rho, const double* drho);
+
 /* Static wall particles: pos n*dim and unit normals n*dim pointing into the
  * fluid (Section 2.3 wall normal). Every wall particle must lie inside the
  * domain box. Invalidates the neighbour configuration. */
 int sphx_set_walls(sphx_ctx* ctx, int64_t n, const double* pos, const double* normal);
 
+/* The same for case c (inside case c's box). */
+int sphx_set_walls_case(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* normal);
+
 /* Configuration update (Section 2.4: at the advection frequency): wrap
  * periodic coordinates, bin particles into cells of size >= 2h, rebuild the
  * inner and contact neighbour lists with the FP64 predicate r^2 < (2h)^2
  * (dx = x_i - x_j, one minimum-image wrap, left-to-right sum), and freeze
- * the pair geometry. SPHX_EESCAPE / SPHX_ENAN / SPHX_EOVERFLOW on failure. */
+ * the pair geometry, for every case. SPHX_EESCAPE / SPHX_ENAN / SPHX_EOVERFLOW
+ * (of the lowest failing case) on failure; then the batch has no
+ * configuration until a later call succeeds. Every case needs fluid
+ * (SPHX_ESTATE otherwise). */
 int sphx_build_neighbors(sphx_ctx* ctx);
 
 /* Neighbour lists as CSR of original ids, ascending within each row.
@@ -123,14 +151,19 @@ int sphx_build_neighbors(sphx_ctx* ctx);
  * SPHX_ECAP if idx is given and cap < *n_out. */
 int sphx_get_neighbors(sphx_ctx* ctx, int kind, int64_t* off, int64_t* idx, int64_t cap, int64_t* n_out);
 
+/* The same for case c (ids relative to that case's own arrays). */
+int sphx_get_neighbors_case(sphx_ctx* ctx, int32_t c, int kind, int64_t* off, int64_t* idx, int64_t cap,
+                            int64_t* n_out);
+
 /* Density re-initialisation of Eq. eqrhosum on the current configuration:
  * rho = max(rho, rho0 sum W / sum W0), sums over self, fluid and wall
- * neighbours. */
+ * neighbours; every case. */
 int sphx_density_reinit(sphx_ctx* ctx);
 
 /* The two time-step criteria for the current state (Eqs. dt-advection
  * without viscosity, |v|max floored at u_ref, and dt-relax). */
 int sphx_time_steps(sphx_ctx* ctx, double* dt_ad, double* dt_ac);
+int sphx_time_steps_case(sphx_ctx* ctx, int32_t c, double* dt_ad, double* dt_ac);
 
 /* The rates of one acoustic sub-step of size dt from the current state,
  * which is left unchanged: the pressure relaxation's dv/dt (n*dim, gravity
@@ -138,33 +171,59 @@ int sphx_time_steps(sphx_ctx* ctx, double* dt_ad, double* dt_ac);
  * Eq. verlet-first-half, Eq. riemannsph momentum, Eq. verlet-first-mediate,
  * Eq. riemannsph continuity. Requires a configuration. */
 int sphx_compute_rates(sphx_ctx* ctx, double dt, double* dvdt, double* drhodt);
+int sphx_compute_rates_case(sphx_ctx* ctx, int32_t c, double dt, double* dvdt, double* drhodt);
 
-/* Advance up to n_steps advection steps (each: dt_ad, density
+/* Advance every case by up to n_steps advection steps (each: dt_ad, density
  * re-initialisation, acoustic sub-steps until the step is covered, the last
- * clipped to land on it, then the configuration update), stopping early when
- * the clock reaches t_stop (a step is clipped to end exactly on t_stop).
- * Sub-step control stays on the device; the host synchronises once per
- * call. *n_substeps (may be NULL) receives the acoustic sub-steps done,
- * *t_out (may be NULL) the clock. */
+ * clipped to land on it, then the configuration update), each case stopping
+ * early when its clock reaches t_stop (a step is clipped to end exactly on
+ * t_stop). The cases advance together, one advection step per case per
+ * queued graph launch; sub-step control stays on the device and the host
+ * synchronises once per batch of up to 64 launches. A case that fails (NaN,
+ * escape, list overflow) stops where it failed while the others go on; the
+ * call then returns the error of the lowest failing case (see
+ * sphx_case_status). *n_substeps (may be NULL) receives the acoustic
+ * sub-steps done, summed over the cases, *t_out (may be NULL) case 0's
+ * clock. */
 int sphx_advance(sphx_ctx* ctx, int32_t n_steps, double t_stop, int64_t* n_substeps, double* t_out);
+
+/* Error state of case c: SPHX_OK, or the code of the failure that stopped
+ * it (sticky until its fluid is set again or a configuration update of the
+ * batch succeeds). */
+int sphx_case_status(sphx_ctx* ctx, int32_t c);
 
 /* Field in original order as FP64 (SPHX_FIELD_*). */
 int sphx_get_field(sphx_ctx* ctx, int field, double* out);
+int sphx_get_field_case(sphx_ctx* ctx, int32_t c, int field, double* out);
 
 /* FP64 global observables of the current state (reduced on the device). */
 int sphx_diagnostics(sphx_ctx* ctx, sphx_diag* out);
 
-/* Average device time per launch (milliseconds) of the acoustic sub-step
- * kernels, measured with HIP events on the context's stream over `reps`
- * launches each of the pressure and density relaxation on the current
- * state; the state and clock are restored afterwards. ms[0] pressure
- * relaxation, ms[1] density relaxation, ms[2] neighbour build, ms[3] one
- * whole advection step launch (graph), per launch. */
+/* The same for case c into out[0]; for c < 0, every case into out[0 ..
+ * n_cases). */
+int sphx_diagnostics_case(sphx_ctx* ctx, int32_t c, sphx_diag* out);
+
+/* Average device time per launch (milliseconds) of the hot kernels,
+ * measured with HIP events on the context's stream over `reps` launches
+ * each, on the current state of every case (each case one acoustic sub-step
+ * of its own dt_ac); state and clocks are restored afterwards. ms[0]
+ * pressure relaxation, ms[1] density relaxation, ms[2] neighbour-list build,
+ * ms[3] density re-initialisation. */
 int sphx_profile(sphx_ctx* ctx, int32_t reps, double* ms);
 
 /* Particle and pair counts of the current configuration: out[0] fluid,
- * out[1] wall, out[2] inner pairs (directed), out[3] contact pairs. */
+ * out[1] wall, out[2] inner pairs (directed), out[3] contact pairs; summed
+ * over the batch, or for case c. */
 int sphx_counts(sphx_ctx* ctx, int64_t* out);
+int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out);
+
+/* Choose the lanes per particle of the pair kernels (4 or 8) by timing
+ * `reps` launches of the pressure and density relaxation of the batch with
+ * each, and rebuild the configuration for the faster one (*lanes, may be
+ * NULL). The lists are the same; the per-particle sums are combined in a
+ * different order, so later results can differ from the default's at
+ * rounding level. Requires a configuration. */
+int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes);
 
 #ifdef __cplusplus
 }

@@ -6,9 +6,15 @@
 // riemannsph, eqriepartial, eqrienoslip, eqriepright), dual-criteria time
 // steps (Eqs. dt-advection, dt-relax) and position-based Verlet (Section 7).
 //
-// Data layout (all arrays in cell-sorted particle order, structure of
-// arrays for what a thread reads only for itself, small packed records for
-// what neighbours gather):
+// One launch serves a batch of independent cases, each a fluid body and a
+// static wall body with its own parameters, clock and time steps. Every case
+// owns whole tiles of TILE consecutive particle slots, so a wavefront (and a
+// block of a pair kernel) never spans two cases: the case and its parameters
+// are uniform and come from the parameter table with scalar loads.
+//
+// Data layout (cases concatenated; inside a case cell-sorted particle order;
+// structure of arrays for what a thread reads only for itself, small packed
+// records for what neighbours gather):
 //   x[k]   double   position accumulators, one array per axis
 //   geo    R2/R4    FP32 (or FP64) offset of the configuration-time position
 //                   from the origin of its cell: the frozen pair geometry is
@@ -18,12 +24,15 @@
 //   st     R4       {v0, v1, dev, drho} in 2D, {v0, v1, v2, dev} in 3D, with
 //                   dev = rho - rho0 (the density deviation carries the
 //                   pressure p = c^2 dev without the cancellation of rho - rho0)
-//   drho3  real     drho/dt in 3D
+//   dr3    real     drho/dt in 3D
 //   hf     R4       {vn.., dev_half}: v^{n+1} and rho^{n+1/2} - rho0 written by
 //                   the pressure relaxation for the density relaxation
 //   nbr    u32      neighbour entries, wave-tiled (ell_at): sorted index |
 //                   stencil code << 26, the code holding the cell offset
 //                   dc + 1 (2 bits per axis)
+// Cells: case c owns global cells [cbase, cbase + ncell) and one padding cell
+// cbase + ncell that holds its unused slots, so one counting sort over all
+// cells leaves every case on its own slot range.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,8 +41,9 @@ namespace sphx {
 
 constexpr int NBR_SHIFT = 26;
 constexpr uint32_t NBR_MASK = (1u << NBR_SHIFT) - 1u;
-constexpr int BLOCK = 256;
-constexpr int BATCH = 4;  // list entries / candidate rounds loaded ahead per lane
+constexpr int TILE = 64;    // particle slots per tile; cases own whole tiles
+constexpr int BLOCK = 256;  // threads per block of every particle kernel
+constexpr int BATCH = 4;    // list entries / candidate rounds loaded ahead per lane
 constexpr uint32_t NO_ENTRY = 0xffffffffu;  // stencil code 63 never occurs
 constexpr int VSLOTS = 64;  // slots the density relaxation folds its block maxima into
 
@@ -41,13 +51,13 @@ enum : uint32_t {
     ERR_ESCAPE = 1u,       // a fluid particle left the domain box
     ERR_NAN = 2u,          // NaN in the state
     ERR_NBR_OVERFLOW = 4u, // neighbour list capacity exceeded
-    ERR_STALL = 8u,        // an advection step needed more sub-steps than queued
 };
 
-// State of one acoustic sub-step; sub-step q of an advection step lives in
+// State of one acoustic sub-step; sub-step q of a queue lives in
 // Ctrl::ss[q & 1]. The pressure relaxation of sub-step q derives it from
-// sub-step q - 1 (every block computes the same values, block 0 stores
-// them), so no kernel reads a slot that the same launch writes.
+// sub-step q - 1 (every block of the case computes the same values, the
+// case's first block stores them), so no kernel reads a slot that the same
+// launch writes.
 struct SubState {
     double tau;      // time covered inside the advection step before this sub-step
     double dt;       // size of this sub-step
@@ -57,7 +67,7 @@ struct SubState {
     int32_t pad;
 };
 
-// Device-side control block of the time loop.
+// Device-side control block of one case's time loop.
 struct Ctrl {
     double t;          // clock (time of the current state)
     double t_end;      // end of the current advection step
@@ -66,10 +76,11 @@ struct Ctrl {
     double vmax;       // |v|max of the current state
     unsigned long long vmax_bits;  // scratch of k_vmax
     SubState ss[2];
-    int32_t rebuild;   // the step is complete: rebuild the configuration
-    int32_t pad0;
+    int32_t midstep;   // the advection step continues in the next queue (its state is in ss[0])
+    int32_t rebuild;   // an advection step ended in this queue: update the configuration
     long long nsub_total;
     long long steps_done;
+    long long steps_target;  // no advection step starts once steps_done reaches it
     uint32_t err;         // sticky error bits; no kernel that tests them also sets them
     uint32_t err_pending; // bits raised by the density relaxation, folded into err later
 };
@@ -81,7 +92,7 @@ template <typename real> __device__ __forceinline__ real zc(const R4<real>& v) {
 template <int D, typename real> struct GeoSel { using T = R2<real>; };
 template <typename real> struct GeoSel<3, real> { using T = R4<real>; };
 
-// Parameters of one simulation, passed by value to every kernel.
+// Parameters of one case (device table, one entry per case).
 template <typename real> struct KP {
     real rho0, c, c2, inv_c2, half_inv_c;     // EoS and Riemann
     real two_m, m, two_vw, vw;                // particle mass and wall volume
@@ -93,7 +104,11 @@ template <typename real> struct KP {
     int n[3], periodic[3];
     double rc2, sigma0, rho0d;
     double cfl_ad_h, cfl_ac_h, u_ref, c0d;
-    int nf, nw, cap, maxn, maxw;
+    int maxn, maxw;                           // list capacity per particle (same for every case)
+    int case_id;
+    int fbase, nf, fcap;                      // fluid slots [fbase, fbase + fcap), the first nf used
+    int wbase, nw;                            // wall slots [wbase, wbase + nw)
+    int cbase, ncell;                         // cells [cbase, cbase + ncell), padding cell cbase + ncell
 };
 
 // Neighbour lists are wave-tiled: the 64/T particles served by one
@@ -121,6 +136,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     const int x = b % NXCD, k = b / NXCD;
     const int q = nb / NXCD, rem = nb % NXCD;
     return k + x * q + (x < rem ? x : rem);
+}
+
+// Tile of the calling wavefront in a one-thread-per-slot launch of BLOCK
+// threads (uniform over the wavefront).
+__device__ __forceinline__ int wave_tile()
+{
+    return __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)BLOCK + threadIdx.x) >> 6));
 }
 
 // ---------------------------------------------------------------------
@@ -155,14 +177,31 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Cell coordinate along axis k (clamped into the grid).
+// Sum over the T lanes of a group (groups are aligned inside the wavefront).
+template <int T>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+template <int T>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Cell coordinate along axis k, clamped into the case's grid (NaN and
+// infinities included, so a bad position still yields a valid cell).
 template <typename real>
 __device__ __forceinline__ int cell_coord(const KP<real>& P, int k, double xk)
 {
-    int c = (int)floor((xk - P.lo[k]) / P.Ld[k]);
-    c = c < 0 ? 0 : c;
-    c = c >= P.n[k] ? P.n[k] - 1 : c;
-    return c;
+    double f = floor((xk - P.lo[k]) / P.Ld[k]);
+    if (!(f >= 0.0)) f = 0.0;
+    if (f > (double)(P.n[k] - 1)) f = (double)(P.n[k] - 1);
+    return (int)f;
 }
 
 // FP64 neighbour predicate on absolute positions: dx = x_i - x_j with one
@@ -224,45 +263,57 @@ __device__ __forceinline__ real kernel_W(const KP<real>& P, real r)
     return P.Wc * s * s * s * s * ((real)1 + (real)2 * qh);
 }
 
+// A case updates its configuration when one of its advection steps ended in
+// the queue just run (or on request, `force`); otherwise its cells, order,
+// frozen geometry and lists are kept, and the sort below is the identity on
+// its slots. The decision is read from state no kernel of the update writes.
+__device__ __forceinline__ bool full_update(const Ctrl* ctrl, int force) { return force || ctrl->rebuild; }
+
 // ---------------------------------------------------------------------
-// S1: cell binning (counting sort)
+// S1: cell binning (one stable counting sort over the cells of all cases)
 
-__global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-// Wrap periodic coordinates, check escapes, compute the cell key and an
-// arrival rank inside the cell. `gate`: skip unless the step is complete.
+// Wrap periodic coordinates, check escapes, compute the global cell key and
+// an arrival rank inside the cell (one thread per slot). The last tile of a
+// case puts the case's unused slots into its padding cell.
 template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_bin(KP<real> P, Ctrl* __restrict__ ctrl, int gate, int n,
-                                                double* __restrict__ x0, double* __restrict__ x1,
-                                                double* __restrict__ x2, int32_t* __restrict__ key,
-                                                int32_t* __restrict__ rank, int32_t* __restrict__ cnt,
-                                                int wrap)
+__global__ __launch_bounds__(BLOCK) void k_bin(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
+                                               int ntiles, Ctrl* __restrict__ ctrl_all, int force,
+                                               double* __restrict__ x0, double* __restrict__ x1,
+                                               double* __restrict__ x2, const int32_t* __restrict__ cell,
+                                               int32_t* __restrict__ key, int32_t* __restrict__ rank,
+                                               int32_t* __restrict__ cnt)
 {
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double* xs[3] = {x0, x1, x2};
-    int c[3] = {0, 0, 0};
-    uint32_t bad = 0;
+    const int tile = wave_tile();
+    if (tile >= ntiles) return;
+    const KP<real>& P = Pt[tcase[tile]];
+    Ctrl* ctrl = ctrl_all + P.case_id;
+    const int lane = threadIdx.x & 63;
+    const int i = tile * TILE + lane;
+    if (lane == 0 && i + TILE == P.fbase + P.fcap) cnt[P.cbase + P.ncell] = P.fcap - P.nf;
+    if (i >= P.fbase + P.nf) return;
+    int kc;
+    if (!full_update(ctrl, force)) {
+        kc = cell[i];
+    } else {
+        double* xs[3] = {x0, x1, x2};
+        int c[3] = {0, 0, 0};
+        uint32_t bad = 0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double xk = xs[k][i];
-        if (xk != xk) bad |= ERR_NAN;
-        if (wrap && P.periodic[k]) {
-            double w = xk;
-            if (w >= P.hi[k]) w -= P.period[k];
-            else if (w < P.lo[k]) w += P.period[k];
-            if (w != xk) { xs[k][i] = w; xk = w; }
+        for (int k = 0; k < D; ++k) {
+            double xk = xs[k][i];
+            if (xk != xk) bad |= ERR_NAN;
+            if (P.periodic[k]) {
+                double w = xk;
+                if (w >= P.hi[k]) w -= P.period[k];
+                else if (w < P.lo[k]) w += P.period[k];
+                if (w != xk) { xs[k][i] = w; xk = w; }
+            }
+            if (!(xk >= P.lo[k] && xk < P.hi[k])) bad |= ERR_ESCAPE;
+            c[k] = cell_coord(P, k, xk);
         }
-        if (!(xk >= P.lo[k] && xk < P.hi[k])) bad |= ERR_ESCAPE;
-        c[k] = cell_coord(P, k, xk);
+        if (bad) atomicOr(&ctrl->err, bad);
+        kc = P.cbase + c[0] + P.n[0] * (c[1] + P.n[1] * c[2]);
     }
-    if (bad) atomicOr(&ctrl->err, bad);
-    int kc = c[0] + P.n[0] * (c[1] + P.n[1] * c[2]);
     key[i] = kc;
     rank[i] = atomicAdd(&cnt[kc], 1);
 }
@@ -290,11 +341,9 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total)
     return incl - v;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_tiles(Ctrl* __restrict__ ctrl, int gate,
-                                                      int32_t* __restrict__ cnt, int32_t* __restrict__ start,
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(int32_t* __restrict__ cnt, int32_t* __restrict__ start,
                                                       int32_t* __restrict__ bsum, int n)
 {
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
     __shared__ int sh[BLOCK];
     int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int v[SCAN_ITEMS];
@@ -318,9 +367,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_tiles(Ctrl* __restrict__ ctrl, i
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_top(Ctrl* __restrict__ ctrl, int gate, int32_t* __restrict__ bsum, int nb)
+__global__ __launch_bounds__(BLOCK) void k_scan_top(int32_t* __restrict__ bsum, int nb)
 {
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
     __shared__ int sh[BLOCK];
     int carry = 0;
     for (int b0 = 0; b0 < nb; b0 += BLOCK) {
@@ -335,10 +383,9 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(Ctrl* __restrict__ ctrl, int
     if (threadIdx.x == 0) bsum[nb] = carry;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_add(Ctrl* __restrict__ ctrl, int gate, int32_t* __restrict__ start,
-                                                    const int32_t* __restrict__ bsum, int n, int nb)
+__global__ __launch_bounds__(BLOCK) void k_scan_add(int32_t* __restrict__ start, const int32_t* __restrict__ bsum,
+                                                    int n, int nb)
 {
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
     int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int off = bsum[blockIdx.x];
 #pragma unroll
@@ -347,24 +394,110 @@ __global__ __launch_bounds__(BLOCK) void k_scan_add(Ctrl* __restrict__ ctrl, int
     if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = bsum[nb];
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scatter(Ctrl* __restrict__ ctrl, int gate, int n, const int32_t* __restrict__ key,
-                                                   const int32_t* __restrict__ rank, const int32_t* __restrict__ start,
-                                                   int32_t* __restrict__ perm)
+// Arrival-order list of each cell's fluid particles.
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_scatter(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
+                                                   int ntiles, int n, const int32_t* __restrict__ key,
+                                                   const int32_t* __restrict__ rank,
+                                                   const int32_t* __restrict__ start, int32_t* __restrict__ perm)
 {
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int tile = wave_tile();
+    if (tile >= ntiles) return;
+    const KP<real>& P = Pt[tcase[tile]];
+    const int i = tile * TILE + (threadIdx.x & 63);
+    if (i >= P.fbase + P.nf) return;
     int p = start[key[i]] + rank[i];
     if (p < n) perm[p] = i;  // always true for consistent counts
 }
 
-// Order each cell's particles by their previous sorted index: together with
-// the scatter this is a stable counting sort, so the order (and every sum
-// over it) is deterministic.
-__global__ __launch_bounds__(BLOCK) void k_cell_order(Ctrl* __restrict__ ctrl, int gate, int ncell,
-                                                      const int32_t* __restrict__ start, int32_t* __restrict__ perm)
+// Stable placement: a particle's slot in its new cell is the number of
+// particles of that cell with a smaller previous index (counted over the
+// cell's arrival-order list from k_scatter), which is the order of a stable
+// counting sort. The particle's state moves there; with a full update the
+// configuration geometry is frozen anew as offsets from the cell origin,
+// otherwise (identity placement) the frozen offsets move along.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_place_fluid(
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, int ntiles,
+    const Ctrl* __restrict__ ctrl_all, int force, int n, const int32_t* __restrict__ arrival,
+    const int32_t* __restrict__ key, const int32_t* __restrict__ start, const double* __restrict__ ax0,
+    const double* __restrict__ ax1, const double* __restrict__ ax2, const R4<real>* __restrict__ ast,
+    const real* __restrict__ adr, const int32_t* __restrict__ aid, const typename GeoSel<D, real>::T* __restrict__ ageo,
+    double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2, R4<real>* __restrict__ bst,
+    real* __restrict__ bdr, int32_t* __restrict__ bid, int32_t* __restrict__ bcell,
+    typename GeoSel<D, real>::T* __restrict__ bgeo)
 {
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
+    const int tile = wave_tile();
+    if (tile >= ntiles) return;
+    const KP<real>& P = Pt[tcase[tile]];
+    const bool full = full_update(ctrl_all + P.case_id, force);
+    const int i = tile * TILE + (threadIdx.x & 63);
+    if (i >= P.fbase + P.nf) return;
+    int kc = key[i];
+    int s0 = start[kc], s1 = min(start[kc + 1], n);
+    int s = s0;
+    for (int q = s0; q < s1; ++q) s += arrival[q] < i;
+    if (s >= n) return;  // never for consistent counts
+    double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
+    bx0[s] = x[0];
+    bx1[s] = x[1];
+    if (D == 3) bx2[s] = x[2];
+    bst[s] = ast[i];
+    if (D == 3) bdr[s] = adr[i];
+    bid[s] = aid[i];
+    bcell[s] = kc;
+    if (!full) {
+        bgeo[s] = ageo[i];
+        return;
+    }
+    const int lc = kc - P.cbase;
+    const int c0 = lc % P.n[0];
+    const int c1 = (lc / P.n[0]) % P.n[1];
+    const int c2 = lc / (P.n[0] * P.n[1]);
+    typename GeoSel<D, real>::T g;
+    g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
+    g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
+    if constexpr (D == 3) {
+        g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
+        g.w = (real)0;
+    }
+    bgeo[s] = g;
+}
+
+// Walls (set-up only; walls are static). `wcase` gives the case of each wall
+// particle in input order.
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_bin_walls(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ wcase,
+                                                     int n, const double* __restrict__ x0,
+                                                     const double* __restrict__ x1, const double* __restrict__ x2,
+                                                     int32_t* __restrict__ key, int32_t* __restrict__ rank,
+                                                     int32_t* __restrict__ cnt)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const KP<real>& P = Pt[wcase[i]];
+    const double xs[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
+    int c[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) c[k] = cell_coord(P, k, xs[k]);
+    int kc = P.cbase + c[0] + P.n[0] * (c[1] + P.n[1] * c[2]);
+    key[i] = kc;
+    rank[i] = atomicAdd(&cnt[kc], 1);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scatter_walls(int n, const int32_t* __restrict__ key,
+                                                         const int32_t* __restrict__ rank,
+                                                         const int32_t* __restrict__ start, int32_t* __restrict__ perm)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int p = start[key[i]] + rank[i];
+    if (p < n) perm[p] = i;
+}
+
+// Order each cell's wall particles by input index (deterministic order).
+__global__ __launch_bounds__(BLOCK) void k_cell_order(int ncell, const int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ perm)
+{
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     int s = start[c], e = start[c + 1];
@@ -379,104 +512,27 @@ __global__ __launch_bounds__(BLOCK) void k_cell_order(Ctrl* __restrict__ ctrl, i
     }
 }
 
-// Gather the fluid state into the new order and freeze the configuration
-// geometry as offsets from the cell origin.
-template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_gather_fluid(
-    KP<real> P, Ctrl* __restrict__ ctrl, int gate, int n, const int32_t* __restrict__ perm,
-    const int32_t* __restrict__ key, const double* __restrict__ ax0, const double* __restrict__ ax1,
-    const double* __restrict__ ax2, const R4<real>* __restrict__ ast, const real* __restrict__ adr,
-    const int32_t* __restrict__ aid, double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
-    R4<real>* __restrict__ bst, real* __restrict__ bdr, int32_t* __restrict__ bid, int32_t* __restrict__ bcell,
-    typename GeoSel<D, real>::T* __restrict__ bgeo)
-{
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    int i = perm[s];
-    int kc = key[i];
-    double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
-    bx0[s] = x[0];
-    bx1[s] = x[1];
-    if (D == 3) bx2[s] = x[2];
-    bst[s] = ast[i];
-    if (D == 3) bdr[s] = adr[i];
-    bid[s] = aid[i];
-    bcell[s] = kc;
-    int c0 = kc % P.n[0];
-    int c1 = (kc / P.n[0]) % P.n[1];
-    int c2 = kc / (P.n[0] * P.n[1]);
-    typename GeoSel<D, real>::T g;
-    g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
-    g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
-    if constexpr (D == 3) {
-        g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
-        g.w = (real)0;
-    }
-    bgeo[s] = g;
-}
-
-// Stable placement: a particle's slot in its new cell is the number of
-// particles of that cell with a smaller previous index (counted over the
-// cell's arrival-order list from k_scatter), which is the order of a stable
-// counting sort. The particle's state moves there and the configuration
-// geometry is frozen as offsets from the cell origin.
-template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_place_fluid(
-    KP<real> P, Ctrl* __restrict__ ctrl, int gate, int n, const int32_t* __restrict__ arrival,
-    const int32_t* __restrict__ key, const int32_t* __restrict__ start, const double* __restrict__ ax0,
-    const double* __restrict__ ax1, const double* __restrict__ ax2, const R4<real>* __restrict__ ast,
-    const real* __restrict__ adr, const int32_t* __restrict__ aid, double* __restrict__ bx0,
-    double* __restrict__ bx1, double* __restrict__ bx2, R4<real>* __restrict__ bst, real* __restrict__ bdr,
-    int32_t* __restrict__ bid, int32_t* __restrict__ bcell, typename GeoSel<D, real>::T* __restrict__ bgeo)
-{
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int kc = key[i];
-    int s0 = start[kc], s1 = min(start[kc + 1], n);
-    int s = s0;
-    for (int q = s0; q < s1; ++q) s += arrival[q] < i;
-    if (s >= n) return;  // never for consistent counts
-    double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
-    bx0[s] = x[0];
-    bx1[s] = x[1];
-    if (D == 3) bx2[s] = x[2];
-    bst[s] = ast[i];
-    if (D == 3) bdr[s] = adr[i];
-    bid[s] = aid[i];
-    bcell[s] = kc;
-    int c0 = kc % P.n[0];
-    int c1 = (kc / P.n[0]) % P.n[1];
-    int c2 = kc / (P.n[0] * P.n[1]);
-    typename GeoSel<D, real>::T g;
-    g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
-    g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
-    if constexpr (D == 3) {
-        g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
-        g.w = (real)0;
-    }
-    bgeo[s] = g;
-}
-
+// Walls: move into cell order, freeze offsets, keep ids relative to the
+// case's first wall particle.
 template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_gather_wall(
-    KP<real> P, int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ key,
-    const double* __restrict__ ax0, const double* __restrict__ ax1, const double* __restrict__ ax2,
-    const double* __restrict__ an0, const double* __restrict__ an1, const double* __restrict__ an2,
-    double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ wcase, int n, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ key, const double* __restrict__ ax0, const double* __restrict__ ax1,
+    const double* __restrict__ ax2, const double* __restrict__ an0, const double* __restrict__ an1,
+    const double* __restrict__ an2, double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
     typename GeoSel<D, real>::T* __restrict__ bgeo, typename GeoSel<D, real>::T* __restrict__ bnrm,
     int32_t* __restrict__ bid)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
-    int kc = key[i];
+    const KP<real>& P = Pt[wcase[i]];
+    int kc = key[i] - P.cbase;
     double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
     bx0[s] = x[0];
     bx1[s] = x[1];
     if (D == 3) bx2[s] = x[2];
-    bid[s] = i;
+    bid[s] = i - P.wbase;
     int c0 = kc % P.n[0];
     int c1 = (kc / P.n[0]) % P.n[1];
     int c2 = kc / (P.n[0] * P.n[1]);
@@ -502,18 +558,21 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
 // positions. Entries keep the cell offset so that the pair geometry can be
 // rebuilt from cell offsets.
 //
-// TB lanes share one particle. The three x-adjacent cells of a stencil row
-// are one contiguous range of the sorted order, scanned TB candidates per
-// round; hits are appended in candidate order through a ballot, so the list
-// does not depend on TB. In FP32 mode a candidate is first classified on the
-// FP32 cell offsets: |r2_32 - r2| <= 6 * 2^-24 L (2 r) + 3 * 2^-24 r^2 <
-// 2.4e-6 L^2 for r <= L (offsets and cell sizes rounded once to FP32, then
-// four roundings in the difference), so with margin 8e-6 L^2 only candidates
-// in a thin shell around 2h need the FP64 test, and the list is bit-exact.
+// TB lanes share one particle; a block is one tile. The three x-adjacent
+// cells of a stencil row are one contiguous range of the sorted order,
+// scanned TB candidates per round; hits are appended in candidate order
+// through a ballot, so the list does not depend on TB. In FP32 mode a
+// candidate is first classified on the FP32 cell offsets: |r2_32 - r2| <=
+// 6 * 2^-24 L (2 r) + 3 * 2^-24 r^2 < 2.4e-6 L^2 for r <= L (offsets and cell
+// sizes rounded once to FP32, then four roundings in the difference), so with
+// margin 8e-6 L^2 only candidates in a thin shell around 2h need the FP64
+// test, and the list is bit-exact. Cases without a full update keep their
+// lists (their order did not change).
 template <int D, typename real, int T, int TB>
-__global__ __launch_bounds__(BLOCK) void k_neighbors(
-    KP<real> P, Ctrl* __restrict__ ctrl, int gate, const double* __restrict__ x0, const double* __restrict__ x1,
-    const double* __restrict__ x2, const int32_t* __restrict__ cell, const int32_t* __restrict__ fstart,
+__global__ __launch_bounds__(TILE * TB) void k_neighbors(
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int force,
+    const double* __restrict__ x0, const double* __restrict__ x1, const double* __restrict__ x2,
+    const int32_t* __restrict__ cell, const int32_t* __restrict__ fstart,
     const typename GeoSel<D, real>::T* __restrict__ geo, const double* __restrict__ wx0,
     const double* __restrict__ wx1, const double* __restrict__ wx2, const int32_t* __restrict__ wstart,
     const typename GeoSel<D, real>::T* __restrict__ wgeo, uint32_t* __restrict__ nbr, int32_t* __restrict__ ncnt,
@@ -522,11 +581,14 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(
     static_assert(64 % TB == 0, "lane groups must tile a wavefront");
     using G = typename GeoSel<D, real>::T;
     constexpr bool PREFILTER = sizeof(real) == 4;
-    if (gate && (!ctrl->rebuild || ctrl->err)) return;
-    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int i = gid / TB;
-    const int l = gid % TB;
-    if (i >= P.nf) return;  // whole lane groups leave together
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const KP<real>& P = Pt[tcase[b]];
+    Ctrl* ctrl = ctrl_all + P.case_id;
+    if (!full_update(ctrl, force) || ctrl->err) return;
+    const int i = b * TILE + (int)threadIdx.x / TB;
+    const int l = threadIdx.x % TB;
+    const int fend = P.fbase + P.nf, wend = P.wbase + P.nw;
+    if (i >= fend) return;  // whole lane groups leave together
     const int gbase = (int)(threadIdx.x & 63) & ~(TB - 1);
     const unsigned long long gmask = TB == 64 ? ~0ull : ((1ull << TB) - 1ull);
     const unsigned long long below = (1ull << l) - 1ull;
@@ -535,7 +597,7 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(
     const float Lm = (float)dmax(P.L[0], dmax(P.L[1], D == 3 ? P.L[2] : P.L[1]));
     const float margin = 8e-6f * Lm * Lm;
     const float rc2f = (float)P.rc2;
-    const int kc = cell[i];
+    const int kc = cell[i] - P.cbase;
     const int ci[3] = {kc % P.n[0], (kc / P.n[0]) % P.n[1], kc / (P.n[0] * P.n[1])};
     int cnt_[2] = {0, 0};
     uint32_t over = 0;
@@ -610,21 +672,19 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(
     const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
         int cz = ci[2] + dz;
-        bool zskip = false;
         if (D == 3) {
             if (P.periodic[2]) cz = cz < 0 ? cz + P.n[2] : (cz >= P.n[2] ? cz - P.n[2] : cz);
-            else zskip = cz < 0 || cz >= P.n[2];
+            else if (cz < 0 || cz >= P.n[2]) continue;
         }
         for (int dy = -1; dy <= 1; ++dy) {
             int cy = ci[1] + dy;
-            if (zskip) continue;
             if (P.periodic[1]) cy = cy < 0 ? cy + P.n[1] : (cy >= P.n[1] ? cy - P.n[1] : cy);
             else if (cy < 0 || cy >= P.n[1]) continue;
-            const int rowc = P.n[0] * (cy + P.n[1] * cz);
+            const int rowc = P.cbase + P.n[0] * (cy + P.n[1] * cz);
             const uint32_t tag_yz = ((uint32_t)(dy + 1) << 2) | ((uint32_t)(dz + 1) << 4);
             for (int body = 0; body < (P.nw > 0 ? 2 : 1); ++body) {
                 const int32_t* st_ = body ? wstart : fstart;
-                const int lim = body ? P.nw : P.nf;
+                const int lim = body ? wend : fend;
                 if (ci[0] >= 1 && ci[0] + 1 < P.n[0]) {
                     // the three cells are contiguous: one range
                     const int c = rowc + ci[0];
@@ -649,35 +709,19 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(
     if (over) atomicOr(&ctrl->err, ERR_NBR_OVERFLOW);
 }
 
-// Sum over the T lanes of a group (groups are aligned inside the wavefront).
-template <int T>
-__device__ __forceinline__ float group_sum(float v)
-{
-#pragma unroll
-    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-template <int T>
-__device__ __forceinline__ double group_sum(double v)
-{
-#pragma unroll
-    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // ---------------------------------------------------------------------
 // S5: the dual-criteria clock (Eqs. dt-advection, dt-relax).
 
 // Sub-step 0 of a new advection step (one thread): dt_ad from |v|max floored
 // at U_ref, clipped to the stop time, and the first acoustic step
-// min(dt_ac, dt_ad). Inactive when the clock has reached the stop time or an
-// error is pending.
+// min(dt_ac, dt_ad). Inactive when the clock has reached the stop time, the
+// step target is reached or an error is pending.
 template <typename real>
 __device__ void prepare_step(const KP<real>& P, Ctrl* __restrict__ ctrl)
 {
     SubState s0 = {0.0, 0.0, 0, 0, 0, 0};
     const double t = ctrl->t, t_stop = ctrl->t_stop, vmax = ctrl->vmax;
-    if (ctrl->err == 0 && t < t_stop) {
+    if (ctrl->err == 0 && t < t_stop && ctrl->steps_done < ctrl->steps_target) {
         double dt_ad = P.cfl_ad_h / fmax(vmax, P.u_ref);
         double t_end = t + dt_ad;
         if (t_end >= t_stop) {
@@ -696,6 +740,7 @@ __device__ void prepare_step(const KP<real>& P, Ctrl* __restrict__ ctrl)
     }
     ctrl->ss[0] = s0;
     ctrl->ss[1].active = 0;
+    ctrl->midstep = 0;
 }
 
 // The sub-step after S given |v|max of the state S produced: the clock
@@ -759,12 +804,15 @@ __device__ __forceinline__ double slot_max(const unsigned long long* __restrict_
     return wave_max(bits_speed<real>(vs[threadIdx.x & 63]));
 }
 
-// Start of the advection steps queued by one call (one thread).
+// Start of the advection steps queued by one call (one thread per case); a
+// case in the middle of an advection step keeps it.
 template <typename real>
-__global__ void k_adv_begin(KP<real> P, Ctrl* __restrict__ ctrl)
+__global__ void k_adv_begin(const KP<real>* __restrict__ Pt, Ctrl* __restrict__ ctrl_all, int ncases)
 {
-    ctrl->rebuild = 0;
-    prepare_step(P, ctrl);
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncases) return;
+    Ctrl* ctrl = ctrl_all + c;
+    if (!ctrl->midstep) prepare_step(Pt[c], ctrl);
 }
 
 // Visit the list entries k = l, l + T, ... < n of particle i in batches of
@@ -792,22 +840,33 @@ __device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int
     }
 }
 
+// Pair kernels: BLOCK threads, T lanes per particle, BLOCK / T <= TILE
+// particles per block, so a block lies inside one tile (one case).
+template <int T>
+__device__ __forceinline__ int pair_block_first(int b)
+{
+    static_assert(T >= BLOCK / TILE && T <= 64, "a pair-kernel block must lie inside one tile");
+    return b * (BLOCK / T);
+}
+
 // S4: density re-initialisation rho = max(rho*, rho0 sum W / sum W0) with
 // the sum over the particle itself, its fluid and its wall neighbours.
-// `gate`: run only at the start of an active advection step. T lanes share a
-// particle and split its neighbour list.
+// `gate`: only for cases starting an advection step in this queue. T lanes
+// share a particle and split its neighbour list.
 template <int D, typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_reinit(
-    KP<real> P, Ctrl* __restrict__ ctrl, int gate, const typename GeoSel<D, real>::T* __restrict__ geo,
-    const typename GeoSel<D, real>::T* __restrict__ wgeo, const uint32_t* __restrict__ nbr,
-    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
-    R4<real>* __restrict__ st)
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, const Ctrl* __restrict__ ctrl_all, int gate,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
+    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
+    const int32_t* __restrict__ wcnt, R4<real>* __restrict__ st)
 {
-    if (gate && (!ctrl->ss[0].active || ctrl->err)) return;
-    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int i = gid / T;
-    const int l = gid % T;
-    if (i >= P.nf) return;
+    const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
+    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    const Ctrl* ctrl = ctrl_all + P.case_id;
+    if (gate && (!ctrl->ss[0].active || ctrl->midstep || ctrl->err)) return;
+    const int i = i0 + (int)threadIdx.x / T;
+    const int l = threadIdx.x % T;
+    if (i >= P.fbase + P.nf) return;
     using G = typename GeoSel<D, real>::T;
     const G oi = geo[i];
     double sigma = 0.0;
@@ -836,20 +895,25 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
 // with shuffles and lane 0 writes.
 template <int D, typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_pressure(
-    KP<real> P, Ctrl* __restrict__ ctrl, const typename GeoSel<D, real>::T* __restrict__ geo,
-    const typename GeoSel<D, real>::T* __restrict__ wgeo, const typename GeoSel<D, real>::T* __restrict__ wnrm,
-    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
-    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, const real* __restrict__ dr3,
-    R4<real>* __restrict__ hf, real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot)
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
+    const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
+    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
+    const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
+    real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all)
 {
-    // Sub-step q: with `adv`, first close sub-step q - 1 (every block derives
-    // the same state from slot (q - 1) & 1 and the maxima of the last density
-    // relaxation; block 0 stores it in slot q & 1). Block 0 also clears the
-    // |v| slots the density relaxation of this sub-step will fill.
-    // While an error or a stall is pending nothing is written: the host
-    // finishes a stalled step from the preserved slots.
+    const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
+    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    Ctrl* ctrl = ctrl_all + P.case_id;
+    unsigned long long* vslot = vslot_all + (size_t)P.case_id * 2 * VSLOTS;
+    // Sub-step q: with `adv`, first close sub-step q - 1 (every block of the
+    // case derives the same state from slot (q - 1) & 1 and the maxima of
+    // the last density relaxation; the case's first block stores it in slot
+    // q & 1). That block also clears the |v| slots the density relaxation of
+    // this sub-step will fill and, at the head of a queue, the update flag.
+    // With an error pending no sub-step state is written.
     const uint32_t err = ctrl->err;
-    const bool leader = blockIdx.x == 0 && threadIdx.x == 0 && !err;
+    const bool first = i0 == P.fbase;
     SubState S;
     if (adv) {
         const SubState Sp = ctrl->ss[(q - 1) & 1];
@@ -857,22 +921,21 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
             const double vmax = slot_max<real>(vslot + ((q - 1) & 1) * VSLOTS);
             bool finished;
             S = next_substep(P, ctrl->dt_ad, Sp, vmax, finished);
-            if (leader) close_substep(ctrl, q & 1, S, vmax, finished);
+            if (first && threadIdx.x == 0) close_substep(ctrl, q & 1, S, vmax, finished);
         } else {
             S = Sp;
             S.active = 0;
-            if (leader) ctrl->ss[q & 1] = S;
+            if (first && threadIdx.x == 0 && !err) ctrl->ss[q & 1] = S;
         }
     } else {
         S = ctrl->ss[q & 1];
-        if (leader) ctrl->rebuild = 0;  // a new advection step
+        if (first && threadIdx.x == 0) ctrl->rebuild = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x < VSLOTS) vslot[(q & 1) * VSLOTS + threadIdx.x] = 0ull;
+    if (first && threadIdx.x < VSLOTS) vslot[(q & 1) * VSLOTS + threadIdx.x] = 0ull;
     if (!S.active || err) return;
-    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int i = gid / T;
-    const int l = gid % T;
-    if (i >= P.nf) return;
+    const int i = i0 + (int)threadIdx.x / T;
+    const int l = threadIdx.x % T;
+    if (i >= P.fbase + P.nf) return;
     using G = typename GeoSel<D, real>::T;
     const real dt = (real)S.dt;
     const real half = (real)0.5 * dt;
@@ -903,20 +966,20 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
             return r;
         },
         [&](uint32_t e, const FluidJ& r) {
-            Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+            Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const R4<real>& sj = r.s;
             real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * r.dr;
-            real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
-            real UR = sj.x * q.e[0] + sj.y * q.e[1] + (D == 3 ? sj.z * q.e[2] : (real)0);
+            real UL = vi[0] * pq.e[0] + vi[1] * pq.e[1] + (D == 3 ? vi[2] * pq.e[2] : (real)0);
+            real UR = sj.x * pq.e[0] + sj.y * pq.e[1] + (D == 3 ? sj.z * pq.e[2] : (real)0);
             real rho_j = P.rho0 + dev_j;
             real p_j = P.c2 * dev_j;
             real du = UL - UR;
             real beta = dmin((real)3 * dmax(du, (real)0), P.c);
             real ps = (real)0.5 * (p_i + p_j) + (real)0.25 * beta * (rho_i + rho_j) * du;
-            real coef = P.two_m * ps * inv_rho_i / rho_j * q.dW;
-            acc[0] += coef * q.e[0];
-            acc[1] += coef * q.e[1];
-            if (D == 3) acc[2] += coef * q.e[2];
+            real coef = P.two_m * ps * inv_rho_i / rho_j * pq.dW;
+            acc[0] += coef * pq.e[0];
+            acc[1] += coef * pq.e[1];
+            if (D == 3) acc[2] += coef * pq.e[2];
         });
     for_pairs<T, BATCH>(
         wnb, i, wcnt[i], P.maxw, l,
@@ -928,19 +991,19 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
             return r;
         },
         [&](uint32_t e, const WallJ& r) {
-            Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+            Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const G& nw = r.n;
             real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
             real du = (real)2 * UL;  // U_R = -U_L for a static wall
-            real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
+            real gr = pq.r * (P.g[0] * pq.e[0] + P.g[1] * pq.e[1] + (D == 3 ? P.g[2] * pq.e[2] : (real)0));
             real pR = p_i + rho_i * gr;
             real rhoR = P.rho0 + pR * P.inv_c2;
             real beta = dmin((real)3 * dmax(du, (real)0), P.c);
             real ps = (real)0.5 * (p_i + pR) + (real)0.25 * beta * (rho_i + rhoR) * du;
-            real coef = P.two_vw * ps * inv_rho_i * q.dW;
-            acc[0] += coef * q.e[0];
-            acc[1] += coef * q.e[1];
-            if (D == 3) acc[2] += coef * q.e[2];
+            real coef = P.two_vw * ps * inv_rho_i * pq.dW;
+            acc[0] += coef * pq.e[0];
+            acc[1] += coef * pq.e[1];
+            if (D == 3) acc[2] += coef * pq.e[2];
         });
     acc[0] = group_sum<T>(acc[0]);
     acc[1] = group_sum<T>(acc[1]);
@@ -971,17 +1034,22 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
 // S7: density relaxation. Riemann continuity equation with fluid and wall
 // neighbours using v^{n+1}, second Verlet half-steps of position (both
 // position half-steps land here, in the paper's order) and density, and the
-// |v|max reduction for the next acoustic step; the last block to finish
-// advances the sub-step clock (S5). T lanes share a particle as in S6.
+// block maxima of |v| for the next acoustic step. T lanes share a particle
+// as in S6.
 template <int D, typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_density(
-    KP<real> P, Ctrl* __restrict__ ctrl, int finalize, const typename GeoSel<D, real>::T* __restrict__ geo,
-    const typename GeoSel<D, real>::T* __restrict__ wgeo, const typename GeoSel<D, real>::T* __restrict__ wnrm,
-    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
-    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ hf, R4<real>* __restrict__ st,
-    real* __restrict__ dr3, double* __restrict__ x0, double* __restrict__ x1, double* __restrict__ x2,
-    real* __restrict__ drho_out, unsigned long long* __restrict__ vslot, int q)
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int finalize,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
+    const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
+    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
+    const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
+    double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
+    unsigned long long* __restrict__ vslot_all, int q)
 {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = pair_block_first<T>(b);
+    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    Ctrl* ctrl = ctrl_all + P.case_id;
     const SubState S = ctrl->ss[q & 1];
     if (!S.active || ctrl->err) return;
     __shared__ double smax[BLOCK / 64];
@@ -989,12 +1057,11 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const double dtd = S.dt;
     const real dt = (real)dtd;
     const real half = (real)0.5 * dt;
-    const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int i = gid / T;
-    const int l = gid % T;
+    const int i = i0 + (int)threadIdx.x / T;
+    const int l = threadIdx.x % T;
     real speed = 0;
     uint32_t bad = 0;
-    if (i < P.nf) {
+    if (i < P.fbase + P.nf) {
         const R4<real> hi_ = hf[i];
         real vi[3];
         vi[0] = hi_.x; vi[1] = hi_.y;
@@ -1016,17 +1083,17 @@ __global__ __launch_bounds__(BLOCK) void k_density(
                 return r;
             },
             [&](uint32_t e, const HalfJ& r) {
-                Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+                Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
                 const R4<real>& hj = r.h;
                 real dev_j = D == 2 ? hj.z : hj.w;
-                real UL = vi[0] * q.e[0] + vi[1] * q.e[1] + (D == 3 ? vi[2] * q.e[2] : (real)0);
-                real UR = hj.x * q.e[0] + hj.y * q.e[1] + (D == 3 ? hj.z * q.e[2] : (real)0);
+                real UL = vi[0] * pq.e[0] + vi[1] * pq.e[1] + (D == 3 ? vi[2] * pq.e[2] : (real)0);
+                real UR = hj.x * pq.e[0] + hj.y * pq.e[1] + (D == 3 ? hj.z * pq.e[2] : (real)0);
                 real rho_j = P.rho0 + dev_j;
                 real p_j = P.c2 * dev_j;
                 real inv_rho_j = (real)1 / rho_j;
                 real rho_bar = (real)0.5 * (rho_i + rho_j);
                 real us = (real)0.5 * (UL + UR) + (p_i - p_j) * P.half_inv_c / rho_bar;
-                sum += P.m * inv_rho_j * (us - UL) * q.dW;
+                sum += P.m * inv_rho_j * (us - UL) * pq.dW;
             });
         for_pairs<T, BATCH>(
             wnb, i, wcnt[i], P.maxw, l,
@@ -1038,15 +1105,15 @@ __global__ __launch_bounds__(BLOCK) void k_density(
                 return r;
             },
             [&](uint32_t e, const WallJ& r) {
-                Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+                Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
                 const G& nw = r.n;
                 real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
-                real gr = q.r * (P.g[0] * q.e[0] + P.g[1] * q.e[1] + (D == 3 ? P.g[2] * q.e[2] : (real)0));
+                real gr = pq.r * (P.g[0] * pq.e[0] + P.g[1] * pq.e[1] + (D == 3 ? P.g[2] * pq.e[2] : (real)0));
                 real pR = p_i + rho_i * gr;
                 real rhoR = P.rho0 + pR * P.inv_c2;
                 real rho_bar = (real)0.5 * (rho_i + rhoR);
                 real us = (p_i - pR) * P.half_inv_c / rho_bar;  // (U_L + U_R)/2 = 0
-                sum += P.vw * (us - UL) * q.dW;
+                sum += P.vw * (us - UL) * pq.dW;
             });
         sum = group_sum<T>(sum);
         if (l == 0) {
@@ -1078,85 +1145,104 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     }
     if (bad) atomicOr(&ctrl->err_pending, bad);
     if (!finalize) return;
-    // block maximum of |v^{n+1}| into the slots of this sub-step, read by the
-    // next pressure relaxation or the step end (no cross-block signalling
-    // here: a device-wide fence per block would write back L2)
+    // block maximum of |v^{n+1}| into the case's slots of this sub-step,
+    // read by the next pressure relaxation or the step end (no cross-block
+    // signalling here: a device-wide fence per block would write back L2)
     double m = wave_max((double)speed);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) smax[wid] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         double bm = smax[0];
-        for (int q = 1; q < BLOCK / 64; ++q) bm = fmax(bm, smax[q]);
+        for (int w = 1; w < BLOCK / 64; ++w) bm = fmax(bm, smax[w]);
         // relaxed, result unused: no wait, no fence; read after the kernel ends
-        atomicMax(&vslot[(q & 1) * VSLOTS + (blockIdx.x & (VSLOTS - 1))], speed_bits((real)bm));
+        unsigned long long* vslot = vslot_all + (size_t)P.case_id * 2 * VSLOTS;
+        atomicMax(&vslot[(q & 1) * VSLOTS + (b & (VSLOTS - 1))], speed_bits((real)bm));
     }
 }
 
-// S5 after the last queued density relaxation (one wavefront): close
-// sub-step q; if the advection step is not covered, flag a stall (`stall`)
-// for the host to finish it; clear both |v| slot sets; with `prepare`,
-// prepare sub-step 0 of the next advection step.
+// S5 after the last queued density relaxation (one wavefront per case):
+// close sub-step q. If the advection step is covered (or was covered
+// earlier in the queue) prepare the next one; otherwise the step continues
+// at the head of the next queue, its next sub-step stored in slot 0.
+// Clears the case's |v| slots.
 template <typename real>
-__global__ __launch_bounds__(64) void k_step_end(KP<real> P, Ctrl* __restrict__ ctrl,
-                                                 unsigned long long* __restrict__ vslot, int q, int prepare,
-                                                 int stall)
+__global__ __launch_bounds__(64) void k_step_end(const KP<real>* __restrict__ Pt, Ctrl* __restrict__ ctrl_all,
+                                                 unsigned long long* __restrict__ vslot_all, int q)
 {
-    const SubState Sp = ctrl->ss[q & 1];
+    const KP<real>& P = Pt[blockIdx.x];
+    Ctrl* ctrl = ctrl_all + blockIdx.x;
+    unsigned long long* vslot = vslot_all + (size_t)blockIdx.x * 2 * VSLOTS;
+    const SubState Sp = ctrl->ss[q & 1];  // read by the whole wavefront before lane 0 writes
     const uint32_t err = ctrl->err;
-    bool stalled = false;
+    bool cont = false;
     if (Sp.active && !err) {
         const double vmax = slot_max<real>(vslot + (q & 1) * VSLOTS);
         bool finished;
         SubState n = next_substep(P, ctrl->dt_ad, Sp, vmax, finished);
-        stalled = !finished && stall;
-        if (threadIdx.x == 0) {
-            close_substep(ctrl, (q + 1) & 1, n, vmax, finished);
-            if (stalled) ctrl->err |= ERR_STALL;
-        }
+        cont = !finished;
+        if (threadIdx.x == 0) close_substep(ctrl, 0, n, vmax, finished);
     }
     vslot[threadIdx.x] = 0ull;
     vslot[VSLOTS + threadIdx.x] = 0ull;
-    // with an error or a stall pending the slots are left for the host
-    if (threadIdx.x == 0 && prepare && !stalled && !err && ctrl->err == 0) prepare_step(P, ctrl);
+    if (threadIdx.x != 0 || err || ctrl->err) return;
+    if (cont) {
+        ctrl->ss[1].active = 0;
+        ctrl->midstep = 1;
+    } else {
+        prepare_step(P, ctrl);
+    }
 }
 
 // ---------------------------------------------------------------------
-// |v|max of the current state (outside the time loop).
+// |v|max of the current state of every case (only < 0) or of case `only`
+// (outside the time loop; one thread per slot).
 template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_vmax(KP<real> P, Ctrl* __restrict__ ctrl, const R4<real>* __restrict__ st)
+__global__ __launch_bounds__(BLOCK) void k_vmax(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
+                                                int ntiles, int only, Ctrl* __restrict__ ctrl_all,
+                                                const R4<real>* __restrict__ st)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tile = wave_tile();
+    if (tile >= ntiles) return;
+    const KP<real>& P = Pt[tcase[tile]];
+    if (only >= 0 && P.case_id != only) return;
+    const int i = tile * TILE + (threadIdx.x & 63);
     real sp = 0;
-    if (i < P.nf) {
+    if (i < P.fbase + P.nf) {
         R4<real> s = st[i];
         sp = D == 2 ? sqrt(s.x * s.x + s.y * s.y) : sqrt(s.x * s.x + s.y * s.y + s.z * s.z);
     }
     double m = wave_max((double)sp);
-    if ((threadIdx.x & 63) == 0) atomicMax(&ctrl->vmax_bits, speed_bits((real)m));
+    if ((threadIdx.x & 63) == 0) atomicMax(&ctrl_all[P.case_id].vmax_bits, speed_bits((real)m));
 }
 
 template <typename real>
-__global__ void k_vmax_fin(Ctrl* __restrict__ ctrl)
+__global__ void k_vmax_fin(Ctrl* __restrict__ ctrl_all, int ncases, int only)
 {
-    ctrl->vmax = bits_speed<real>(ctrl->vmax_bits);
-    ctrl->vmax_bits = 0ull;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncases || (only >= 0 && c != only)) return;
+    ctrl_all[c].vmax = bits_speed<real>(ctrl_all[c].vmax_bits);
+    ctrl_all[c].vmax_bits = 0ull;
 }
 
 // ---------------------------------------------------------------------
-// S8: FP64 diagnostics. Per block partial sums; k_diag_fin reduces them in a
-// fixed order so the result is deterministic.
+// S8: FP64 diagnostics. Per tile partial sums; k_diag_fin reduces each
+// case's tiles in a fixed order so the result is deterministic.
 constexpr int NDIAG = 8;  // mom0..2, e_kin, e_pot, e_int, front (max), max |dev|/rho0 (max)
 
 template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_diag(KP<real> P, const double* __restrict__ x0, const double* __restrict__ x1,
-                                                const double* __restrict__ x2, const R4<real>* __restrict__ st,
-                                                double* __restrict__ part)
+__global__ __launch_bounds__(BLOCK) void k_diag(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
+                                                int ntiles, const double* __restrict__ x0,
+                                                const double* __restrict__ x1, const double* __restrict__ x2,
+                                                const R4<real>* __restrict__ st, double* __restrict__ part)
 {
-    __shared__ double sh[NDIAG][BLOCK / 64];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tile = wave_tile();
+    if (tile >= ntiles) return;
+    const KP<real>& P = Pt[tcase[tile]];
+    const int lane = threadIdx.x & 63;
+    const int i = tile * TILE + lane;
     double v[NDIAG] = {0, 0, 0, 0, 0, 0, -1e300, 0};
-    if (i < P.nf) {
+    if (i < P.fbase + P.nf) {
         R4<real> s = st[i];
         double m = P.md;
         double vel[3] = {(double)s.x, (double)s.y, D == 3 ? (double)s.z : 0.0};
@@ -1172,33 +1258,29 @@ __global__ __launch_bounds__(BLOCK) void k_diag(KP<real> P, const double* __rest
         v[6] = x[0];
         v[7] = fabs(a);
     }
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NDIAG; ++q) {
         double r = (q == 6 || q == 7) ? wave_max(v[q]) : wave_sum(v[q]);
-        if (lane == 0) sh[q][wid] = r;
-    }
-    __syncthreads();
-    if (threadIdx.x < NDIAG) {
-        int q = threadIdx.x;
-        double r = sh[q][0];
-        for (int w = 1; w < BLOCK / 64; ++w) r = (q == 6 || q == 7) ? fmax(r, sh[q][w]) : r + sh[q][w];
-        part[(size_t)blockIdx.x * NDIAG + q] = r;
+        if (lane == 0) part[(size_t)tile * NDIAG + q] = r;
     }
 }
 
-// One block, fixed reduction order (strided partials, then shuffle trees),
-// so the result does not depend on timing.
-__global__ __launch_bounds__(BLOCK) void k_diag_fin(const double* __restrict__ part, int nb, double* __restrict__ out)
+// One block per case, fixed reduction order (strided partials, then
+// shuffle trees), so the result does not depend on timing.
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_diag_fin(const KP<real>* __restrict__ Pt, const double* __restrict__ part,
+                                                    double* __restrict__ out)
 {
+    const KP<real>& P = Pt[blockIdx.x];
+    const int t0 = P.fbase / TILE, nt = P.fcap / TILE;
     __shared__ double sh[NDIAG][BLOCK / 64];
     double v[NDIAG];
 #pragma unroll
     for (int q = 0; q < NDIAG; ++q) v[q] = q == 6 ? -1e300 : 0.0;
-    for (int b = threadIdx.x; b < nb; b += BLOCK)
+    for (int b = threadIdx.x; b < nt; b += BLOCK)
 #pragma unroll
         for (int q = 0; q < NDIAG; ++q) {
-            double x = part[(size_t)b * NDIAG + q];
+            double x = part[(size_t)(t0 + b) * NDIAG + q];
             v[q] = (q == 6 || q == 7) ? fmax(v[q], x) : v[q] + x;
         }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1212,21 +1294,24 @@ __global__ __launch_bounds__(BLOCK) void k_diag_fin(const double* __restrict__ p
         int q = threadIdx.x;
         double r = sh[q][0];
         for (int w = 1; w < BLOCK / 64; ++w) r = (q == 6 || q == 7) ? fmax(r, sh[q][w]) : r + sh[q][w];
-        out[q] = r;
+        out[(size_t)blockIdx.x * NDIAG + q] = r;
     }
 }
 
 // ---------------------------------------------------------------------
-// Output helpers: fields back to original id order, as FP64.
+// Output helpers: one case's field back to its original order, as FP64.
 template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_unsort_field(KP<real> P, int which, const int32_t* __restrict__ id,
-                                                        const double* __restrict__ x0, const double* __restrict__ x1,
-                                                        const double* __restrict__ x2, const R4<real>* __restrict__ st,
-                                                        const real* __restrict__ dr3, double* __restrict__ out)
+__global__ __launch_bounds__(BLOCK) void k_unsort_field(const KP<real>* __restrict__ Pt, int c, int which,
+                                                        const int32_t* __restrict__ id, const double* __restrict__ x0,
+                                                        const double* __restrict__ x1, const double* __restrict__ x2,
+                                                        const R4<real>* __restrict__ st, const real* __restrict__ dr3,
+                                                        double* __restrict__ out)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P.nf) return;
-    int o = id[i];
+    const KP<real>& P = Pt[c];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.nf) return;
+    const int i = P.fbase + k;
+    const int o = id[i];
     R4<real> s = st[i];
     double dev = D == 2 ? (double)s.z : (double)s.w;
     switch (which) {
@@ -1248,34 +1333,38 @@ __global__ __launch_bounds__(BLOCK) void k_unsort_field(KP<real> P, int which, c
 }
 
 template <typename real>
-__global__ __launch_bounds__(BLOCK) void k_unsort_vec(int n, int width, const int32_t* __restrict__ id,
+__global__ __launch_bounds__(BLOCK) void k_unsort_vec(int base, int n, int width, const int32_t* __restrict__ id,
                                                       const real* __restrict__ in, double* __restrict__ out)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int o = id[i];
-    for (int k = 0; k < width; ++k) out[(size_t)o * width + k] = (double)in[(size_t)i * width + k];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int i = base + k;
+    const int o = id[i];
+    for (int w = 0; w < width; ++w) out[(size_t)o * width + w] = (double)in[(size_t)i * width + w];
 }
 
-// Load particles given in original order into the (unsorted) state set.
+// Load one case's particles, given in original order, into its slots.
 template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_load_fluid(KP<real> P, const double* __restrict__ pos,
-                                                      const double* __restrict__ vel, const double* __restrict__ rho,
-                                                      const double* __restrict__ drho, double* __restrict__ x0,
-                                                      double* __restrict__ x1, double* __restrict__ x2,
-                                                      R4<real>* __restrict__ st, real* __restrict__ dr3,
-                                                      int32_t* __restrict__ id)
+__global__ __launch_bounds__(BLOCK) void k_load_fluid(const KP<real>* __restrict__ Pt, int c,
+                                                      const double* __restrict__ pos, const double* __restrict__ vel,
+                                                      const double* __restrict__ rho, const double* __restrict__ drho,
+                                                      double* __restrict__ x0, double* __restrict__ x1,
+                                                      double* __restrict__ x2, R4<real>* __restrict__ st,
+                                                      real* __restrict__ dr3, int32_t* __restrict__ id,
+                                                      int32_t* __restrict__ cell)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P.nf) return;
-    x0[i] = pos[(size_t)i * D + 0];
-    x1[i] = pos[(size_t)i * D + 1];
-    if (D == 3) x2[i] = pos[(size_t)i * D + 2];
+    const KP<real>& P = Pt[c];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.nf) return;
+    const int i = P.fbase + k;
+    x0[i] = pos[(size_t)k * D + 0];
+    x1[i] = pos[(size_t)k * D + 1];
+    if (D == 3) x2[i] = pos[(size_t)k * D + 2];
     double v[3] = {0, 0, 0};
     if (vel)
-        for (int k = 0; k < D; ++k) v[k] = vel[(size_t)i * D + k];
-    double dev = rho ? rho[i] - P.rho0d : 0.0;
-    double dr = drho ? drho[i] : 0.0;
+        for (int a = 0; a < D; ++a) v[a] = vel[(size_t)k * D + a];
+    double dev = rho ? rho[k] - P.rho0d : 0.0;
+    double dr = drho ? drho[k] : 0.0;
     R4<real> s;
     s.x = (real)v[0];
     s.y = (real)v[1];
@@ -1288,7 +1377,8 @@ __global__ __launch_bounds__(BLOCK) void k_load_fluid(KP<real> P, const double* 
         dr3[i] = (real)dr;
     }
     st[i] = s;
-    id[i] = i;
+    id[i] = k;
+    cell[i] = P.cbase;  // replaced by the next (full) binning
 }
 
 }  // namespace sphx

@@ -1,8 +1,8 @@
 // sphx_runtime.hip -- host runtime of the MI355X Riemann-WCSPH library:
-// context, device buffers, HIP-graph capture of the advection step and the
-// C ABI declared in include/sphx.h. All particle arithmetic runs in the
-// kernels of sphx_device.hpp; the host only sizes buffers, launches,
-// captures graphs and marshals arrays in and out.
+// context, batch layout of the cases, device buffers, HIP-graph capture of
+// the advection step and the C ABI declared in include/sphx.h. All particle
+// arithmetic runs in the kernels of sphx_device.hpp; the host only sizes
+// buffers, launches, captures graphs and marshals arrays in and out.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +21,7 @@ using namespace sphx;
 struct EngineBase;
 
 struct sphx_ctx {
-    sphx_params prm;
+    std::vector<sphx_params> prm;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
@@ -50,34 +50,44 @@ struct sphx_ctx {
 struct EngineBase {
     virtual ~EngineBase() {}
     virtual int init() = 0;
-    virtual int set_fluid(int64_t n, const double* pos, const double* vel, const double* rho, const double* drho) = 0;
-    virtual int set_walls(int64_t n, const double* pos, const double* nrm) = 0;
+    virtual int ncases() const = 0;
+    virtual int set_fluid(int c, int64_t n, const double* pos, const double* vel, const double* rho,
+                          const double* drho) = 0;
+    virtual int set_walls(int c, int64_t n, const double* pos, const double* nrm) = 0;
     virtual int build_neighbors() = 0;
-    virtual int get_neighbors(int kind, int64_t* off, int64_t* idx, int64_t cap, int64_t* n_out) = 0;
+    virtual int get_neighbors(int c, int kind, int64_t* off, int64_t* idx, int64_t cap, int64_t* n_out) = 0;
     virtual int density_reinit() = 0;
-    virtual int time_steps(double* dt_ad, double* dt_ac) = 0;
-    virtual int compute_rates(double dt, double* dvdt, double* drhodt) = 0;
+    virtual int time_steps(int c, double* dt_ad, double* dt_ac) = 0;
+    virtual int compute_rates(int c, double dt, double* dvdt, double* drhodt) = 0;
     virtual int advance(int32_t n_steps, double t_stop, int64_t* nsub, double* t_out) = 0;
-    virtual int get_field(int which, double* out) = 0;
-    virtual int diagnostics(sphx_diag* out) = 0;
+    virtual int case_status(int c) = 0;
+    virtual int get_field(int c, int which, double* out) = 0;
+    virtual int diagnostics(int c, sphx_diag* out) = 0;
     virtual int profile(int32_t reps, double* ms) = 0;
-    virtual int counts(int64_t* out) = 0;
+    virtual int counts(int c, int64_t* out) = 0;
+    virtual int autotune(int32_t reps, int32_t* lanes) = 0;
 };
 
 static inline int nblk(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
+static inline int round_tile(long long n) { return (int)((n + TILE - 1) / TILE * TILE); }
 
 template <int D, typename real>
 struct Engine final : EngineBase {
     using G = typename GeoSel<D, real>::T;
     sphx_ctx* ctx;
     hipStream_t s;
-    KP<real> P{};
-    static constexpr int LN = D == 2 ? 4 : 8;   // lanes per particle in the pair kernels
-    static constexpr int LB = 4;  // lanes per particle in the neighbour build (measured best of 1-64)
-    int ncell = 0, nsub_q = 5, steps_per_graph = 2;
+    static constexpr int LB = 4;  // lanes per particle in the neighbour build (one tile per block)
+    int ln = D == 2 ? 4 : 8;      // lanes per particle in the pair kernels (4 or 8)
+    int C = 0;                    // cases
+    std::vector<KP<real>> hP;     // parameter table (host copy)
+    KP<real>* dP = nullptr;
+    int32_t* tcase = nullptr;     // case of every tile
+    int ntiles = 0, ntot = 0;     // tiles and fluid slots of the layout
+    int ncell = 0;                // cells of all cases, padding cells included
+    int nsub_q = 5, steps_per_graph = 2;
     int maxn = 0, maxw = 0;
-    // fluid: two state sets (current and gather target)
-    int nf = 0, cap = 0;
+    bool laid_out = false;
+    // fluid: two state sets (current and placement target)
     double* x[2][3] = {};
     R4<real>* st[2] = {};
     real* dr3[2] = {};
@@ -93,18 +103,19 @@ struct Engine final : EngineBase {
     int32_t *cnt = nullptr, *fstart = nullptr, *bsum = nullptr;
     real* acc_out = nullptr;
     real* drho_out = nullptr;
-    unsigned long long* vslot = nullptr;  // |v| maxima slots of the density relaxation (zero between uses)
     double* outbuf = nullptr;
     double* stage = nullptr;
     size_t stage_n = 0;
     double* diag_part = nullptr;
     double* diag_out = nullptr;
+    unsigned long long* vslot = nullptr;  // |v| maxima slots per case (zero between uses)
     // state backup for calls that must leave the state unchanged
     R4<real>* bk_st = nullptr;
     real* bk_dr = nullptr;
     double* bk_x[3] = {};
-    // walls
-    int nw = 0, wcap = 0;
+    // walls (static), all cases concatenated
+    int nw_tot = 0;
+    std::vector<std::vector<double>> wpos_h, wnrm_h;  // per case, as given
     double* wx[3] = {};
     G* wgeo = nullptr;
     G* wnrm = nullptr;
@@ -114,27 +125,25 @@ struct Engine final : EngineBase {
     Ctrl* ctrl = nullptr;
     Ctrl* hctrl = nullptr;  // pinned mirror
     int cur = 0;
-    long long cur_steps = 0;
     bool configured = false;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // steps_per_graph steps, by start parity
-    hipGraphExec_t gone[2] = {nullptr, nullptr};    // one step, by start parity
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // steps_per_graph queues, by start parity
+    hipGraphExec_t gone[2] = {nullptr, nullptr};   // one queue, by start parity
     std::vector<void*> fluid_allocs, wall_allocs;
 
-    explicit Engine(sphx_ctx* c) : ctx(c), s(c->stream) {}
+    Engine(sphx_ctx* c, int ncase) : ctx(c), s(c->stream), C(ncase) {}
 
     ~Engine() override
     {
         drop_graphs();
         free_list(fluid_allocs);
         free_list(wall_allocs);
-        (void)hipFree(ctrl);
-        (void)hipFree(cnt);
-        (void)hipFree(fstart);
-        (void)hipFree(bsum);
-        (void)hipFree(wstart);
-        (void)hipFree(diag_out);
+        for (void* p : {(void*)ctrl, (void*)cnt, (void*)fstart, (void*)bsum, (void*)wstart, (void*)diag_out,
+                        (void*)dP, (void*)vslot, (void*)stage})
+            (void)hipFree(p);
         if (hctrl) (void)hipHostFree(hctrl);
     }
+
+    int ncases() const override { return C; }
 
     static void free_list(std::vector<void*>& v)
     {
@@ -162,10 +171,14 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
+    std::string case_tag(int c) const { return C > 1 ? "case " + std::to_string(c) + ": " : std::string(); }
+
     // ------------------------------------------------------------------
-    int init() override
+    int init_case(int c, int cbase)
     {
-        const sphx_params& q = ctx->prm;
+        const sphx_params& q = ctx->prm[c];
+        KP<real>& P = hP[c];
+        P = KP<real>{};
         const double PI = 3.14159265358979323846;
         double alpha = D == 2 ? 7.0 / (4.0 * PI) : 21.0 / (16.0 * PI);
         double h = q.h;
@@ -187,17 +200,17 @@ struct Engine final : EngineBase {
         P.dWc = (real)(-5.0 * alpha / std::pow(h, D + 1));
         for (int k = 0; k < 3; ++k) P.g[k] = (real)(k < D ? q.gravity[k] : 0.0);
         double rc = 2.0 * h;
-        ncell = 1;
+        long long nc = 1;
         for (int k = 0; k < 3; ++k) {
             if (k < D) {
                 double len = q.hi[k] - q.lo[k];
-                if (!(len > 0)) return ctx->fail(SPHX_EINVAL, "empty domain box");
+                if (!(len > 0)) return ctx->fail(SPHX_EINVAL, case_tag(c) + "empty domain box");
                 long long n = (long long)std::floor(len / rc);
                 while (n > 1 && len / (double)n < rc) --n;
                 if (n < 1) n = 1;
-                if (n > 100000) return ctx->fail(SPHX_EINVAL, "cell grid too large");
+                if (n > 100000) return ctx->fail(SPHX_EINVAL, case_tag(c) + "cell grid too large");
                 if (q.periodic[k] && n < 3)
-                    return ctx->fail(SPHX_EINVAL, "a periodic axis needs at least 3 cells of size 2h");
+                    return ctx->fail(SPHX_EINVAL, case_tag(c) + "a periodic axis needs at least 3 cells of size 2h");
                 P.n[k] = (int)n;
                 P.Ld[k] = len / (double)n;
                 P.lo[k] = q.lo[k];
@@ -215,9 +228,10 @@ struct Engine final : EngineBase {
                 P.periodic[k] = 0;
             }
             P.L[k] = (real)P.Ld[k];
-            ncell *= P.n[k];
+            nc *= P.n[k];
         }
-        if ((long long)P.n[0] * P.n[1] * P.n[2] > 50000000LL) return ctx->fail(SPHX_EINVAL, "cell grid too large");
+        if (nc > 50000000LL || (long long)cbase + nc + 1 > 200000000LL)
+            return ctx->fail(SPHX_EINVAL, case_tag(c) + "cell grid too large");
         P.rc2 = (2.0 * h) * (2.0 * h);
         if (q.sigma0 > 0) {
             P.sigma0 = q.sigma0;
@@ -227,8 +241,8 @@ struct Engine final : EngineBase {
             double sum = 0.0;
             for (int a = -K; a <= K; ++a)
                 for (int b = -K; b <= K; ++b)
-                    for (int c = (D == 3 ? -K : 0); c <= (D == 3 ? K : 0); ++c) {
-                        double r = q.dp * std::sqrt((double)(a * a + b * b + c * c));
+                    for (int cc = (D == 3 ? -K : 0); cc <= (D == 3 ? K : 0); ++cc) {
+                        double r = q.dp * std::sqrt((double)(a * a + b * b + cc * cc));
                         double qq = r / h;
                         if (qq < 2.0) {
                             double sq = 1.0 - 0.5 * qq;
@@ -240,38 +254,69 @@ struct Engine final : EngineBase {
         P.cfl_ad_h = q.cfl_ad * h;
         P.cfl_ac_h = q.cfl_ac * h;
         P.u_ref = q.u_ref;
-        maxn = D == 2 ? 48 : 128;
-        maxw = D == 2 ? 32 : 96;
         P.maxn = maxn;
         P.maxw = maxw;
-        nsub_q = q.nsub_queue > 0 ? q.nsub_queue : 5;
+        P.case_id = c;
+        P.cbase = cbase;
+        P.ncell = (int)nc;
+        return SPHX_OK;
+    }
+
+    int init() override
+    {
+        maxn = D == 2 ? 48 : 128;
+        maxw = D == 2 ? 32 : 96;
+        hP.resize(C);
+        wpos_h.assign(C, {});
+        wnrm_h.assign(C, {});
+        int cbase = 0;
+        for (int c = 0; c < C; ++c) {
+            RETCHK(init_case(c, cbase));
+            cbase += hP[c].ncell + 1;  // + padding cell
+        }
+        ncell = cbase;
+        nsub_q = ctx->prm[0].nsub_queue > 0 ? ctx->prm[0].nsub_queue : 5;
         if (nsub_q > 64) nsub_q = 64;
-        HIPCHK(hipMalloc((void**)&ctrl, sizeof(Ctrl)));
-        HIPCHK(hipHostMalloc((void**)&hctrl, sizeof(Ctrl), hipHostMallocDefault));
-        std::memset(hctrl, 0, sizeof(Ctrl));
-        HIPCHK(hipMemcpyAsync(ctrl, hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMalloc((void**)&ctrl, sizeof(Ctrl) * C));
+        HIPCHK(hipHostMalloc((void**)&hctrl, sizeof(Ctrl) * C, hipHostMallocDefault));
+        std::memset(hctrl, 0, sizeof(Ctrl) * C);
+        HIPCHK(hipMemcpyAsync(ctrl, hctrl, sizeof(Ctrl) * C, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMalloc((void**)&dP, sizeof(KP<real>) * C));
+        HIPCHK(hipMalloc((void**)&vslot, sizeof(unsigned long long) * 2 * VSLOTS * C));
+        HIPCHK(hipMemsetAsync(vslot, 0, sizeof(unsigned long long) * 2 * VSLOTS * C, s));
         HIPCHK(hipMalloc((void**)&cnt, sizeof(int32_t) * (size_t)ncell));
         HIPCHK(hipMalloc((void**)&fstart, sizeof(int32_t) * ((size_t)ncell + 1)));
         HIPCHK(hipMalloc((void**)&wstart, sizeof(int32_t) * ((size_t)ncell + 1)));
         HIPCHK(hipMalloc((void**)&bsum, sizeof(int32_t) * ((size_t)nblk_scan() + 1)));
-        HIPCHK(hipMalloc((void**)&diag_out, sizeof(double) * NDIAG));
+        HIPCHK(hipMalloc((void**)&diag_out, sizeof(double) * NDIAG * C));
         HIPCHK(hipMemsetAsync(wstart, 0, sizeof(int32_t) * ((size_t)ncell + 1), s));
         HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));
+        RETCHK(upload_params());
         HIPCHK(hipStreamSynchronize(s));
-        P.nf = 0;
-        P.nw = 0;
         return SPHX_OK;
     }
 
     int nblk_scan() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
+    int pair_blocks() const { return (int)((long long)ntot * ln / BLOCK); }
+
+    int upload_params()
+    {
+        HIPCHK(hipMemcpyAsync(dP, hP.data(), sizeof(KP<real>) * C, hipMemcpyHostToDevice, s));
+        return SPHX_OK;
+    }
 
     int sync_ctrl()
     {
-        HIPCHK(hipMemcpyAsync(hctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hctrl, ctrl, sizeof(Ctrl) * C, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (hctrl->err_pending) {  // raised outside a finalising launch (rates, profiling)
-            hctrl->err |= hctrl->err_pending;
-            hctrl->err_pending = 0;
+        bool fold = false;
+        for (int c = 0; c < C; ++c)
+            if (hctrl[c].err_pending) {  // raised outside a sub-step queue (rates, profiling)
+                hctrl[c].err |= hctrl[c].err_pending;
+                hctrl[c].err_pending = 0;
+                fold = true;
+            }
+        if (fold) {
             RETCHK(push_ctrl());
             HIPCHK(hipStreamSynchronize(s));
         }
@@ -280,24 +325,102 @@ struct Engine final : EngineBase {
 
     int push_ctrl()
     {
-        HIPCHK(hipMemcpyAsync(ctrl, hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(ctrl, hctrl, sizeof(Ctrl) * C, hipMemcpyHostToDevice, s));
         return SPHX_OK;
     }
 
-    int err_code(uint32_t e)
+    int err_code(int c, uint32_t e)
     {
-        if (e & ERR_NAN) return ctx->fail(SPHX_ENAN, "NaN in the particle state");
-        if (e & ERR_ESCAPE) return ctx->fail(SPHX_EESCAPE, "a fluid particle left the domain box");
-        if (e & ERR_NBR_OVERFLOW) return ctx->fail(SPHX_EOVERFLOW, "neighbour list capacity exceeded");
+        if (e & ERR_NAN) return ctx->fail(SPHX_ENAN, case_tag(c) + "NaN in the particle state");
+        if (e & ERR_ESCAPE) return ctx->fail(SPHX_EESCAPE, case_tag(c) + "a fluid particle left the domain box");
+        if (e & ERR_NBR_OVERFLOW) return ctx->fail(SPHX_EOVERFLOW, case_tag(c) + "neighbour list capacity exceeded");
+        return SPHX_OK;
+    }
+
+    // First error among the cases (lowest case index), from the host mirror.
+    int first_error()
+    {
+        for (int c = 0; c < C; ++c)
+            if (hctrl[c].err) return err_code(c, hctrl[c].err);
+        return SPHX_OK;
+    }
+
+    int check_case(int c)
+    {
+        if (c < 0 || c >= C) return ctx->fail(SPHX_EINVAL, "case index out of range");
+        return SPHX_OK;
+    }
+
+    int all_have_fluid()
+    {
+        for (int c = 0; c < C; ++c)
+            if (hP[c].nf == 0) return ctx->fail(SPHX_ESTATE, case_tag(c) + "no fluid particles");
         return SPHX_OK;
     }
 
     // ------------------------------------------------------------------
-    int alloc_fluid(int n)
+    // Layout: case c gets fcap = n rounded up to whole tiles, the others
+    // keep theirs; the state of every other case moves to its new slots.
+    int relayout(int c_new, int n_new)
     {
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<KP<real>> old = hP;
+        int old_cur = cur;
+        double* ox[3] = {x[cur][0], x[cur][1], x[cur][2]};
+        R4<real>* ost = st[cur];
+        real* odr = dr3[cur];
+        int32_t* oid = id[cur];
+        int32_t* ocell = cell[cur];
+        std::vector<void*> old_allocs;
+        old_allocs.swap(fluid_allocs);
+        (void)old_cur;
+        int base = 0;
+        for (int c = 0; c < C; ++c) {
+            KP<real>& P = hP[c];
+            if (c == c_new) {
+                P.nf = n_new;
+                P.fcap = round_tile(n_new);
+            }
+            P.fbase = base;
+            base += P.fcap;
+        }
+        ntot = base;
+        ntiles = ntot / TILE;
         drop_graphs();
-        free_list(fluid_allocs);
-        cap = n;
+        int rc = alloc_fluid();
+        if (rc != SPHX_OK) {
+            free_list(old_allocs);
+            laid_out = false;
+            return rc;
+        }
+        cur = 0;
+        if (laid_out) {
+            for (int c = 0; c < C; ++c) {
+                if (c == c_new || old[c].nf == 0) continue;
+                size_t n = (size_t)old[c].nf, o = (size_t)old[c].fbase, d = (size_t)hP[c].fbase;
+                for (int k = 0; k < D; ++k)
+                    HIPCHK(hipMemcpyAsync(x[0][k] + d, ox[k] + o, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(st[0] + d, ost + o, n * sizeof(R4<real>), hipMemcpyDeviceToDevice, s));
+                if (D == 3) HIPCHK(hipMemcpyAsync(dr3[0] + d, odr + o, n * sizeof(real), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(id[0] + d, oid + o, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(cell[0] + d, ocell + o, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            }
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        free_list(old_allocs);
+        std::vector<int32_t> tc(std::max(ntiles, 1), 0);
+        for (int c = 0; c < C; ++c)
+            for (int t = hP[c].fbase / TILE; t < (hP[c].fbase + hP[c].fcap) / TILE; ++t) tc[t] = c;
+        HIPCHK(hipMemcpy(tcase, tc.data(), sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice));
+        RETCHK(upload_params());
+        laid_out = true;
+        configured = false;
+        return SPHX_OK;
+    }
+
+    int alloc_fluid()
+    {
+        const int n = std::max(ntot, TILE);
         auto& L = fluid_allocs;
         for (int a = 0; a < 2; ++a) {
             for (int k = 0; k < D; ++k) RETCHK(dalloc(L, x[a][k], n));
@@ -309,21 +432,19 @@ struct Engine final : EngineBase {
             RETCHK(dalloc(L, id[a], n));
             RETCHK(dalloc(L, cell[a], n));
         }
+        RETCHK(dalloc(L, tcase, n / TILE));
         RETCHK(dalloc(L, hf, n));
-        size_t ncap = (size_t)(n + 63) / 64 * 64;  // whole wave tiles
-        RETCHK(dalloc(L, nbr, (size_t)maxn * ncap));
+        RETCHK(dalloc(L, nbr, (size_t)maxn * n));
         RETCHK(dalloc(L, ncnt, n));
-        RETCHK(dalloc(L, wnb, (size_t)maxw * ncap));
+        RETCHK(dalloc(L, wnb, (size_t)maxw * n));
         RETCHK(dalloc(L, wcnt, n));
         RETCHK(dalloc(L, key, n));
         RETCHK(dalloc(L, rank, n));
         RETCHK(dalloc(L, perm, n));
         RETCHK(dalloc(L, acc_out, (size_t)n * D));
-        RETCHK(dalloc(L, vslot, 2 * VSLOTS));
-        HIPCHK(hipMemsetAsync(vslot, 0, sizeof(unsigned long long) * 2 * VSLOTS, s));
         RETCHK(dalloc(L, drho_out, n));
         RETCHK(dalloc(L, outbuf, (size_t)n * D));
-        RETCHK(dalloc(L, diag_part, (size_t)nblk(n) * NDIAG));
+        RETCHK(dalloc(L, diag_part, (size_t)(n / TILE) * NDIAG));
         RETCHK(dalloc(L, bk_st, n));
         if (D == 3) RETCHK(dalloc(L, bk_dr, n));
         for (int k = 0; k < D; ++k) RETCHK(dalloc(L, bk_x[k], n));
@@ -335,25 +456,32 @@ struct Engine final : EngineBase {
     {
         if (ndoubles <= stage_n) return SPHX_OK;
         if (stage) {
+            HIPCHK(hipStreamSynchronize(s));
             (void)hipFree(stage);
             stage = nullptr;
+            stage_n = 0;
         }
         HIPCHK(hipMalloc((void**)&stage, ndoubles * sizeof(double)));
         stage_n = ndoubles;
         return SPHX_OK;
     }
 
-    int set_fluid(int64_t n, const double* pos, const double* vel, const double* rho, const double* drho) override
+    int set_fluid(int c, int64_t n, const double* pos, const double* vel, const double* rho,
+                  const double* drho) override
     {
-        if (n < 0 || (n > 0 && !pos) || n > (int64_t)NBR_MASK) return ctx->fail(SPHX_EINVAL, "bad fluid particle count or positions");
+        RETCHK(check_case(c));
+        if (n < 0 || (n > 0 && !pos) || n > (int64_t)NBR_MASK / 2)
+            return ctx->fail(SPHX_EINVAL, "bad fluid particle count or positions");
         HIPCHK(hipStreamSynchronize(s));
-        if ((int)n > cap || n == 0) RETCHK(alloc_fluid((int)std::max<int64_t>(n, 1)));
-        drop_graphs();
-        nf = (int)n;
-        P.nf = nf;
-        P.cap = cap;
-        configured = false;
-        cur = 0;
+        long long others = (long long)ntot - hP[c].fcap;
+        if (others + round_tile(n) > (long long)NBR_MASK) return ctx->fail(SPHX_EINVAL, "too many particles in the batch");
+        if (!laid_out || round_tile(n) > hP[c].fcap) {
+            RETCHK(relayout(c, (int)n));
+        } else {
+            hP[c].nf = (int)n;
+            RETCHK(upload_params());
+            configured = false;
+        }
         // stage: pos | vel | rho | drho
         size_t nn = (size_t)n;
         RETCHK(ensure_stage(nn * (2 * D + 2)));
@@ -366,128 +494,186 @@ struct Engine final : EngineBase {
             if (vel) HIPCHK(hipMemcpyAsync(dvel, vel, nn * D * sizeof(double), hipMemcpyHostToDevice, s));
             if (rho) HIPCHK(hipMemcpyAsync(drh, rho, nn * sizeof(double), hipMemcpyHostToDevice, s));
             if (drho) HIPCHK(hipMemcpyAsync(ddr, drho, nn * sizeof(double), hipMemcpyHostToDevice, s));
-            k_load_fluid<D, real><<<nblk(n), BLOCK, 0, s>>>(P, dpos, vel ? dvel : nullptr, rho ? drh : nullptr,
-                                                             drho ? ddr : nullptr, x[0][0], x[0][1], x[0][2], st[0],
-                                                             dr3[0], id[0]);
-            HIPCHK(hipGetLastError());
-        }
-        std::memset(hctrl, 0, sizeof(Ctrl));
-        RETCHK(push_ctrl());
-        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));  // after a failed rebuild
-        cur_steps = 0;
-        if (n > 0) {
-            k_vmax<D, real><<<nblk(n), BLOCK, 0, s>>>(P, ctrl, st[0]);
-            k_vmax_fin<real><<<1, 1, 0, s>>>(ctrl);
+            k_load_fluid<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, c, dpos, vel ? dvel : nullptr, rho ? drh : nullptr,
+                                                             drho ? ddr : nullptr, x[cur][0], x[cur][1], x[cur][2],
+                                                             st[cur], dr3[cur], id[cur], cell[cur]);
             HIPCHK(hipGetLastError());
         }
         RETCHK(sync_ctrl());
-        return SPHX_OK;
+        std::memset(&hctrl[c], 0, sizeof(Ctrl));
+        RETCHK(push_ctrl());
+        if (n > 0) {
+            k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, c, ctrl, st[cur]);
+            k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, c);
+            HIPCHK(hipGetLastError());
+        }
+        return sync_ctrl();
     }
 
-    int set_walls(int64_t n, const double* pos, const double* nrm) override
+    int set_walls(int c, int64_t n, const double* pos, const double* nrm) override
     {
-        if (n < 0 || (n > 0 && (!pos || !nrm)) || n > (int64_t)NBR_MASK) return ctx->fail(SPHX_EINVAL, "bad wall particle count or arrays");
+        RETCHK(check_case(c));
+        if (n < 0 || (n > 0 && (!pos || !nrm)) || n > (int64_t)NBR_MASK / 2)
+            return ctx->fail(SPHX_EINVAL, "bad wall particle count or arrays");
+        const KP<real>& P = hP[c];
         for (int64_t i = 0; i < n; ++i)
             for (int k = 0; k < D; ++k) {
                 double v = pos[i * D + k];
-                if (!(v >= P.lo[k] && v < P.hi[k])) return ctx->fail(SPHX_EINVAL, "wall particle outside the domain box");
+                if (!(v >= P.lo[k] && v < P.hi[k]))
+                    return ctx->fail(SPHX_EINVAL, case_tag(c) + "wall particle outside the domain box");
             }
+        long long tot = 0;
+        for (int d = 0; d < C; ++d) tot += d == c ? n : hP[d].nw;
+        if (tot > (long long)NBR_MASK) return ctx->fail(SPHX_EINVAL, "too many wall particles in the batch");
+        wpos_h[c].assign(pos, pos + n * D);
+        wnrm_h[c].assign(nrm, nrm + n * D);
+        hP[c].nw = (int)n;
+        return upload_walls();
+    }
+
+    // Concatenate the walls of every case, sort them by (global) cell and
+    // input order, freeze their offsets.
+    int upload_walls()
+    {
         HIPCHK(hipStreamSynchronize(s));
         drop_graphs();
         configured = false;
         free_list(wall_allocs);
-        nw = (int)n;
-        wcap = (int)std::max<int64_t>(n, 1);
+        int base = 0;
+        for (int c = 0; c < C; ++c) {
+            hP[c].wbase = base;
+            base += hP[c].nw;
+        }
+        nw_tot = base;
+        RETCHK(upload_params());
+        const int wcap = std::max(nw_tot, 1);
         auto& L = wall_allocs;
         for (int k = 0; k < D; ++k) RETCHK(dalloc(L, wx[k], wcap));
         if (D == 2) wx[2] = wx[1];
         RETCHK(dalloc(L, wgeo, wcap));
         RETCHK(dalloc(L, wnrm, wcap));
         RETCHK(dalloc(L, wid, wcap));
-        int32_t *wkey, *wrank, *wperm;
-        RETCHK(dalloc(L, wkey, wcap));
-        RETCHK(dalloc(L, wrank, wcap));
-        RETCHK(dalloc(L, wperm, wcap));
-        P.nw = nw;
-        if (n == 0) {
+        if (nw_tot == 0) {
             HIPCHK(hipMemsetAsync(wstart, 0, sizeof(int32_t) * ((size_t)ncell + 1), s));
             HIPCHK(hipStreamSynchronize(s));
             return SPHX_OK;
         }
-        // stage SoA positions and normals (original order)
-        size_t nn = (size_t)n;
+        int32_t *wkey, *wrank, *wperm, *wcase;
+        std::vector<void*> tmp;
+        RETCHK(dalloc(tmp, wkey, wcap));
+        RETCHK(dalloc(tmp, wrank, wcap));
+        RETCHK(dalloc(tmp, wperm, wcap));
+        RETCHK(dalloc(tmp, wcase, wcap));
+        size_t nn = (size_t)nw_tot;
         RETCHK(ensure_stage(nn * 6));
         std::vector<double> soa(nn * 6, 0.0);
-        for (size_t i = 0; i < nn; ++i)
-            for (int k = 0; k < D; ++k) {
-                soa[k * nn + i] = pos[i * D + k];
-                soa[(3 + k) * nn + i] = nrm[i * D + k];
+        std::vector<int32_t> wc(nn);
+        for (int c = 0; c < C; ++c)
+            for (int i = 0; i < hP[c].nw; ++i) {
+                size_t g = (size_t)hP[c].wbase + i;
+                wc[g] = c;
+                for (int k = 0; k < D; ++k) {
+                    soa[k * nn + g] = wpos_h[c][(size_t)i * D + k];
+                    soa[(3 + k) * nn + g] = wnrm_h[c][(size_t)i * D + k];
+                }
             }
         HIPCHK(hipMemcpyAsync(stage, soa.data(), nn * 6 * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(wcase, wc.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
         double* sx[3] = {stage, stage + nn, stage + 2 * nn};
         double* sn[3] = {stage + 3 * nn, stage + 4 * nn, stage + 5 * nn};
-        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));
-        k_bin<D, real><<<nblk(n), BLOCK, 0, s>>>(P, ctrl, 0, (int)n, sx[0], sx[1], sx[2], wkey, wrank, cnt, 0);
-        RETCHK(enqueue_scan(0, wstart));
-        k_scatter<<<nblk(n), BLOCK, 0, s>>>(ctrl, 0, (int)n, wkey, wrank, wstart, wperm);
-        k_cell_order<<<nblk(ncell), BLOCK, 0, s>>>(ctrl, 0, ncell, wstart, wperm);
-        k_gather_wall<D, real><<<nblk(n), BLOCK, 0, s>>>(P, (int)n, wperm, wkey, sx[0], sx[1], sx[2], sn[0], sn[1],
+        const int n = nw_tot;
+        k_bin_walls<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, n, sx[0], sx[1], sx[2], wkey, wrank, cnt);
+        RETCHK(enqueue_scan(wstart));
+        k_scatter_walls<<<nblk(n), BLOCK, 0, s>>>(n, wkey, wrank, wstart, wperm);
+        k_cell_order<<<nblk(ncell), BLOCK, 0, s>>>(ncell, wstart, wperm);
+        k_gather_wall<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, n, wperm, wkey, sx[0], sx[1], sx[2], sn[0], sn[1],
                                                           sn[2], wx[0], wx[1], wx[2], wgeo, wnrm, wid);
         HIPCHK(hipGetLastError());
-        RETCHK(sync_ctrl());
+        HIPCHK(hipStreamSynchronize(s));
+        free_list(tmp);
         return SPHX_OK;
     }
 
-    int enqueue_scan(int gate, int32_t* out)
+    int enqueue_scan(int32_t* out)
     {
         int nb = nblk_scan();
-        k_scan_tiles<<<nb, BLOCK, 0, s>>>(ctrl, gate, cnt, out, bsum, ncell);
-        k_scan_top<<<1, BLOCK, 0, s>>>(ctrl, gate, bsum, nb);
-        k_scan_add<<<nb, BLOCK, 0, s>>>(ctrl, gate, out, bsum, ncell, nb);
+        k_scan_tiles<<<nb, BLOCK, 0, s>>>(cnt, out, bsum, ncell);
+        k_scan_top<<<1, BLOCK, 0, s>>>(bsum, nb);
+        k_scan_add<<<nb, BLOCK, 0, s>>>(out, bsum, ncell, nb);
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
 
-    // S1-S3 from state set a into set b. The cell counters are zero on entry
-    // (zeroed at allocation and by every scan that consumes them).
-    int enqueue_rebuild(int gate, int a)
+    // S1-S3 from state set a into set b for every case (a full update where
+    // a step ended or `force`, the identity elsewhere). The cell counters are
+    // zero on entry (zeroed at allocation and by every scan that consumes
+    // them).
+    template <int T>
+    void launch_neighbors(int force, int b)
+    {
+        k_neighbors<D, real, T, LB><<<ntiles, TILE * LB, 0, s>>>(dP, tcase, ctrl, force, x[b][0], x[b][1], x[b][2],
+                                                                cell[b], fstart, geo[b], wx[0], wx[1], wx[2], wstart,
+                                                                wgeo, nbr, ncnt, wnb, wcnt);
+    }
+
+    int enqueue_rebuild(int force, int a)
     {
         int b = 1 - a;
-        k_bin<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, gate, nf, x[a][0], x[a][1], x[a][2], key, rank, cnt, 1);
-        RETCHK(enqueue_scan(gate, fstart));
-        k_scatter<<<nblk(nf), BLOCK, 0, s>>>(ctrl, gate, nf, key, rank, fstart, perm);
-        k_place_fluid<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, gate, nf, perm, key, fstart, x[a][0], x[a][1],
-                                                           x[a][2], st[a], dr3[a], id[a], x[b][0], x[b][1], x[b][2],
-                                                           st[b], dr3[b], id[b], cell[b], geo[b]);
-        k_neighbors<D, real, LN, LB><<<nblk((long long)nf * LB), BLOCK, 0, s>>>(
-            P, ctrl, gate, x[b][0], x[b][1], x[b][2], cell[b], fstart, geo[b], wx[0], wx[1], wx[2], wstart, wgeo, nbr,
-            ncnt, wnb, wcnt);
+        const int nb = nblk(ntot);
+        k_bin<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, x[a][0], x[a][1], x[a][2], cell[a], key,
+                                            rank, cnt);
+        RETCHK(enqueue_scan(fstart));
+        k_scatter<real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ntot, key, rank, fstart, perm);
+        k_place_fluid<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, ntot, perm, key, fstart, x[a][0],
+                                                     x[a][1], x[a][2], st[a], dr3[a], id[a], geo[a], x[b][0], x[b][1],
+                                                     x[b][2], st[b], dr3[b], id[b], cell[b], geo[b]);
+        if (ln == 4) launch_neighbors<4>(force, b);
+        else launch_neighbors<8>(force, b);
         HIPCHK(hipGetLastError());
         return SPHX_OK;
+    }
+
+    template <int T>
+    void launch_substep(int a, int q, int adv, int finalize, real* acc, real* dro)
+    {
+        const int nb = pair_blocks();
+        k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a],
+                                                    dr3[a], hf, acc, q, adv, vslot);
+        k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+                                                   hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro, vslot, q);
     }
 
     // Pressure and density relaxation of sub-step q on set a; `adv`: close
     // sub-step q - 1 first (inside the pressure relaxation).
     int enqueue_substep(int a, int q, int adv, int finalize, real* acc, real* dro)
     {
-        k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb,
-                                                                          wcnt, st[a], dr3[a], hf, acc, q, adv, vslot);
-        k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, finalize, geo[a], wgeo, wnrm, nbr,
-                                                                         ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
-                                                                         x[a][1], x[a][2], dro, vslot, q);
+        if (ln == 4) launch_substep<4>(a, q, adv, finalize, acc, dro);
+        else launch_substep<8>(a, q, adv, finalize, acc, dro);
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
 
-    // One advection step on set a (graph body): re-init, the queued
-    // sub-steps, the step end (which prepares the next step), the rebuild.
+    int enqueue_reinit(int gate, int a)
+    {
+        const int nb = pair_blocks();
+        if (ln == 4)
+            k_reinit<D, real, 4><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
+        else
+            k_reinit<D, real, 8><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
+        HIPCHK(hipGetLastError());
+        return SPHX_OK;
+    }
+
+    // One queue on set a (graph body): re-initialisation for the cases
+    // starting a step, the queued sub-steps, the step end (which prepares the
+    // next step or marks a continuation), the configuration update.
     int enqueue_step(int a)
     {
-        k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[a], wgeo, nbr, ncnt, wnb, wcnt,
-                                                                        st[a]);
+        RETCHK(enqueue_reinit(1, a));
         for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr));
-        k_step_end<real><<<1, 64, 0, s>>>(P, ctrl, vslot, nsub_q - 1, 1, 1);
-        RETCHK(enqueue_rebuild(1, a));
+        k_step_end<real><<<C, 64, 0, s>>>(dP, ctrl, vslot, nsub_q - 1);
+        HIPCHK(hipGetLastError());
+        RETCHK(enqueue_rebuild(0, a));
         return SPHX_OK;
     }
 
@@ -524,38 +710,47 @@ struct Engine final : EngineBase {
     // ------------------------------------------------------------------
     int build_neighbors() override
     {
-        if (nf == 0) return ctx->fail(SPHX_ESTATE, "no fluid particles");
+        RETCHK(all_have_fluid());
         RETCHK(sync_ctrl());
-        hctrl->err = 0;
+        for (int c = 0; c < C; ++c) hctrl[c].err = 0;
         RETCHK(push_ctrl());
-        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));  // a failed rebuild may leave counts
-        RETCHK(enqueue_rebuild(0, cur));
+        RETCHK(enqueue_rebuild(1, cur));
         RETCHK(sync_ctrl());
         cur ^= 1;
-        if (hctrl->err) {
+        int rc = first_error();
+        if (rc != SPHX_OK) {
             configured = false;
-            uint32_t e = hctrl->err;
-            hctrl->err = 0;
+            for (int c = 0; c < C; ++c) hctrl[c].err = 0;
             RETCHK(push_ctrl());
-            return err_code(e);
+            HIPCHK(hipStreamSynchronize(s));
+            return rc;
         }
         configured = true;
         return SPHX_OK;
     }
 
-    int get_neighbors(int kind, int64_t* off, int64_t* idx, int64_t cap_idx, int64_t* n_out) override
+    size_t ell_index(int i, int k, int mx) const { return ln == 4 ? ell_at<4>(i, k, mx) : ell_at<8>(i, k, mx); }
+
+    int get_neighbors(int c, int kind, int64_t* off, int64_t* idx, int64_t cap_idx, int64_t* n_out) override
     {
+        RETCHK(check_case(c));
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
-        int mx = kind == SPHX_INNER ? maxn : maxw;
-        std::vector<int32_t> cnts(nf), ids(nf), oid(std::max(nw, 1));
-        size_t ncap = (size_t)(cap + 63) / 64 * 64;
-        std::vector<uint32_t> ell((size_t)mx * ncap);
-        HIPCHK(hipMemcpyAsync(cnts.data(), kind == SPHX_INNER ? ncnt : wcnt, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(ids.data(), id[cur], sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+        const KP<real>& P = hP[c];
+        const int nf = P.nf, nw = P.nw;
+        const int mx = kind == SPHX_INNER ? maxn : maxw;
+        std::vector<int32_t> cnts(std::max(nf, 1)), ids(std::max(nf, 1)), oid(std::max(nw, 1));
+        // the case's tiles hold one contiguous range of list words
+        const size_t e0 = ell_index(P.fbase, 0, mx), ne = (size_t)mx * P.fcap;
+        std::vector<uint32_t> ell(std::max<size_t>(ne, 1));
+        if (nf > 0) {
+            HIPCHK(hipMemcpyAsync(cnts.data(), (kind == SPHX_INNER ? ncnt : wcnt) + P.fbase, sizeof(int32_t) * nf,
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(ids.data(), id[cur] + P.fbase, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(ell.data(), (kind == SPHX_INNER ? nbr : wnb) + e0, sizeof(uint32_t) * ne,
+                                  hipMemcpyDeviceToHost, s));
+        }
         if (kind != SPHX_INNER && nw > 0)
-            HIPCHK(hipMemcpyAsync(oid.data(), wid, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(ell.data(), kind == SPHX_INNER ? nbr : wnb, sizeof(uint32_t) * (size_t)mx * ncap,
-                              hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(oid.data(), wid + P.wbase, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         std::vector<int64_t> rowlen(nf + 1, 0);
         for (int i = 0; i < nf; ++i) rowlen[ids[i] + 1] = cnts[i];
@@ -569,8 +764,8 @@ struct Engine final : EngineBase {
             for (int i = 0; i < nf; ++i) {
                 int64_t o = rowlen[ids[i]];
                 for (int k = 0; k < cnts[i]; ++k) {
-                    uint32_t j = ell[ell_at<LN>(i, k, mx)] & NBR_MASK;
-                    idx[o + k] = kind == SPHX_INNER ? ids[j] : oid[j];
+                    uint32_t j = ell[ell_index(P.fbase + i, k, mx) - e0] & NBR_MASK;
+                    idx[o + k] = kind == SPHX_INNER ? ids[j - P.fbase] : oid[j - P.wbase];
                 }
                 std::sort(idx + o, idx + o + cnts[i]);
             }
@@ -581,27 +776,21 @@ struct Engine final : EngineBase {
     int density_reinit() override
     {
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
-        k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 0, geo[cur], wgeo, nbr, ncnt, wnb, wcnt, st[cur]);
-        HIPCHK(hipGetLastError());
+        RETCHK(enqueue_reinit(0, cur));
         HIPCHK(hipStreamSynchronize(s));
         return SPHX_OK;
     }
 
-    int refresh_vmax()
+    int time_steps(int c, double* dt_ad, double* dt_ac) override
     {
-        if (nf > 0) {
-            k_vmax<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, ctrl, st[cur]);
-            k_vmax_fin<real><<<1, 1, 0, s>>>(ctrl);
-            HIPCHK(hipGetLastError());
-        }
-        return sync_ctrl();
-    }
-
-    int time_steps(double* dt_ad, double* dt_ac) override
-    {
-        if (nf == 0) return ctx->fail(SPHX_ESTATE, "no fluid particles");
-        RETCHK(refresh_vmax());
-        double vmax = hctrl->vmax;
+        RETCHK(check_case(c));
+        if (hP[c].nf == 0) return ctx->fail(SPHX_ESTATE, case_tag(c) + "no fluid particles");
+        k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, c, ctrl, st[cur]);
+        k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, c);
+        HIPCHK(hipGetLastError());
+        RETCHK(sync_ctrl());
+        const KP<real>& P = hP[c];
+        double vmax = hctrl[c].vmax;
         if (dt_ad) *dt_ad = P.cfl_ad_h / std::fmax(vmax, P.u_ref);
         if (dt_ac) *dt_ac = P.cfl_ac_h / (P.c0d + vmax);
         return SPHX_OK;
@@ -609,241 +798,290 @@ struct Engine final : EngineBase {
 
     int backup_state()
     {
-        HIPCHK(hipMemcpyAsync(bk_st, st[cur], sizeof(R4<real>) * nf, hipMemcpyDeviceToDevice, s));
-        if (D == 3) HIPCHK(hipMemcpyAsync(bk_dr, dr3[cur], sizeof(real) * nf, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(bk_st, st[cur], sizeof(R4<real>) * ntot, hipMemcpyDeviceToDevice, s));
+        if (D == 3) HIPCHK(hipMemcpyAsync(bk_dr, dr3[cur], sizeof(real) * ntot, hipMemcpyDeviceToDevice, s));
         for (int k = 0; k < D; ++k)
-            HIPCHK(hipMemcpyAsync(bk_x[k], x[cur][k], sizeof(double) * nf, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(bk_x[k], x[cur][k], sizeof(double) * ntot, hipMemcpyDeviceToDevice, s));
         return SPHX_OK;
     }
 
-    int restore_state(const Ctrl& saved)
+    int restore_state(const std::vector<Ctrl>& saved)
     {
-        HIPCHK(hipMemcpyAsync(st[cur], bk_st, sizeof(R4<real>) * nf, hipMemcpyDeviceToDevice, s));
-        if (D == 3) HIPCHK(hipMemcpyAsync(dr3[cur], bk_dr, sizeof(real) * nf, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(st[cur], bk_st, sizeof(R4<real>) * ntot, hipMemcpyDeviceToDevice, s));
+        if (D == 3) HIPCHK(hipMemcpyAsync(dr3[cur], bk_dr, sizeof(real) * ntot, hipMemcpyDeviceToDevice, s));
         for (int k = 0; k < D; ++k)
-            HIPCHK(hipMemcpyAsync(x[cur][k], bk_x[k], sizeof(double) * nf, hipMemcpyDeviceToDevice, s));
-        *hctrl = saved;
+            HIPCHK(hipMemcpyAsync(x[cur][k], bk_x[k], sizeof(double) * ntot, hipMemcpyDeviceToDevice, s));
+        std::memcpy(hctrl, saved.data(), sizeof(Ctrl) * C);
         RETCHK(push_ctrl());
         HIPCHK(hipStreamSynchronize(s));
         return SPHX_OK;
     }
 
-    int compute_rates(double dt, double* dvdt, double* drhodt) override
+    int compute_rates(int c, double dt, double* dvdt, double* drhodt) override
     {
+        RETCHK(check_case(c));
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
         RETCHK(sync_ctrl());
-        Ctrl saved = *hctrl;
+        std::vector<Ctrl> saved(hctrl, hctrl + C);
         RETCHK(backup_state());
-        hctrl->ss[0] = SubState{0.0, dt, 0, 1, 0, 0};
-        hctrl->err = 0;
+        for (int d = 0; d < C; ++d) {
+            hctrl[d].ss[0] = SubState{0.0, d == c ? dt : 0.0, 0, d == c ? 1 : 0, 0, 0};
+            hctrl[d].midstep = 0;
+        }
+        hctrl[c].err = 0;
         RETCHK(push_ctrl());
         RETCHK(enqueue_substep(cur, 0, 0, 0, acc_out, drho_out));
-        if (dvdt) {
-            k_unsort_vec<real><<<nblk(nf), BLOCK, 0, s>>>(nf, D, id[cur], acc_out, outbuf);
+        const KP<real>& P = hP[c];
+        if (dvdt && P.nf > 0) {
+            k_unsort_vec<real><<<nblk(P.nf), BLOCK, 0, s>>>(P.fbase, P.nf, D, id[cur], acc_out, outbuf);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(dvdt, outbuf, sizeof(double) * (size_t)nf * D, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(dvdt, outbuf, sizeof(double) * (size_t)P.nf * D, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
         }
-        if (drhodt) {
-            k_unsort_vec<real><<<nblk(nf), BLOCK, 0, s>>>(nf, 1, id[cur], drho_out, outbuf);
+        if (drhodt && P.nf > 0) {
+            k_unsort_vec<real><<<nblk(P.nf), BLOCK, 0, s>>>(P.fbase, P.nf, 1, id[cur], drho_out, outbuf);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(drhodt, outbuf, sizeof(double) * (size_t)nf, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(drhodt, outbuf, sizeof(double) * (size_t)P.nf, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
         }
         RETCHK(sync_ctrl());
-        uint32_t e = hctrl->err;
+        uint32_t e = hctrl[c].err;
         RETCHK(restore_state(saved));
-        return err_code(e);
+        return err_code(c, e);
     }
 
-    // Finish an advection step that ran out of queued sub-steps, from the
-    // host, one sub-step per synchronisation; then rebuild its configuration
-    // and prepare the next step.
-    int finish_stalled_step()
+    bool busy(int c) const { return !hctrl[c].err && (hctrl[c].midstep || hctrl[c].ss[0].active); }
+
+    // Queues every case still needs at least: one advection step per queue,
+    // bounded by its step target and by the longest possible advection step.
+    long long queues_needed() const
     {
-        hctrl->err &= ~ERR_STALL;
-        RETCHK(push_ctrl());
-        int q = nsub_q;
-        for (int it = 0; it < 100000; ++it, ++q) {
-            RETCHK(enqueue_substep(cur, q, 0, 1, nullptr, nullptr));
-            k_step_end<real><<<1, 64, 0, s>>>(P, ctrl, vslot, q, 0, 0);
-            HIPCHK(hipGetLastError());
-            RETCHK(sync_ctrl());
-            if (hctrl->err) return err_code(hctrl->err);
-            if (hctrl->rebuild) break;
+        long long need = 0;
+        for (int c = 0; c < C; ++c) {
+            if (!busy(c)) continue;
+            const Ctrl& k = hctrl[c];
+            long long r = k.steps_target - k.steps_done;
+            double dt_max = hP[c].cfl_ad_h / hP[c].u_ref;
+            double by_time = std::ceil((k.t_stop - k.t) / dt_max);
+            if (by_time < (double)r) r = (long long)std::max(by_time, 1.0);
+            need = std::max(need, std::max(r, 1LL));
         }
-        if (!hctrl->rebuild) return ctx->fail(SPHX_ESTATE, "advection step did not finish");
-        RETCHK(enqueue_rebuild(1, cur));
-        k_adv_begin<real><<<1, 1, 0, s>>>(P, ctrl);
-        HIPCHK(hipGetLastError());
-        RETCHK(sync_ctrl());
-        cur ^= 1;
-        cur_steps = hctrl->steps_done;
-        return err_code(hctrl->err);
+        return need;
     }
 
     int advance(int32_t n_steps, double t_stop, int64_t* nsub_out, double* t_out) override
     {
-        if (nf == 0) return ctx->fail(SPHX_ESTATE, "no fluid particles");
+        RETCHK(all_have_fluid());
+        if (n_steps < 0) return ctx->fail(SPHX_EINVAL, "negative step count");
         if (!configured) RETCHK(build_neighbors());
         RETCHK(capture_graphs());
         RETCHK(sync_ctrl());
-        long long sub0 = hctrl->nsub_total;
-        long long start = hctrl->steps_done;
-        cur_steps = start;
-        HIPCHK(hipMemcpyAsync(&ctrl->t_stop, &t_stop, sizeof(double), hipMemcpyHostToDevice, s));
-        k_adv_begin<real><<<1, 1, 0, s>>>(P, ctrl);
+        std::vector<long long> sub0(C);
+        for (int c = 0; c < C; ++c) {
+            sub0[c] = hctrl[c].nsub_total;
+            hctrl[c].t_stop = t_stop;
+            hctrl[c].steps_target = hctrl[c].steps_done + n_steps;
+        }
+        RETCHK(push_ctrl());
+        k_adv_begin<real><<<(C + 63) / 64, 64, 0, s>>>(dP, ctrl, C);
         HIPCHK(hipGetLastError());
         RETCHK(sync_ctrl());
-        long long remaining = n_steps;
-        while (remaining > 0 && hctrl->t < t_stop) {
-            // up to 64 steps per batch, one host synchronisation per batch
-            long long batch = std::min<long long>(remaining, 64);
-            int pp = cur;
+        // queues in batches of at most 64, one host synchronisation per batch
+        for (long long need = queues_needed(); need > 0; need = queues_needed()) {
+            long long batch = std::min<long long>(need, 64);
             long long q = 0;
             for (; q + steps_per_graph <= batch; q += steps_per_graph) {
-                HIPCHK(hipGraphLaunch(gexec[pp], s));
-                pp = (pp + steps_per_graph) & 1;
+                HIPCHK(hipGraphLaunch(gexec[cur], s));
+                cur = (cur + steps_per_graph) & 1;
             }
             for (; q < batch; ++q) {
-                HIPCHK(hipGraphLaunch(gone[pp], s));
-                pp ^= 1;
+                HIPCHK(hipGraphLaunch(gone[cur], s));
+                cur ^= 1;
             }
-            int cur_before = cur;
-            long long steps_before = cur_steps;
             RETCHK(sync_ctrl());
-            long long done = hctrl->steps_done - steps_before;
-            cur = (int)((cur_before + done) & 1);
-            cur_steps = hctrl->steps_done;
-            if (hctrl->err & ~ERR_STALL) {
-                // a NaN or an escape stops the rebuild of the step it occurs in
-                if ((hctrl->err & (ERR_ESCAPE | ERR_NAN)) && done > 0) cur = (int)((cur_before + done - 1) & 1);
-                configured = false;
-                return err_code(hctrl->err);
-            }
-            if (hctrl->err & ERR_STALL) RETCHK(finish_stalled_step());
-            remaining = n_steps - (cur_steps - start);
         }
-        if (nsub_out) *nsub_out = hctrl->nsub_total - sub0;
-        if (t_out) *t_out = hctrl->t;
-        return SPHX_OK;
+        long long nsub = 0;
+        for (int c = 0; c < C; ++c) nsub += hctrl[c].nsub_total - sub0[c];
+        if (nsub_out) *nsub_out = nsub;
+        if (t_out) *t_out = hctrl[0].t;
+        return first_error();
     }
 
-    int get_field(int which, double* out) override
+    int case_status(int c) override
     {
+        RETCHK(check_case(c));
+        RETCHK(sync_ctrl());
+        return err_code(c, hctrl[c].err);
+    }
+
+    int get_field(int c, int which, double* out) override
+    {
+        RETCHK(check_case(c));
         if (which < 0 || which > 4 || !out) return ctx->fail(SPHX_EINVAL, "bad field");
-        if (nf == 0) return SPHX_OK;
-        k_unsort_field<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, which, id[cur], x[cur][0], x[cur][1], x[cur][2], st[cur],
-                                                            dr3[cur], outbuf);
+        const KP<real>& P = hP[c];
+        if (P.nf == 0) return SPHX_OK;
+        k_unsort_field<D, real><<<nblk(P.nf), BLOCK, 0, s>>>(dP, c, which, id[cur], x[cur][0], x[cur][1], x[cur][2],
+                                                              st[cur], dr3[cur], outbuf);
         HIPCHK(hipGetLastError());
-        size_t cnt_out = (which <= 1 ? (size_t)D : 1) * nf;
+        size_t cnt_out = (which <= 1 ? (size_t)D : 1) * P.nf;
         HIPCHK(hipMemcpyAsync(out, outbuf, sizeof(double) * cnt_out, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         return SPHX_OK;
     }
 
-    int diagnostics(sphx_diag* out) override
+    // c >= 0: one case into out[0]; c < 0: every case into out[0..C).
+    int diagnostics(int c, sphx_diag* out) override
     {
         if (!out) return ctx->fail(SPHX_EINVAL, "NULL output");
-        double r[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (nf > 0) {
-            k_diag<D, real><<<nblk(nf), BLOCK, 0, s>>>(P, x[cur][0], x[cur][1], x[cur][2], st[cur], diag_part);
-            k_diag_fin<<<1, BLOCK, 0, s>>>(diag_part, nblk(nf), diag_out);
+        if (c >= C) return ctx->fail(SPHX_EINVAL, "case index out of range");
+        std::vector<double> r((size_t)NDIAG * C, 0.0);
+        if (ntiles > 0) {
+            k_diag<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, x[cur][0], x[cur][1], x[cur][2], st[cur],
+                                                          diag_part);
+            k_diag_fin<real><<<C, BLOCK, 0, s>>>(dP, diag_part, diag_out);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(r, diag_out, sizeof(r), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(r.data(), diag_out, sizeof(double) * NDIAG * C, hipMemcpyDeviceToHost, s));
         }
         RETCHK(sync_ctrl());
-        out->mass = P.md * nf;
-        out->momentum[0] = r[0];
-        out->momentum[1] = r[1];
-        out->momentum[2] = r[2];
-        out->e_kin = r[3];
-        out->e_pot = r[4];
-        out->e_int = r[5];
-        out->front = r[6];
-        out->max_drho = r[7];
-        out->t = hctrl->t;
-        out->n_substeps = hctrl->nsub_total;
-        out->n_steps = hctrl->steps_done;
+        for (int d = (c < 0 ? 0 : c), k = 0; d < (c < 0 ? C : c + 1); ++d, ++k) {
+            const double* v = &r[(size_t)d * NDIAG];
+            sphx_diag& o = out[k];
+            bool any = hP[d].nf > 0;
+            o.mass = hP[d].md * hP[d].nf;
+            o.momentum[0] = v[0];
+            o.momentum[1] = v[1];
+            o.momentum[2] = v[2];
+            o.e_kin = v[3];
+            o.e_pot = v[4];
+            o.e_int = v[5];
+            o.front = any ? v[6] : 0.0;
+            o.max_drho = v[7];
+            o.t = hctrl[d].t;
+            o.n_substeps = hctrl[d].nsub_total;
+            o.n_steps = hctrl[d].steps_done;
+        }
         return SPHX_OK;
     }
 
+    template <typename F>
+    int time_launches(int reps, double* ms, F launch)
+    {
+        hipEvent_t ev[2];
+        HIPCHK(hipEventCreate(&ev[0]));
+        HIPCHK(hipEventCreate(&ev[1]));
+        float t = 0.f;
+        HIPCHK(hipEventRecord(ev[0], s));
+        for (int r = 0; r < reps; ++r) launch();
+        HIPCHK(hipEventRecord(ev[1], s));
+        HIPCHK(hipEventSynchronize(ev[1]));
+        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        HIPCHK(hipGetLastError());
+        *ms = (double)t / reps;
+        return SPHX_OK;
+    }
+
+    template <int T>
+    int profile_t(int reps, double* ms)
+    {
+        const int nb = pair_blocks();
+        const int a = cur;
+        RETCHK(time_launches(reps, &ms[0], [&] {
+            k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+                                                        st[a], dr3[a], hf, nullptr, 0, 0, vslot);
+        }));
+        RETCHK(time_launches(reps, &ms[1], [&] {
+            k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+                                                       hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], nullptr, vslot, 0);
+        }));
+        // the list build is idempotent on the current set
+        RETCHK(time_launches(reps, &ms[2], [&] { launch_neighbors<T>(1, a); }));
+        RETCHK(time_launches(reps, &ms[3], [&] {
+            k_reinit<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, 0, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
+        }));
+        return SPHX_OK;
+    }
+
+    // Per-launch device time of the hot kernels on the current state of
+    // every case (each case one sub-step of its own dt_ac); the state and the
+    // clocks are restored afterwards.
     int profile(int32_t reps, double* ms) override
     {
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
         if (reps < 1 || !ms) return ctx->fail(SPHX_EINVAL, "bad profile arguments");
         RETCHK(sync_ctrl());
-        Ctrl saved = *hctrl;
+        std::vector<Ctrl> saved(hctrl, hctrl + C);
         RETCHK(backup_state());
-        hipEvent_t ev[2];
-        HIPCHK(hipEventCreate(&ev[0]));
-        HIPCHK(hipEventCreate(&ev[1]));
-        double dt_ac = P.cfl_ac_h / (P.c0d + hctrl->vmax);
-        hctrl->ss[0] = SubState{0.0, dt_ac, 0, 1, 0, 0};
-        hctrl->err = 0;
+        for (int c = 0; c < C; ++c) {
+            double dt_ac = hP[c].cfl_ac_h / (hP[c].c0d + hctrl[c].vmax);
+            hctrl[c].ss[0] = SubState{0.0, dt_ac, 0, 1, 0, 0};
+            hctrl[c].midstep = 0;
+            hctrl[c].err = 0;
+        }
         RETCHK(push_ctrl());
-        float t;
-        // pressure relaxation
-        HIPCHK(hipEventRecord(ev[0], s));
-        for (int r = 0; r < reps; ++r)
-            k_pressure<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(
-                P, ctrl, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[cur], dr3[cur], hf, nullptr, 0, 0, vslot);
-        HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(hipEventSynchronize(ev[1]));
-        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
-        ms[0] = t / reps;
-        // density relaxation (with its |v|max reduction and clock update)
-        HIPCHK(hipEventRecord(ev[0], s));
-        for (int r = 0; r < reps; ++r)
-            k_density<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 1, geo[cur], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf,
-                                                           st[cur], dr3[cur], x[cur][0], x[cur][1], x[cur][2], nullptr,
-                                                                         vslot, 0);
-        HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(hipEventSynchronize(ev[1]));
-        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
-        ms[1] = t / reps;
-        // neighbour build (idempotent on the current set)
-        HIPCHK(hipEventRecord(ev[0], s));
-        for (int r = 0; r < reps; ++r)
-            k_neighbors<D, real, LN, LB><<<nblk((long long)nf * LB), BLOCK, 0, s>>>(
-                P, ctrl, 0, x[cur][0], x[cur][1], x[cur][2], cell[cur], fstart, geo[cur], wx[0], wx[1], wx[2], wstart,
-                wgeo, nbr, ncnt, wnb, wcnt);
-        HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(hipEventSynchronize(ev[1]));
-        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
-        ms[2] = t / reps;
-        // density re-initialisation (gate off; restored below)
-        HIPCHK(hipEventRecord(ev[0], s));
-        for (int r = 0; r < reps; ++r)
-            k_reinit<D, real, LN><<<nblk((long long)nf * LN), BLOCK, 0, s>>>(P, ctrl, 0, geo[cur], wgeo, nbr, ncnt, wnb, wcnt, st[cur]);
-        HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(hipEventSynchronize(ev[1]));
-        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
-        ms[3] = t / reps;
-        (void)hipEventDestroy(ev[0]);
-        (void)hipEventDestroy(ev[1]);
-        HIPCHK(hipGetLastError());
+        if (ln == 4) RETCHK(profile_t<4>(reps, ms));
+        else RETCHK(profile_t<8>(reps, ms));
         RETCHK(sync_ctrl());
-        uint32_t e = hctrl->err;
+        int rc = first_error();
         RETCHK(restore_state(saved));
-        return err_code(e);
+        // the |v| slots the profiled launches filled
+        HIPCHK(hipMemsetAsync(vslot, 0, sizeof(unsigned long long) * 2 * VSLOTS * C, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return rc;
     }
 
-    int counts(int64_t* out) override
+    int counts(int c, int64_t* out) override
     {
         if (!out) return ctx->fail(SPHX_EINVAL, "NULL output");
-        out[0] = nf;
-        out[1] = nw;
-        out[2] = out[3] = 0;
-        if (!configured || nf == 0) return SPHX_OK;
-        std::vector<int32_t> a(nf), b(nf);
-        HIPCHK(hipMemcpyAsync(a.data(), ncnt, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(b.data(), wcnt, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+        if (c >= C) return ctx->fail(SPHX_EINVAL, "case index out of range");
+        out[0] = out[1] = out[2] = out[3] = 0;
+        for (int d = 0; d < C; ++d)
+            if (c < 0 || d == c) {
+                out[0] += hP[d].nf;
+                out[1] += hP[d].nw;
+            }
+        if (!configured || ntot == 0) return SPHX_OK;
+        std::vector<int32_t> a(ntot), b(ntot);
+        HIPCHK(hipMemcpyAsync(a.data(), ncnt, sizeof(int32_t) * ntot, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(b.data(), wcnt, sizeof(int32_t) * ntot, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        for (int i = 0; i < nf; ++i) {
-            out[2] += a[i];
-            out[3] += b[i];
+        for (int d = 0; d < C; ++d) {
+            if (c >= 0 && d != c) continue;
+            for (int i = hP[d].fbase; i < hP[d].fbase + hP[d].nf; ++i) {
+                out[2] += a[i];
+                out[3] += b[i];
+            }
         }
+        return SPHX_OK;
+    }
+
+    // Pick the lanes per particle of the pair kernels (4 or 8) by timing one
+    // pressure and one density relaxation of every case with each; the lists
+    // are rebuilt in the chosen layout (the same lists; sums are combined in
+    // a different order, so results change at rounding level).
+    int autotune(int32_t reps, int32_t* lanes) override
+    {
+        if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
+        if (reps < 1) return ctx->fail(SPHX_EINVAL, "bad repetition count");
+        const int cand[2] = {4, 8};
+        double best = 1e300;
+        int best_ln = ln;
+        for (int t : cand) {
+            ln = t;
+            RETCHK(build_neighbors());
+            double ms[4];
+            RETCHK(profile(reps, ms));
+            double tt = ms[0] + ms[1];
+            if (tt < best) {
+                best = tt;
+                best_ln = t;
+            }
+        }
+        ln = best_ln;
+        drop_graphs();
+        RETCHK(build_neighbors());
+        if (lanes) *lanes = ln;
         return SPHX_OK;
     }
 };
@@ -851,19 +1089,20 @@ struct Engine final : EngineBase {
 // ---------------------------------------------------------------------
 // C ABI
 
-extern "C" {
-
-int sphx_create(const sphx_params* params, void* stream, sphx_ctx** out)
+static int create_impl(const sphx_params* params, int32_t n, void* stream, sphx_ctx** out)
 {
-    if (!params || !out) return SPHX_EINVAL;
+    if (!params || !out || n < 1) return SPHX_EINVAL;
     *out = nullptr;
-    const sphx_params& q = *params;
-    if ((q.dim != 2 && q.dim != 3) || (q.precision != SPHX_FP32 && q.precision != SPHX_FP64) || !(q.dp > 0) ||
-        !(q.h > 0) || !(q.rho0 > 0) || !(q.c0 > 0) || !(q.u_ref > 0) || !(q.cfl_ad > 0) || !(q.cfl_ac > 0))
-        return SPHX_EINVAL;
+    for (int c = 0; c < n; ++c) {
+        const sphx_params& q = params[c];
+        if ((q.dim != 2 && q.dim != 3) || (q.precision != SPHX_FP32 && q.precision != SPHX_FP64) || !(q.dp > 0) ||
+            !(q.h > 0) || !(q.rho0 > 0) || !(q.c0 > 0) || !(q.u_ref > 0) || !(q.cfl_ad > 0) || !(q.cfl_ac > 0))
+            return SPHX_EINVAL;
+        if (q.dim != params[0].dim || q.precision != params[0].precision) return SPHX_EINVAL;
+    }
     std::unique_ptr<sphx_ctx> ctx(new (std::nothrow) sphx_ctx());
     if (!ctx) return SPHX_ENOMEM;
-    ctx->prm = q;
+    ctx->prm.assign(params, params + n);
     if (stream) {
         ctx->stream = (hipStream_t)stream;
     } else {
@@ -871,10 +1110,11 @@ int sphx_create(const sphx_params* params, void* stream, sphx_ctx** out)
         if (e != hipSuccess) return SPHX_EHIP;
         ctx->own_stream = true;
     }
-    if (q.dim == 2 && q.precision == SPHX_FP64) ctx->eng.reset(new Engine<2, double>(ctx.get()));
-    else if (q.dim == 2) ctx->eng.reset(new Engine<2, float>(ctx.get()));
-    else if (q.precision == SPHX_FP64) ctx->eng.reset(new Engine<3, double>(ctx.get()));
-    else ctx->eng.reset(new Engine<3, float>(ctx.get()));
+    const sphx_params& q = params[0];
+    if (q.dim == 2 && q.precision == SPHX_FP64) ctx->eng.reset(new Engine<2, double>(ctx.get(), n));
+    else if (q.dim == 2) ctx->eng.reset(new Engine<2, float>(ctx.get(), n));
+    else if (q.precision == SPHX_FP64) ctx->eng.reset(new Engine<3, double>(ctx.get(), n));
+    else ctx->eng.reset(new Engine<3, float>(ctx.get(), n));
     int rc = ctx->eng->init();
     if (rc != SPHX_OK) {
         ctx->eng.reset();
@@ -883,6 +1123,15 @@ int sphx_create(const sphx_params* params, void* stream, sphx_ctx** out)
     }
     *out = ctx.release();
     return SPHX_OK;
+}
+
+extern "C" {
+
+int sphx_create(const sphx_params* params, void* stream, sphx_ctx** out) { return create_impl(params, 1, stream, out); }
+
+int sphx_create_batch(const sphx_params* params, int32_t n_cases, void* stream, sphx_ctx** out)
+{
+    return create_impl(params, n_cases, stream, out);
 }
 
 void sphx_destroy(sphx_ctx* ctx)
@@ -903,14 +1152,27 @@ const char* sphx_last_error(const sphx_ctx* ctx) { return ctx ? ctx->err.c_str()
         return ctx->eng->expr;          \
     } while (0)
 
+int sphx_num_cases(const sphx_ctx* ctx) { return ctx ? ctx->eng->ncases() : SPHX_EINVAL; }
+
 int sphx_set_fluid(sphx_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* rho, const double* drho)
 {
-    ENG_CALL(set_fluid(n, pos, vel, rho, drho));
+    ENG_CALL(set_fluid(0, n, pos, vel, rho, drho));
+}
+
+int sphx_set_fluid_case(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* vel, const double* rho,
+                        const double* drho)
+{
+    ENG_CALL(set_fluid(c, n, pos, vel, rho, drho));
 }
 
 int sphx_set_walls(sphx_ctx* ctx, int64_t n, const double* pos, const double* normal)
 {
-    ENG_CALL(set_walls(n, pos, normal));
+    ENG_CALL(set_walls(0, n, pos, normal));
+}
+
+int sphx_set_walls_case(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* normal)
+{
+    ENG_CALL(set_walls(c, n, pos, normal));
 }
 
 int sphx_build_neighbors(sphx_ctx* ctx) { ENG_CALL(build_neighbors()); }
@@ -918,16 +1180,33 @@ int sphx_build_neighbors(sphx_ctx* ctx) { ENG_CALL(build_neighbors()); }
 int sphx_get_neighbors(sphx_ctx* ctx, int kind, int64_t* off, int64_t* idx, int64_t cap, int64_t* n_out)
 {
     if (ctx && kind != SPHX_INNER && kind != SPHX_CONTACT) return ctx->fail(SPHX_EINVAL, "bad neighbour kind");
-    ENG_CALL(get_neighbors(kind, off, idx, cap, n_out));
+    ENG_CALL(get_neighbors(0, kind, off, idx, cap, n_out));
+}
+
+int sphx_get_neighbors_case(sphx_ctx* ctx, int32_t c, int kind, int64_t* off, int64_t* idx, int64_t cap,
+                            int64_t* n_out)
+{
+    if (ctx && kind != SPHX_INNER && kind != SPHX_CONTACT) return ctx->fail(SPHX_EINVAL, "bad neighbour kind");
+    ENG_CALL(get_neighbors(c, kind, off, idx, cap, n_out));
 }
 
 int sphx_density_reinit(sphx_ctx* ctx) { ENG_CALL(density_reinit()); }
 
-int sphx_time_steps(sphx_ctx* ctx, double* dt_ad, double* dt_ac) { ENG_CALL(time_steps(dt_ad, dt_ac)); }
+int sphx_time_steps(sphx_ctx* ctx, double* dt_ad, double* dt_ac) { ENG_CALL(time_steps(0, dt_ad, dt_ac)); }
+
+int sphx_time_steps_case(sphx_ctx* ctx, int32_t c, double* dt_ad, double* dt_ac)
+{
+    ENG_CALL(time_steps(c, dt_ad, dt_ac));
+}
 
 int sphx_compute_rates(sphx_ctx* ctx, double dt, double* dvdt, double* drhodt)
 {
-    ENG_CALL(compute_rates(dt, dvdt, drhodt));
+    ENG_CALL(compute_rates(0, dt, dvdt, drhodt));
+}
+
+int sphx_compute_rates_case(sphx_ctx* ctx, int32_t c, double dt, double* dvdt, double* drhodt)
+{
+    ENG_CALL(compute_rates(c, dt, dvdt, drhodt));
 }
 
 int sphx_advance(sphx_ctx* ctx, int32_t n_steps, double t_stop, int64_t* n_substeps, double* t_out)
@@ -935,12 +1214,22 @@ int sphx_advance(sphx_ctx* ctx, int32_t n_steps, double t_stop, int64_t* n_subst
     ENG_CALL(advance(n_steps, t_stop, n_substeps, t_out));
 }
 
-int sphx_get_field(sphx_ctx* ctx, int field, double* out) { ENG_CALL(get_field(field, out)); }
+int sphx_case_status(sphx_ctx* ctx, int32_t c) { ENG_CALL(case_status(c)); }
 
-int sphx_diagnostics(sphx_ctx* ctx, sphx_diag* out) { ENG_CALL(diagnostics(out)); }
+int sphx_get_field(sphx_ctx* ctx, int field, double* out) { ENG_CALL(get_field(0, field, out)); }
+
+int sphx_get_field_case(sphx_ctx* ctx, int32_t c, int field, double* out) { ENG_CALL(get_field(c, field, out)); }
+
+int sphx_diagnostics(sphx_ctx* ctx, sphx_diag* out) { ENG_CALL(diagnostics(0, out)); }
+
+int sphx_diagnostics_case(sphx_ctx* ctx, int32_t c, sphx_diag* out) { ENG_CALL(diagnostics(c, out)); }
 
 int sphx_profile(sphx_ctx* ctx, int32_t reps, double* ms) { ENG_CALL(profile(reps, ms)); }
 
-int sphx_counts(sphx_ctx* ctx, int64_t* out) { ENG_CALL(counts(out)); }
+int sphx_counts(sphx_ctx* ctx, int64_t* out) { ENG_CALL(counts(-1, out)); }
+
+int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out) { ENG_CALL(counts(c, out)); }
+
+int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes) { ENG_CALL(autotune(reps, lanes)); }
 
 }  // extern "C"

@@ -24,10 +24,12 @@ SPHX_FIELD_POS, SPHX_FIELD_VEL, SPHX_FIELD_RHO, SPHX_FIELD_P, SPHX_FIELD_DRHO = 
 ERROR_NAMES = {SPHX_EINVAL: "EINVAL", SPHX_ENOMEM: "ENOMEM", SPHX_EHIP: "EHIP", SPHX_EESCAPE: "EESCAPE",
                SPHX_ENAN: "ENAN", SPHX_ECAP: "ECAP", SPHX_EOVERFLOW: "EOVERFLOW", SPHX_ESTATE: "ESTATE"}
 
-EXPORTED = ("sphx_create", "sphx_destroy", "sphx_last_error", "sphx_set_fluid", "sphx_set_walls",
-            "sphx_build_neighbors", "sphx_get_neighbors", "sphx_density_reinit", "sphx_time_steps",
-            "sphx_compute_rates", "sphx_advance", "sphx_get_field", "sphx_diagnostics", "sphx_profile",
-            "sphx_counts")
+EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_destroy", "sphx_last_error",
+            "sphx_set_fluid", "sphx_set_fluid_case", "sphx_set_walls", "sphx_set_walls_case",
+            "sphx_build_neighbors", "sphx_get_neighbors", "sphx_get_neighbors_case", "sphx_density_reinit",
+            "sphx_time_steps", "sphx_time_steps_case", "sphx_compute_rates", "sphx_compute_rates_case",
+            "sphx_advance", "sphx_case_status", "sphx_get_field", "sphx_get_field_case", "sphx_diagnostics",
+            "sphx_diagnostics_case", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune")
 
 
 class SphxError(RuntimeError):
@@ -65,36 +67,41 @@ def load(path=None):
     L = C.CDLL(p)
     vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     pd, pi64 = C.POINTER(C.c_double), C.POINTER(C.c_int64)
-    L.sphx_create.restype = C.c_int
-    L.sphx_create.argtypes = [C.POINTER(sphx_params), vp, C.POINTER(vp)]
+    sig = {
+        "sphx_create": [C.POINTER(sphx_params), vp, C.POINTER(vp)],
+        "sphx_create_batch": [C.POINTER(sphx_params), i32, vp, C.POINTER(vp)],
+        "sphx_num_cases": [vp],
+        "sphx_set_fluid": [vp, i64, vp, vp, vp, vp],
+        "sphx_set_fluid_case": [vp, i32, i64, vp, vp, vp, vp],
+        "sphx_set_walls": [vp, i64, vp, vp],
+        "sphx_set_walls_case": [vp, i32, i64, vp, vp],
+        "sphx_build_neighbors": [vp],
+        "sphx_get_neighbors": [vp, C.c_int, vp, vp, i64, pi64],
+        "sphx_get_neighbors_case": [vp, i32, C.c_int, vp, vp, i64, pi64],
+        "sphx_density_reinit": [vp],
+        "sphx_time_steps": [vp, pd, pd],
+        "sphx_time_steps_case": [vp, i32, pd, pd],
+        "sphx_compute_rates": [vp, d, vp, vp],
+        "sphx_compute_rates_case": [vp, i32, d, vp, vp],
+        "sphx_advance": [vp, i32, d, pi64, pd],
+        "sphx_case_status": [vp, i32],
+        "sphx_get_field": [vp, C.c_int, vp],
+        "sphx_get_field_case": [vp, i32, C.c_int, vp],
+        "sphx_diagnostics": [vp, C.POINTER(sphx_diag)],
+        "sphx_diagnostics_case": [vp, i32, C.POINTER(sphx_diag)],
+        "sphx_profile": [vp, i32, pd],
+        "sphx_counts": [vp, pi64],
+        "sphx_counts_case": [vp, i32, pi64],
+        "sphx_autotune": [vp, i32, C.POINTER(i32)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.restype = C.c_int
+        f.argtypes = args
     L.sphx_destroy.restype = None
     L.sphx_destroy.argtypes = [vp]
     L.sphx_last_error.restype = C.c_char_p
     L.sphx_last_error.argtypes = [vp]
-    L.sphx_set_fluid.restype = C.c_int
-    L.sphx_set_fluid.argtypes = [vp, i64, vp, vp, vp, vp]
-    L.sphx_set_walls.restype = C.c_int
-    L.sphx_set_walls.argtypes = [vp, i64, vp, vp]
-    L.sphx_build_neighbors.restype = C.c_int
-    L.sphx_build_neighbors.argtypes = [vp]
-    L.sphx_get_neighbors.restype = C.c_int
-    L.sphx_get_neighbors.argtypes = [vp, C.c_int, vp, vp, i64, pi64]
-    L.sphx_density_reinit.restype = C.c_int
-    L.sphx_density_reinit.argtypes = [vp]
-    L.sphx_time_steps.restype = C.c_int
-    L.sphx_time_steps.argtypes = [vp, pd, pd]
-    L.sphx_compute_rates.restype = C.c_int
-    L.sphx_compute_rates.argtypes = [vp, d, vp, vp]
-    L.sphx_advance.restype = C.c_int
-    L.sphx_advance.argtypes = [vp, i32, d, pi64, pd]
-    L.sphx_get_field.restype = C.c_int
-    L.sphx_get_field.argtypes = [vp, C.c_int, vp]
-    L.sphx_diagnostics.restype = C.c_int
-    L.sphx_diagnostics.argtypes = [vp, C.POINTER(sphx_diag)]
-    L.sphx_profile.restype = C.c_int
-    L.sphx_profile.argtypes = [vp, i32, pd]
-    L.sphx_counts.restype = C.c_int
-    L.sphx_counts.argtypes = [vp, pi64]
     if path is None:
         _lib = L
     return L
@@ -125,21 +132,30 @@ def params_from_case(case, precision=None, nsub_queue=0, sigma0=0.0):
 
 
 class Simulation:
-    """One library context: a fluid body and a static wall body."""
+    """One library context: a batch of cases (one by default), each a fluid
+    body and a static wall body. Per-case methods take `case` (default 0)."""
 
     def __init__(self, params, stream=None, lib=None):
         self._L = lib or load()
-        self.params = params
-        self.dim = params.dim
+        plist = list(params) if isinstance(params, (list, tuple)) else [params]
+        self.params = plist[0]
+        self.dim = plist[0].dim
+        self.n_cases = len(plist)
         h = C.c_void_p()
         s = None
         if stream is not None:
             s = getattr(stream, "cuda_stream", stream) or None
-        rc = self._L.sphx_create(C.byref(params), s, C.byref(h))
+        if len(plist) == 1:
+            rc = self._L.sphx_create(C.byref(plist[0]), s, C.byref(h))
+            what = "sphx_create"
+        else:
+            arr = (sphx_params * len(plist))(*plist)
+            rc = self._L.sphx_create_batch(arr, len(plist), s, C.byref(h))
+            what = "sphx_create_batch"
         if rc != SPHX_OK:
-            raise SphxError(rc, "sphx_create")
+            raise SphxError(rc, what)
         self._h = h
-        self.nf = 0
+        self.nf = [0] * self.n_cases
 
     @classmethod
     def from_case(cls, case, precision=None, nsub_queue=0, stream=None, with_walls=True):
@@ -147,6 +163,16 @@ class Simulation:
         sim.set_fluid(case.fluid_pos)
         if with_walls and case.n_wall:
             sim.set_walls(case.wall_pos, case.wall_normal)
+        return sim
+
+    @classmethod
+    def from_cases(cls, cases, precision=None, nsub_queue=0, stream=None, with_walls=True):
+        """A batch of several cases in one context (same dim and precision)."""
+        sim = cls([params_from_case(c, precision, nsub_queue) for c in cases], stream=stream)
+        for k, c in enumerate(cases):
+            sim.set_fluid(c.fluid_pos, case=k)
+            if with_walls and c.n_wall:
+                sim.set_walls(c.wall_pos, c.wall_normal, case=k)
         return sim
 
     def close(self):
@@ -165,61 +191,79 @@ class Simulation:
             msg = self._L.sphx_last_error(self._h)
             raise SphxError(rc, what, msg.decode() if msg else "")
 
-    def set_fluid(self, pos, vel=None, rho=None, drho=None):
+    def set_fluid(self, pos, vel=None, rho=None, drho=None, case=0):
         pos, vel, rho, drho = _f64(pos), _f64(vel), _f64(rho), _f64(drho)
-        self._check(self._L.sphx_set_fluid(self._h, pos.shape[0], _ptr(pos), _ptr(vel), _ptr(rho), _ptr(drho)),
-                    "sphx_set_fluid")
-        self.nf = pos.shape[0]
+        self._check(self._L.sphx_set_fluid_case(self._h, case, pos.shape[0], _ptr(pos), _ptr(vel), _ptr(rho),
+                                                _ptr(drho)), "sphx_set_fluid_case")
+        self.nf[case] = pos.shape[0]
 
-    def set_walls(self, pos, normal):
+    def set_walls(self, pos, normal, case=0):
         pos, normal = _f64(pos), _f64(normal)
-        self._check(self._L.sphx_set_walls(self._h, pos.shape[0], _ptr(pos), _ptr(normal)), "sphx_set_walls")
+        self._check(self._L.sphx_set_walls_case(self._h, case, pos.shape[0], _ptr(pos), _ptr(normal)),
+                    "sphx_set_walls_case")
 
     def build_neighbors(self):
         self._check(self._L.sphx_build_neighbors(self._h), "sphx_build_neighbors")
 
-    def get_neighbors(self, kind=SPHX_INNER):
+    def get_neighbors(self, kind=SPHX_INNER, case=0):
         n = C.c_int64()
-        off = np.zeros(self.nf + 1, dtype=np.int64)
-        self._check(self._L.sphx_get_neighbors(self._h, kind, _ptr(off), None, 0, C.byref(n)), "sphx_get_neighbors")
+        off = np.zeros(self.nf[case] + 1, dtype=np.int64)
+        self._check(self._L.sphx_get_neighbors_case(self._h, case, kind, _ptr(off), None, 0, C.byref(n)),
+                    "sphx_get_neighbors_case")
         idx = np.zeros(max(n.value, 1), dtype=np.int64)
-        self._check(self._L.sphx_get_neighbors(self._h, kind, None, _ptr(idx), n.value, C.byref(n)),
-                    "sphx_get_neighbors")
+        self._check(self._L.sphx_get_neighbors_case(self._h, case, kind, None, _ptr(idx), n.value, C.byref(n)),
+                    "sphx_get_neighbors_case")
         return off, idx[:n.value]
 
     def density_reinit(self):
         self._check(self._L.sphx_density_reinit(self._h), "sphx_density_reinit")
 
-    def time_steps(self):
+    def time_steps(self, case=0):
         a, b = C.c_double(), C.c_double()
-        self._check(self._L.sphx_time_steps(self._h, C.byref(a), C.byref(b)), "sphx_time_steps")
+        self._check(self._L.sphx_time_steps_case(self._h, case, C.byref(a), C.byref(b)), "sphx_time_steps_case")
         return a.value, b.value
 
-    def compute_rates(self, dt):
-        dvdt = np.zeros((self.nf, self.dim), dtype=np.float64)
-        drho = np.zeros(self.nf, dtype=np.float64)
-        self._check(self._L.sphx_compute_rates(self._h, float(dt), _ptr(dvdt), _ptr(drho)), "sphx_compute_rates")
+    def compute_rates(self, dt, case=0):
+        dvdt = np.zeros((self.nf[case], self.dim), dtype=np.float64)
+        drho = np.zeros(self.nf[case], dtype=np.float64)
+        self._check(self._L.sphx_compute_rates_case(self._h, case, float(dt), _ptr(dvdt), _ptr(drho)),
+                    "sphx_compute_rates_case")
         return dvdt, drho
 
     def advance(self, n_steps=1, t_stop=float("inf")):
+        """Advance every case; returns the acoustic sub-steps done (summed
+        over the cases)."""
         n = C.c_int64()
         t = C.c_double()
         self._check(self._L.sphx_advance(self._h, int(n_steps), float(t_stop), C.byref(n), C.byref(t)),
                     "sphx_advance")
         return n.value
 
-    def get_field(self, which):
-        shape = (self.nf, self.dim) if which in (SPHX_FIELD_POS, SPHX_FIELD_VEL) else (self.nf,)
+    def case_status(self, case):
+        return self._L.sphx_case_status(self._h, case)
+
+    def get_field(self, which, case=0):
+        nf = self.nf[case]
+        shape = (nf, self.dim) if which in (SPHX_FIELD_POS, SPHX_FIELD_VEL) else (nf,)
         out = np.zeros(shape, dtype=np.float64)
-        self._check(self._L.sphx_get_field(self._h, which, _ptr(out)), "sphx_get_field")
+        self._check(self._L.sphx_get_field_case(self._h, case, which, _ptr(out)), "sphx_get_field_case")
         return out
 
-    def diagnostics(self):
-        d = sphx_diag()
-        self._check(self._L.sphx_diagnostics(self._h, C.byref(d)), "sphx_diagnostics")
+    @staticmethod
+    def _diag_dict(d):
         return dict(mass=d.mass, momentum=np.array(d.momentum[:]), e_kin=d.e_kin, e_pot=d.e_pot,
                     e_int=d.e_int, front=d.front, max_drho=d.max_drho, t=d.t, n_substeps=d.n_substeps,
                     n_steps=d.n_steps)
+
+    def diagnostics(self, case=0):
+        d = sphx_diag()
+        self._check(self._L.sphx_diagnostics_case(self._h, case, C.byref(d)), "sphx_diagnostics_case")
+        return self._diag_dict(d)
+
+    def diagnostics_all(self):
+        arr = (sphx_diag * self.n_cases)()
+        self._check(self._L.sphx_diagnostics_case(self._h, -1, arr), "sphx_diagnostics_case")
+        return [self._diag_dict(d) for d in arr]
 
     @property
     def t(self):
@@ -230,7 +274,15 @@ class Simulation:
         self._check(self._L.sphx_profile(self._h, int(reps), ms), "sphx_profile")
         return dict(pressure=ms[0], density=ms[1], neighbors=ms[2], reinit=ms[3])
 
-    def counts(self):
+    def counts(self, case=None):
         out = (C.c_int64 * 4)()
-        self._check(self._L.sphx_counts(self._h, out), "sphx_counts")
+        if case is None:
+            self._check(self._L.sphx_counts(self._h, out), "sphx_counts")
+        else:
+            self._check(self._L.sphx_counts_case(self._h, case, out), "sphx_counts_case")
         return dict(fluid=out[0], wall=out[1], inner_pairs=out[2], contact_pairs=out[3])
+
+    def autotune(self, reps=10):
+        lanes = C.c_int32()
+        self._check(self._L.sphx_autotune(self._h, int(reps), C.byref(lanes)), "sphx_autotune")
+        return lanes.value

@@ -229,8 +229,8 @@ def test_runs_are_deterministic():
 
 
 def test_short_substep_queue_gives_identical_results():
-    """An advection step that needs more sub-steps than the graph queues is
-    finished from the host: same arithmetic, same bits."""
+    """An advection step that needs more sub-steps than one graph launch
+    queues continues in the next launch: same arithmetic, same bits."""
     case = wl.config_small(4)
     res = []
     for q in (2, 0):
