@@ -95,28 +95,36 @@ def cpu_baseline(case, budget_s=15.0):
 
 
 def cpu_baseline_ensemble(cases, budget_s=15.0):
-    """The FP64 oracle on the ensemble's cases one after another, one
-    advection step each from t=0 (configuration build included), until the
-    time budget is spent."""
+    """The FP64 oracle on the ensemble's cases from t=0: every case's
+    configuration is built, then the cases take advection steps in turn,
+    one step each per round, until the time budget is spent."""
     import oracle as O
     t0 = time.perf_counter()
-    work = 0
-    nsub = 0
-    used = 0
+    orcs = []
     for c in cases:
-        if time.perf_counter() - t0 >= budget_s:
-            break
         o = O.Oracle(c)
         o.build_config()
-        n = o.advance(1e9)
-        o.close()
-        work += c.n_fluid * n
-        nsub += n
-        used += 1
+        orcs.append(o)
+    work = 0
+    nsub = 0
+    rounds = 0
+    done = 0
+    while time.perf_counter() - t0 < budget_s:
+        for c, o in zip(cases, orcs):
+            n = o.advance(1e9)
+            work += c.n_fluid * n
+            nsub += n
+            done += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        rounds += 1
     wall = time.perf_counter() - t0
+    for o in orcs:
+        o.close()
     return {"value": work / wall / 1e6, "unit": "M particle-steps/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"first advection step ({nsub} acoustic sub-steps in all) of the first {used} of "
-                      f"{len(cases)} ensemble cases from t=0, one after another, {wall:.1f} s, FP64 oracle, OpenMP"}
+            "sample": f"{done} advection steps ({nsub} acoustic sub-steps) over the {len(cases)} ensemble cases "
+                      f"from t=0, round robin ({rounds} rounds), configuration builds included, {wall:.1f} s, "
+                      f"FP64 oracle, OpenMP"}
 
 
 def main():

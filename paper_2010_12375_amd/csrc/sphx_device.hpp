@@ -551,6 +551,9 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
     bnrm[s] = nn;
 }
 
+// Compile-time body selector of the neighbour build (0 fluid, 1 wall).
+template <int B> struct BodyTag { static constexpr int value = B; };
+
 // ---------------------------------------------------------------------
 // S2: neighbour configuration. For each fluid particle scan the 3^d cells
 // around its cell in the fluid and wall cell lists and keep j != i with
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     using G = typename GeoSel<D, real>::T;
     constexpr bool PREFILTER = sizeof(real) == 4;
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const KP<real>& P = Pt[tcase[b]];
+    const KP<real> P = Pt[tcase[b]];  // a copy: the fields stay in registers through the loops
     Ctrl* ctrl = ctrl_all + P.case_id;
     if (!full_update(ctrl, force) || ctrl->err) return;
     const int i = b * TILE + (int)threadIdx.x / TB;
@@ -599,19 +602,22 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const float rc2f = (float)P.rc2;
     const int kc = cell[i] - P.cbase;
     const int ci[3] = {kc % P.n[0], (kc / P.n[0]) % P.n[1], kc / (P.n[0] * P.n[1])};
-    int cnt_[2] = {0, 0};
+    int cnt_f = 0, cnt_w = 0;
     uint32_t over = 0;
 
-    // Scan candidates [j0, j1) of one body; cell offset in x from the
-    // range boundaries b1, b2 (first candidate of the 2nd and 3rd cell).
-    auto scan = [&](int body, int j0, int j1, int b1, int b2, int dcx0, uint32_t tag_yz) {
-        const G* csrc = body ? wgeo : geo;
-        const double* bx0 = body ? wx0 : x0;
-        const double* bx1 = body ? wx1 : x1;
-        const double* bx2 = body ? wx2 : x2;
-        uint32_t* out = body ? wnb : nbr;
-        const int mx = body ? P.maxw : P.maxn;
-        int& nn = cnt_[body];
+    // Scan candidates [j0, j1) of one body (fluid: BODY 0, wall: BODY 1, a
+    // compile-time constant so that every choice below is static); cell
+    // offset in x from the range boundaries b1, b2 (first candidate of the
+    // 2nd and 3rd cell).
+    auto scan = [&](auto bodyc, int j0, int j1, int b1, int b2, int dcx0, uint32_t tag_yz) {
+        constexpr int BODY = decltype(bodyc)::value;
+        const G* csrc = BODY ? wgeo : geo;
+        const double* bx0 = BODY ? wx0 : x0;
+        const double* bx1 = BODY ? wx1 : x1;
+        const double* bx2 = BODY ? wx2 : x2;
+        uint32_t* out = BODY ? wnb : nbr;
+        const int mx = BODY ? P.maxw : P.maxn;
+        int& nn = BODY ? cnt_w : cnt_f;
         // BATCH rounds per iteration: all candidate loads first, then the
         // tests and ballots in candidate order
         for (int jb = j0; jb < j1; jb += TB * BATCH) {
@@ -636,7 +642,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
                 const int j = jb + u * TB + l;
                 const int dcx = dcx0 + (j >= b1) + (j >= b2);
                 bool in = false;
-                if (j < j1 && (body || j != i)) {
+                if (j < j1 && (BODY || j != i)) {
                     if constexpr (PREFILTER) {
                         float dx = (float)((oi.x - oj[u].x) - (real)dcx * P.L[0]);
                         float dy = (float)((oi.y - oj[u].y) - (real)((int)((tag_yz >> 2) & 3u) - 1) * P.L[1]);
@@ -669,6 +675,27 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
         }
     };
 
+    // One stencil row (three x-adjacent cells) of one body.
+    auto row = [&](auto bodyc, int rowc, uint32_t tag_yz) {
+        constexpr int BODY = decltype(bodyc)::value;
+        const int32_t* st_ = BODY ? wstart : fstart;
+        const int lim = BODY ? wend : fend;
+        if (ci[0] >= 1 && ci[0] + 1 < P.n[0]) {
+            // the three cells are contiguous: one range
+            const int c = rowc + ci[0];
+            scan(bodyc, min(st_[c - 1], lim), min(st_[c + 2], lim), min(st_[c], lim), min(st_[c + 1], lim), -1,
+                 tag_yz);
+        } else {
+            for (int dx = -1; dx <= 1; ++dx) {
+                int cx = ci[0] + dx;
+                if (P.periodic[0]) cx = cx < 0 ? cx + P.n[0] : (cx >= P.n[0] ? cx - P.n[0] : cx);
+                else if (cx < 0 || cx >= P.n[0]) continue;
+                const int c = rowc + cx;
+                scan(bodyc, min(st_[c], lim), min(st_[c + 1], lim), 0x7fffffff, 0x7fffffff, dx, tag_yz);
+            }
+        }
+    };
+
     const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
         int cz = ci[2] + dz;
@@ -682,29 +709,13 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
             else if (cy < 0 || cy >= P.n[1]) continue;
             const int rowc = P.cbase + P.n[0] * (cy + P.n[1] * cz);
             const uint32_t tag_yz = ((uint32_t)(dy + 1) << 2) | ((uint32_t)(dz + 1) << 4);
-            for (int body = 0; body < (P.nw > 0 ? 2 : 1); ++body) {
-                const int32_t* st_ = body ? wstart : fstart;
-                const int lim = body ? wend : fend;
-                if (ci[0] >= 1 && ci[0] + 1 < P.n[0]) {
-                    // the three cells are contiguous: one range
-                    const int c = rowc + ci[0];
-                    scan(body, min(st_[c - 1], lim), min(st_[c + 2], lim), min(st_[c], lim), min(st_[c + 1], lim), -1,
-                         tag_yz);
-                } else {
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        int cx = ci[0] + dx;
-                        if (P.periodic[0]) cx = cx < 0 ? cx + P.n[0] : (cx >= P.n[0] ? cx - P.n[0] : cx);
-                        else if (cx < 0 || cx >= P.n[0]) continue;
-                        const int c = rowc + cx;
-                        scan(body, min(st_[c], lim), min(st_[c + 1], lim), 0x7fffffff, 0x7fffffff, dx, tag_yz);
-                    }
-                }
-            }
+            row(BodyTag<0>{}, rowc, tag_yz);
+            if (P.nw > 0) row(BodyTag<1>{}, rowc, tag_yz);
         }
     }
     if (l == 0) {
-        ncnt[i] = cnt_[0] < P.maxn ? cnt_[0] : P.maxn;
-        wcnt[i] = cnt_[1] < P.maxw ? cnt_[1] : P.maxw;
+        ncnt[i] = cnt_f < P.maxn ? cnt_f : P.maxn;
+        wcnt[i] = cnt_w < P.maxw ? cnt_w : P.maxw;
     }
     if (over) atomicOr(&ctrl->err, ERR_NBR_OVERFLOW);
 }
@@ -861,7 +872,7 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
     const int32_t* __restrict__ wcnt, R4<real>* __restrict__ st)
 {
     const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
-    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
     const Ctrl* ctrl = ctrl_all + P.case_id;
     if (gate && (!ctrl->ss[0].active || ctrl->midstep || ctrl->err)) return;
     const int i = i0 + (int)threadIdx.x / T;
@@ -903,7 +914,7 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all)
 {
     const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
-    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
     Ctrl* ctrl = ctrl_all + P.case_id;
     unsigned long long* vslot = vslot_all + (size_t)P.case_id * 2 * VSLOTS;
     // Sub-step q: with `adv`, first close sub-step q - 1 (every block of the
@@ -1048,7 +1059,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
 {
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i0 = pair_block_first<T>(b);
-    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
     Ctrl* ctrl = ctrl_all + P.case_id;
     const SubState S = ctrl->ss[q & 1];
     if (!S.active || ctrl->err) return;

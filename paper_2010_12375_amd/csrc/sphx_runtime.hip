@@ -113,6 +113,12 @@ struct Engine final : EngineBase {
     R4<real>* bk_st = nullptr;
     real* bk_dr = nullptr;
     double* bk_x[3] = {};
+    // fluid given before the first device layout, per case (uploaded together)
+    struct Pending {
+        bool has = false;
+        std::vector<double> pos, vel, rho, drho;
+    };
+    std::vector<Pending> pend;
     // walls (static), all cases concatenated
     int nw_tot = 0;
     std::vector<std::vector<double>> wpos_h, wnrm_h;  // per case, as given
@@ -267,6 +273,7 @@ struct Engine final : EngineBase {
         maxn = D == 2 ? 48 : 128;
         maxw = D == 2 ? 32 : 96;
         hP.resize(C);
+        pend.assign(C, Pending{});
         wpos_h.assign(C, {});
         wnrm_h.assign(C, {});
         int cbase = 0;
@@ -359,13 +366,13 @@ struct Engine final : EngineBase {
     }
 
     // ------------------------------------------------------------------
-    // Layout: case c gets fcap = n rounded up to whole tiles, the others
-    // keep theirs; the state of every other case moves to its new slots.
-    int relayout(int c_new, int n_new)
+    // Layout: every case owns hP[c].fcap slots (whole tiles), in case order.
+    // With `keep`, the state of every case in the old layout moves to its
+    // new slots (case `skip` excepted).
+    int layout(bool keep, int skip)
     {
         HIPCHK(hipStreamSynchronize(s));
         std::vector<KP<real>> old = hP;
-        int old_cur = cur;
         double* ox[3] = {x[cur][0], x[cur][1], x[cur][2]};
         R4<real>* ost = st[cur];
         real* odr = dr3[cur];
@@ -373,16 +380,10 @@ struct Engine final : EngineBase {
         int32_t* ocell = cell[cur];
         std::vector<void*> old_allocs;
         old_allocs.swap(fluid_allocs);
-        (void)old_cur;
         int base = 0;
         for (int c = 0; c < C; ++c) {
-            KP<real>& P = hP[c];
-            if (c == c_new) {
-                P.nf = n_new;
-                P.fcap = round_tile(n_new);
-            }
-            P.fbase = base;
-            base += P.fcap;
+            hP[c].fbase = base;
+            base += hP[c].fcap;
         }
         ntot = base;
         ntiles = ntot / TILE;
@@ -394,9 +395,9 @@ struct Engine final : EngineBase {
             return rc;
         }
         cur = 0;
-        if (laid_out) {
+        if (keep && laid_out) {
             for (int c = 0; c < C; ++c) {
-                if (c == c_new || old[c].nf == 0) continue;
+                if (c == skip || old[c].nf == 0) continue;
                 size_t n = (size_t)old[c].nf, o = (size_t)old[c].fbase, d = (size_t)hP[c].fbase;
                 for (int k = 0; k < D; ++k)
                     HIPCHK(hipMemcpyAsync(x[0][k] + d, ox[k] + o, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -415,6 +416,23 @@ struct Engine final : EngineBase {
         RETCHK(upload_params());
         laid_out = true;
         configured = false;
+        return SPHX_OK;
+    }
+
+    // The first device layout: every case at the size of the fluid given so
+    // far, all of it uploaded at once.
+    int ensure_layout()
+    {
+        if (laid_out) return SPHX_OK;
+        for (int c = 0; c < C; ++c) hP[c].fcap = round_tile(hP[c].nf);
+        RETCHK(layout(false, -1));
+        for (int c = 0; c < C; ++c) {
+            Pending& p = pend[c];
+            if (p.has && hP[c].nf > 0)
+                RETCHK(load_case(c, hP[c].nf, p.pos.data(), p.vel.empty() ? nullptr : p.vel.data(),
+                                 p.rho.empty() ? nullptr : p.rho.data(), p.drho.empty() ? nullptr : p.drho.data()));
+            p = Pending{};
+        }
         return SPHX_OK;
     }
 
@@ -472,17 +490,43 @@ struct Engine final : EngineBase {
         RETCHK(check_case(c));
         if (n < 0 || (n > 0 && !pos) || n > (int64_t)NBR_MASK / 2)
             return ctx->fail(SPHX_EINVAL, "bad fluid particle count or positions");
-        HIPCHK(hipStreamSynchronize(s));
-        long long others = (long long)ntot - hP[c].fcap;
+        long long others = 0;
+        for (int d = 0; d < C; ++d)
+            if (d != c) others += laid_out ? hP[d].fcap : round_tile(hP[d].nf);
         if (others + round_tile(n) > (long long)NBR_MASK) return ctx->fail(SPHX_EINVAL, "too many particles in the batch");
-        if (!laid_out || round_tile(n) > hP[c].fcap) {
-            RETCHK(relayout(c, (int)n));
-        } else {
+        if (!laid_out) {
+            // kept on the host until the first call that needs the device
+            Pending& p = pend[c];
+            p.has = true;
+            const size_t nn = (size_t)n;
+            p.pos.assign(pos, pos + nn * D);
+            if (vel) p.vel.assign(vel, vel + nn * D);
+            else p.vel.clear();
+            if (rho) p.rho.assign(rho, rho + nn);
+            else p.rho.clear();
+            if (drho) p.drho.assign(drho, drho + nn);
+            else p.drho.clear();
             hP[c].nf = (int)n;
+            std::memset(&hctrl[c], 0, sizeof(Ctrl));
+            configured = false;
+            return SPHX_OK;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        hP[c].nf = (int)n;
+        if (round_tile(n) > hP[c].fcap) {
+            hP[c].fcap = round_tile(n);
+            RETCHK(layout(true, c));
+        } else {
             RETCHK(upload_params());
             configured = false;
         }
-        // stage: pos | vel | rho | drho
+        return load_case(c, n, pos, vel, rho, drho);
+    }
+
+    // Load case c's fluid (n particles, original order) into its slots of the
+    // current set; reset its clock and counters and take its |v|max.
+    int load_case(int c, int64_t n, const double* pos, const double* vel, const double* rho, const double* drho)
+    {
         size_t nn = (size_t)n;
         RETCHK(ensure_stage(nn * (2 * D + 2)));
         double* dpos = stage;
@@ -711,6 +755,7 @@ struct Engine final : EngineBase {
     int build_neighbors() override
     {
         RETCHK(all_have_fluid());
+        RETCHK(ensure_layout());
         RETCHK(sync_ctrl());
         for (int c = 0; c < C; ++c) hctrl[c].err = 0;
         RETCHK(push_ctrl());
@@ -785,6 +830,7 @@ struct Engine final : EngineBase {
     {
         RETCHK(check_case(c));
         if (hP[c].nf == 0) return ctx->fail(SPHX_ESTATE, case_tag(c) + "no fluid particles");
+        RETCHK(ensure_layout());
         k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, c, ctrl, st[cur]);
         k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, c);
         HIPCHK(hipGetLastError());
@@ -918,6 +964,7 @@ struct Engine final : EngineBase {
     {
         RETCHK(check_case(c));
         if (which < 0 || which > 4 || !out) return ctx->fail(SPHX_EINVAL, "bad field");
+        RETCHK(ensure_layout());
         const KP<real>& P = hP[c];
         if (P.nf == 0) return SPHX_OK;
         k_unsort_field<D, real><<<nblk(P.nf), BLOCK, 0, s>>>(dP, c, which, id[cur], x[cur][0], x[cur][1], x[cur][2],
@@ -934,6 +981,7 @@ struct Engine final : EngineBase {
     {
         if (!out) return ctx->fail(SPHX_EINVAL, "NULL output");
         if (c >= C) return ctx->fail(SPHX_EINVAL, "case index out of range");
+        RETCHK(ensure_layout());
         std::vector<double> r((size_t)NDIAG * C, 0.0);
         if (ntiles > 0) {
             k_diag<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, x[cur][0], x[cur][1], x[cur][2], st[cur],
@@ -1035,6 +1083,7 @@ struct Engine final : EngineBase {
     {
         if (!out) return ctx->fail(SPHX_EINVAL, "NULL output");
         if (c >= C) return ctx->fail(SPHX_EINVAL, "case index out of range");
+        RETCHK(ensure_layout());
         out[0] = out[1] = out[2] = out[3] = 0;
         for (int d = 0; d < C; ++d)
             if (c < 0 || d == c) {
