@@ -108,6 +108,12 @@ int sphx_create_batch(const sphx_params* params, int32_t n_cases, void* stream, 
 /* Number of cases of the context (or SPHX_EINVAL for NULL). */
 int sphx_num_cases(const sphx_ctx* ctx);
 
+/* Replace case c's parameters (dim and precision unchanged) when its cell
+ * grid stays the same (same box, periodicity and cell count per axis); its
+ * particles, clock and walls stay. SPHX_EINVAL otherwise. Invalidates the
+ * neighbour configuration of the batch. */
+int sphx_set_params_case(sphx_ctx* ctx, int32_t c, const sphx_params* params);
+
 /* Free every device buffer, graph and the owned stream. NULL is a no-op. */
 void sphx_destroy(sphx_ctx* ctx);
 
@@ -224,6 +230,64 @@ int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out);
  * different order, so later results can differ from the default's at
  * rounding level. Requires a configuration. */
 int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes);
+
+/* ---------------------------------------------------------------------
+ * Message-passing surrogate (2D contexts only; SPHX_EINVAL in 3D).
+ *
+ * A network on the SPH neighbour graph of the current configuration (the
+ * inner and contact relations, Section 9) predicts for every fluid particle
+ * its mean acceleration and density rate over the next two advection steps
+ * (about ten acoustic sub-steps). Hidden width 64, three message-passing
+ * layers: node features v/u_ref, (rho - rho0)/(0.01 rho0), neighbour counts;
+ * edge features (x_j - x_i)/h, r/h, (v_j - v_i)/u_ref, W(r)/W(0), a wall
+ * flag, the pressure difference (p_j - p_i)/(rho0 |g| h) (the one-sided wall
+ * state for a wall); edge messages relu(P_i + Q_j + R_ij) (a learned vector in place of
+ * Q_j for wall edges) summed per particle; residual node updates; output
+ * (a_x/g, a_y/g, 1000 Drho h/(rho0 u_ref)). Matrix products take bfloat16
+ * operands and accumulate in FP32 (MFMA). Parameters are one flat float32
+ * array of sphx_gnn_num_params() values in this order, each matrix K x 64
+ * row-major (input dimension first): Wn[32x64] bn[64] We[32x64] be[64], then
+ * per layer Wa[64x64] Wb[64x64] Wc[64x64] bm[64] qw[64] Wu[128x64] bu[64],
+ * then Wo1[64x64] bo1[64] Wo2[64x3] bo2[3] (rows 8..31 of Wn and We multiply
+ * zero padding). One parameter set serves every case of the batch. The plain
+ * scheme stays the fallback whenever a case's predicted density deviates from
+ * rho0 by more than the caller's bound (1 % is the variation the sound speed
+ * is chosen for, Section 2.1). */
+
+int64_t sphx_gnn_num_params(void);
+
+/* Set the parameters (n == sphx_gnn_num_params()); resets Adam's moments. */
+int sphx_gnn_set_params(sphx_ctx* ctx, const float* params, int64_t n);
+
+/* Current parameters / the gradient of the last training step. */
+int sphx_gnn_get_params(sphx_ctx* ctx, float* params, int64_t n);
+int sphx_gnn_get_grad(sphx_ctx* ctx, float* grad, int64_t n);
+
+/* Predictions for every case on the current configuration (SPHX_ESTATE
+ * without one); sphx_gnn_get_output_case returns case c's, nf x 3 in
+ * original order, valid until the configuration or the parameters change. */
+int sphx_gnn_forward(sphx_ctx* ctx);
+int sphx_gnn_get_output_case(sphx_ctx* ctx, int32_t c, double* out);
+
+/* Training: targets of case c (nf x 3, original order, same scaling as the
+ * output), set on the current configuration (after sphx_build_neighbors;
+ * SPHX_ESTATE without one); sphx_gnn_train_step runs the forward and backward passes over
+ * every case (loss: mean squared error over all fluid particles and outputs)
+ * and one Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr.
+ * Every case needs a target set on the current configuration. */
+int sphx_gnn_set_target_case(sphx_ctx* ctx, int32_t c, const double* target);
+int sphx_gnn_train_step(sphx_ctx* ctx, double lr, double* loss);
+
+/* `windows` surrogate windows: each predicts every case's mean rates over
+ * dt = 2 dt_ad (from its current |v|max) and, for the cases whose predicted
+ * max |rho/rho0 - 1| stays <= max_drho, applies v += a dt, x += (v + v')/2 dt,
+ * rho += Drho dt, advances the clock by dt and the step count by 2 and updates
+ * the configuration; every other case takes the two advection steps with the
+ * plain scheme. plain_every > 0 also sends every plain_every-th window to the
+ * plain scheme. *n_fallback / *n_surrogate (may be NULL) count case-windows
+ * of each kind. Errors as for sphx_advance. */
+int sphx_surrogate_advance(sphx_ctx* ctx, int32_t windows, double max_drho, int32_t plain_every,
+                           int64_t* n_fallback, int64_t* n_surrogate);
 
 #ifdef __cplusplus
 }

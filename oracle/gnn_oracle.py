@@ -17,13 +17,20 @@ Network (hidden width 64, 3 message-passing layers):
     neighbour counts / 32 and / 16, zero-padded to 32;
   edge features g_e of e = (i -> j), j a fluid or a wall particle:
     (x_j - x_i)/h (2), r/h, (v_j - v_i)/u_ref (2; v_j = 0 for a wall),
-    W(r)/W(0), 1 for a wall edge, zero-padded to 32;
+    W(r)/W(0), 1 for a wall edge, the pressure difference
+    (p_j - p_i)/(rho0 |g| h) with p = c0^2 (rho - rho0) (for a wall the
+    one-sided wall state of Section 2.3, p_w - p_i = rho_i g.(x_w - x_i)),
+    zero-padded to 32; a difference taken before any rounding, since the
+    pressure gradient lives in density differences far below bf16
+    resolution of the density itself;
   H = relu(F Wn + bn),  E0 = relu(G We + be)
   layer l:  P = H Wa + bm,  Q = H Wb,  R = E0 Wc
             m_e = relu(P_i + Q_j + R_e)   (wall edge: qw in place of Q_j)
             A_i = sum of m_e over the edges of i
             H <- H + relu([H | A] Wu + bu)
-  decoder:  Y = relu(H Wo1 + bo1) Wo2 + bo2,  Y = (a_x/g, a_y/g, Drho h/(rho0 u_ref))
+  decoder:  Y = relu(H Wo1 + bo1) Wo2 + bo2,  Y = (a_x/g, a_y/g, 1000 Drho h/(rho0 u_ref))
+  (the density rate in units of 0.1 % of rho0 per h/u_ref, so that all three
+  outputs are of order one)
 With `emu`, every operand of every matrix product is rounded to bfloat16
 (round to nearest even) first, as the MFMA kernels take them, except the last
 product (D1 Wo2), which stays unrounded; sums are FP64 here.
@@ -106,7 +113,7 @@ def wendland_ratio(q):
 def features(graph, x, v, rho, xw, prm):
     """Node and edge features (float64, zero-padded to 32 columns).
     x, v: fluid positions and velocities at the configuration time; xw: wall
-    positions; prm: dict with h, rho0, u_ref."""
+    positions; prm: dict with h, rho0, u_ref, c0, gvec (gravity vector)."""
     n, h, u = graph.n, prm["h"], prm["u_ref"]
     F = np.zeros((n, FEAT_PAD))
     F[:, 0:2] = v[:, :2] / u
@@ -126,6 +133,13 @@ def features(graph, x, v, rho, xw, prm):
     G[:, 3:5] = (vj - v[graph.src, :2]) / u
     G[:, 5] = wendland_ratio(r / h)
     G[:, 6] = graph.wall.astype(float)
+    gvec = np.asarray(prm["gvec"], dtype=float)[:2]
+    gmag = float(np.linalg.norm(gvec))
+    rj = np.where(inner, rho[np.where(inner, graph.dst, 0)], 0.0)
+    ri = rho[graph.src]
+    dp_inner = prm["c0"] ** 2 * (rj - ri)
+    dp_wall = ri * (d @ gvec)
+    G[:, 7] = np.where(inner, dp_inner, dp_wall) / (prm["rho0"] * gmag * h)
     return F, G
 
 
@@ -227,7 +241,7 @@ def apply(Y, x, v, rho, dt, prm):
     """The surrogate's state update over dt from its predicted mean rates:
     v' = v + a dt, x' = x + (v + v')/2 dt, rho' = rho + Drho dt."""
     a = Y[:, 0:2] * prm["g"]
-    drho = Y[:, 2] * prm["rho0"] * prm["u_ref"] / prm["h"]
+    drho = Y[:, 2] * 1e-3 * prm["rho0"] * prm["u_ref"] / prm["h"]
     v2 = v.copy()
     v2[:, :2] = v[:, :2] + a * dt
     x2 = x.copy()

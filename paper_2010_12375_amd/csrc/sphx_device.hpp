@@ -1206,17 +1206,18 @@ __global__ __launch_bounds__(64) void k_step_end(const KP<real>* __restrict__ Pt
 }
 
 // ---------------------------------------------------------------------
-// |v|max of the current state of every case (only < 0) or of case `only`
-// (outside the time loop; one thread per slot).
+// |v|max of the current state of every case (only < 0) or of case `only`,
+// restricted to the cases with mask[c] != 0 if a mask is given (outside the
+// time loop; one thread per slot).
 template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_vmax(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
-                                                int ntiles, int only, Ctrl* __restrict__ ctrl_all,
-                                                const R4<real>* __restrict__ st)
+                                                int ntiles, int only, const int32_t* __restrict__ mask,
+                                                Ctrl* __restrict__ ctrl_all, const R4<real>* __restrict__ st)
 {
     const int tile = wave_tile();
     if (tile >= ntiles) return;
     const KP<real>& P = Pt[tcase[tile]];
-    if (only >= 0 && P.case_id != only) return;
+    if ((only >= 0 && P.case_id != only) || (mask && !mask[P.case_id])) return;
     const int i = tile * TILE + (threadIdx.x & 63);
     real sp = 0;
     if (i < P.fbase + P.nf) {
@@ -1228,10 +1229,10 @@ __global__ __launch_bounds__(BLOCK) void k_vmax(const KP<real>* __restrict__ Pt,
 }
 
 template <typename real>
-__global__ void k_vmax_fin(Ctrl* __restrict__ ctrl_all, int ncases, int only)
+__global__ void k_vmax_fin(Ctrl* __restrict__ ctrl_all, int ncases, int only, const int32_t* __restrict__ mask)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncases || (only >= 0 && c != only)) return;
+    if (c >= ncases || (only >= 0 && c != only) || (mask && !mask[c])) return;
     ctrl_all[c].vmax = bits_speed<real>(ctrl_all[c].vmax_bits);
     ctrl_all[c].vmax_bits = 0ull;
 }

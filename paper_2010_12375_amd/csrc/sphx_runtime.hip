@@ -9,12 +9,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <vector>
 
 #include "sphx.h"
 #include "sphx_device.hpp"
+#include "sphx_gnn.hpp"
 
 using namespace sphx;
 
@@ -66,6 +68,39 @@ struct EngineBase {
     virtual int profile(int32_t reps, double* ms) = 0;
     virtual int counts(int c, int64_t* out) = 0;
     virtual int autotune(int32_t reps, int32_t* lanes) = 0;
+    virtual int set_params_case(int c, const sphx_params* q) = 0;
+    virtual int gnn_set_params(const float* p, int64_t n) = 0;
+    virtual int gnn_get(int which, float* p, int64_t n) = 0;
+    virtual int gnn_forward() = 0;
+    virtual int gnn_get_output(int c, double* out) = 0;
+    virtual int gnn_set_target(int c, const double* t) = 0;
+    virtual int gnn_train_step(double lr, double* loss) = 0;
+    virtual int surrogate_advance(int32_t windows, double max_drho, int32_t plain_every, int64_t* n_fallback,
+                                  int64_t* n_surrogate) = 0;
+};
+
+// Parameter layout of the surrogate (float offsets into the flat array, in
+// storage order) and of its bf16 weight copies (K x 64 elements each).
+struct GnnLayout {
+    int Wn, bn, We, be, Wa[3], Wb[3], Wc[3], bm[3], qw[3], Wu[3], bu[3], Wo1, bo1, Wo2, bo2, total;
+    int pWn, pWe, pWa[3], pWb[3], pWc[3], pWu[3], pWo1, ptotal;
+    GnnLayout()
+    {
+        int o = 0, q = 0;
+        auto take = [&](int n) { int r = o; o += n; return r; };
+        auto pk = [&](int k) { int r = q; q += k * gnn::HID; return r; };
+        Wn = take(32 * 64); bn = take(64); We = take(32 * 64); be = take(64);
+        pWn = pk(32); pWe = pk(32);
+        for (int l = 0; l < 3; ++l) {
+            Wa[l] = take(64 * 64); Wb[l] = take(64 * 64); Wc[l] = take(64 * 64); bm[l] = take(64); qw[l] = take(64);
+            Wu[l] = take(128 * 64); bu[l] = take(64);
+            pWa[l] = pk(64); pWb[l] = pk(64); pWc[l] = pk(64); pWu[l] = pk(128);
+        }
+        Wo1 = take(64 * 64); bo1 = take(64); Wo2 = take(64 * 3); bo2 = take(3);
+        pWo1 = pk(64);
+        total = o;
+        ptotal = q;
+    }
 };
 
 static inline int nblk(long long n) { return (int)((n + BLOCK - 1) / BLOCK); }
@@ -143,6 +178,9 @@ struct Engine final : EngineBase {
         drop_graphs();
         free_list(fluid_allocs);
         free_list(wall_allocs);
+        free_list(gn.fixed);
+        free_list(gn.nodes);
+        free_list(gn.edges);
         for (void* p : {(void*)ctrl, (void*)cnt, (void*)fstart, (void*)bsum, (void*)wstart, (void*)diag_out,
                         (void*)dP, (void*)vslot, (void*)stage})
             (void)hipFree(p);
@@ -416,6 +454,7 @@ struct Engine final : EngineBase {
         RETCHK(upload_params());
         laid_out = true;
         configured = false;
+        ++conf_gen;
         return SPHX_OK;
     }
 
@@ -461,7 +500,7 @@ struct Engine final : EngineBase {
         RETCHK(dalloc(L, perm, n));
         RETCHK(dalloc(L, acc_out, (size_t)n * D));
         RETCHK(dalloc(L, drho_out, n));
-        RETCHK(dalloc(L, outbuf, (size_t)n * D));
+        RETCHK(dalloc(L, outbuf, (size_t)n * std::max(D, 3)));  // fields (n x dim) and surrogate outputs (n x 3)
         RETCHK(dalloc(L, diag_part, (size_t)(n / TILE) * NDIAG));
         RETCHK(dalloc(L, bk_st, n));
         if (D == 3) RETCHK(dalloc(L, bk_dr, n));
@@ -547,8 +586,8 @@ struct Engine final : EngineBase {
         std::memset(&hctrl[c], 0, sizeof(Ctrl));
         RETCHK(push_ctrl());
         if (n > 0) {
-            k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, c, ctrl, st[cur]);
-            k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, c);
+            k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, c, nullptr, ctrl, st[cur]);
+            k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, c, nullptr);
             HIPCHK(hipGetLastError());
         }
         return sync_ctrl();
@@ -662,6 +701,7 @@ struct Engine final : EngineBase {
 
     int enqueue_rebuild(int force, int a)
     {
+        ++conf_gen;
         int b = 1 - a;
         const int nb = nblk(ntot);
         k_bin<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, x[a][0], x[a][1], x[a][2], cell[a], key,
@@ -831,8 +871,8 @@ struct Engine final : EngineBase {
         RETCHK(check_case(c));
         if (hP[c].nf == 0) return ctx->fail(SPHX_ESTATE, case_tag(c) + "no fluid particles");
         RETCHK(ensure_layout());
-        k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, c, ctrl, st[cur]);
-        k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, c);
+        k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, c, nullptr, ctrl, st[cur]);
+        k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, c, nullptr);
         HIPCHK(hipGetLastError());
         RETCHK(sync_ctrl());
         const KP<real>& P = hP[c];
@@ -917,8 +957,14 @@ struct Engine final : EngineBase {
 
     int advance(int32_t n_steps, double t_stop, int64_t* nsub_out, double* t_out) override
     {
-        RETCHK(all_have_fluid());
         if (n_steps < 0) return ctx->fail(SPHX_EINVAL, "negative step count");
+        return advance_cases(std::vector<long long>(C, n_steps), t_stop, nsub_out, t_out);
+    }
+
+    // Advance case c by up to steps[c] advection steps (0: the case idles).
+    int advance_cases(const std::vector<long long>& steps, double t_stop, int64_t* nsub_out, double* t_out)
+    {
+        RETCHK(all_have_fluid());
         if (!configured) RETCHK(build_neighbors());
         RETCHK(capture_graphs());
         RETCHK(sync_ctrl());
@@ -926,7 +972,7 @@ struct Engine final : EngineBase {
         for (int c = 0; c < C; ++c) {
             sub0[c] = hctrl[c].nsub_total;
             hctrl[c].t_stop = t_stop;
-            hctrl[c].steps_target = hctrl[c].steps_done + n_steps;
+            hctrl[c].steps_target = hctrl[c].steps_done + steps[c];
         }
         RETCHK(push_ctrl());
         k_adv_begin<real><<<(C + 63) / 64, 64, 0, s>>>(dP, ctrl, C);
@@ -1133,6 +1179,499 @@ struct Engine final : EngineBase {
         if (lanes) *lanes = ln;
         return SPHX_OK;
     }
+
+    // Replace case c's physical parameters; its cell grid must stay the same
+    // (same box, periodicity and cell size), its particles stay.
+    int set_params_case(int c, const sphx_params* q) override
+    {
+        RETCHK(check_case(c));
+        if (!q || q->dim != D || q->precision != ctx->prm[c].precision || !(q->dp > 0) || !(q->h > 0) ||
+            !(q->rho0 > 0) || !(q->c0 > 0) || !(q->u_ref > 0) || !(q->cfl_ad > 0) || !(q->cfl_ac > 0))
+            return ctx->fail(SPHX_EINVAL, "bad parameters");
+        const KP<real> old = hP[c];
+        const sphx_params oldq = ctx->prm[c];
+        ctx->prm[c] = *q;
+        int rc = init_case(c, old.cbase);
+        bool same = rc == SPHX_OK && hP[c].ncell == old.ncell;
+        for (int k = 0; k < 3 && same; ++k) same = hP[c].n[k] == old.n[k] && hP[c].Ld[k] == old.Ld[k] &&
+                                                   hP[c].lo[k] == old.lo[k] && hP[c].periodic[k] == old.periodic[k];
+        if (!same) {
+            hP[c] = old;
+            ctx->prm[c] = oldq;
+            return rc != SPHX_OK ? rc : ctx->fail(SPHX_EINVAL, case_tag(c) + "the cell grid would change");
+        }
+        hP[c].fbase = old.fbase;
+        hP[c].nf = old.nf;
+        hP[c].fcap = old.fcap;
+        hP[c].wbase = old.wbase;
+        hP[c].nw = old.nw;
+        RETCHK(upload_params());
+        configured = false;
+        return SPHX_OK;
+    }
+
+    // ------------------------------------------------------------------
+    // Message-passing surrogate (2D). Node rows are the fluid slots, edge rows
+    // the CSR of each particle's inner then contact list entries.
+    struct Gnn {
+        GnnLayout L;
+        bool ready = false;
+        long long step = 0;
+        long long gen = -1;       // configuration generation of the last forward
+        float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+        uint16_t *wt = nullptr, *wn = nullptr;
+        int Ncap = 0;
+        long long Ecap = 0;
+        bool Ecap_train = false, Ncap_train = false;
+        std::vector<void*> fixed, nodes, edges;
+        int32_t *ecount = nullptr, *eoff = nullptr, *bsumN = nullptr, *edst = nullptr, *erev = nullptr;
+        float *F = nullptr, *X[3] = {}, *Hs = nullptr, *Z[3] = {}, *P = nullptr, *Q = nullptr, *D1 = nullptr,
+              *Y = nullptr, *T = nullptr, *dY = nullptr;
+        float *dH = nullptr, *dZ = nullptr, *dA = nullptr, *dPb = nullptr, *dQb = nullptr, *wsum = nullptr;
+        float *G = nullptr, *E0 = nullptr, *R = nullptr, *pre[3] = {}, *dM = nullptr, *dE0 = nullptr;
+        float *part = nullptr, *bpart = nullptr;
+        double *lpart = nullptr, *dtc = nullptr, *tmax = nullptr;
+        int32_t* accept = nullptr;
+        std::vector<long long> target_gen;   // configuration generation each case's target was set on
+        long long E = 0;
+    } gn;
+    long long conf_gen = 0;      // incremented by every configuration update
+    static constexpr int PART_BLOCKS = 1024;
+
+    int gnn_fixed_alloc()
+    {
+        if (gn.p) return SPHX_OK;
+        auto& A = gn.fixed;
+        const int np = gn.L.total;
+        RETCHK(dalloc(A, gn.p, np));
+        RETCHK(dalloc(A, gn.g, np));
+        RETCHK(dalloc(A, gn.m, np));
+        RETCHK(dalloc(A, gn.v, np));
+        RETCHK(dalloc(A, gn.wt, gn.L.ptotal));
+        RETCHK(dalloc(A, gn.wn, gn.L.ptotal));
+        RETCHK(dalloc(A, gn.part, (size_t)PART_BLOCKS * 128 * gnn::HID));
+        RETCHK(dalloc(A, gn.bpart, (size_t)PART_BLOCKS * gnn::HID));
+        RETCHK(dalloc(A, gn.dtc, C));
+        RETCHK(dalloc(A, gn.accept, C));
+        HIPCHK(hipMemsetAsync(gn.g, 0, sizeof(float) * np, s));
+        return SPHX_OK;
+    }
+
+    // Node buffers for N slots (the training ones included: they are small).
+    int gnn_nodes(bool)
+    {
+        const bool train = true;
+        const int N = std::max(ntot, TILE);
+        if (gn.Ncap >= N && gn.Ncap_train) return SPHX_OK;
+        HIPCHK(hipStreamSynchronize(s));
+        free_list(gn.nodes);
+        auto& A = gn.nodes;
+        const size_t n64 = (size_t)N * gnn::HID;
+        RETCHK(dalloc(A, gn.ecount, N));
+        RETCHK(dalloc(A, gn.eoff, N + 1));
+        RETCHK(dalloc(A, gn.bsumN, (N + SCAN_TILE - 1) / SCAN_TILE + 1));
+        RETCHK(dalloc(A, gn.F, (size_t)N * gnn::FPAD));
+        for (int l = 0; l < 3; ++l) {
+            RETCHK(dalloc(A, gn.X[l], 2 * n64));
+            RETCHK(dalloc(A, gn.Z[l], n64));
+        }
+        RETCHK(dalloc(A, gn.Hs, n64));
+        RETCHK(dalloc(A, gn.P, n64));
+        RETCHK(dalloc(A, gn.Q, n64));
+        RETCHK(dalloc(A, gn.D1, n64));
+        RETCHK(dalloc(A, gn.Y, (size_t)N * gnn::NOUT));
+        RETCHK(dalloc(A, gn.T, (size_t)N * gnn::NOUT));
+        RETCHK(dalloc(A, gn.dY, (size_t)N * gnn::NOUT));
+        RETCHK(dalloc(A, gn.lpart, nblk(N)));
+        RETCHK(dalloc(A, gn.tmax, N / TILE + 1));
+        if (train) {
+            RETCHK(dalloc(A, gn.dH, n64));
+            RETCHK(dalloc(A, gn.dZ, n64));
+            RETCHK(dalloc(A, gn.dA, n64));
+            RETCHK(dalloc(A, gn.dPb, n64));
+            RETCHK(dalloc(A, gn.dQb, n64));
+            RETCHK(dalloc(A, gn.wsum, n64));
+        }
+        HIPCHK(hipMemsetAsync(gn.T, 0, sizeof(float) * (size_t)N * gnn::NOUT, s));
+        gn.Ncap = N;
+        gn.Ncap_train = train;
+        gn.target_gen.assign(C, -1);
+        gn.gen = -1;
+        return SPHX_OK;
+    }
+
+    int gnn_edges_alloc(long long E, bool train)
+    {
+        E = std::max(E, 1LL);
+        if (gn.Ecap >= E && (!train || gn.Ecap_train)) return SPHX_OK;
+        HIPCHK(hipStreamSynchronize(s));
+        free_list(gn.edges);
+        auto& A = gn.edges;
+        const long long cap = E + E / 8 + 1024;
+        const size_t e64 = (size_t)cap * gnn::HID;
+        RETCHK(dalloc(A, gn.edst, cap));
+        RETCHK(dalloc(A, gn.erev, cap));
+        RETCHK(dalloc(A, gn.G, (size_t)cap * gnn::FPAD));
+        RETCHK(dalloc(A, gn.E0, e64));
+        RETCHK(dalloc(A, gn.R, e64));
+        if (train) {
+            for (int l = 0; l < 3; ++l) RETCHK(dalloc(A, gn.pre[l], e64));
+            RETCHK(dalloc(A, gn.dM, e64));
+            RETCHK(dalloc(A, gn.dE0, e64));
+        } else {
+            for (int l = 0; l < 3; ++l) gn.pre[l] = nullptr;
+        }
+        gn.Ecap = cap;
+        gn.Ecap_train = train;
+        return SPHX_OK;
+    }
+
+    int gnn_check_ready()
+    {
+        if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
+        if (!gn.ready) return ctx->fail(SPHX_ESTATE, "surrogate parameters not set");
+        if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
+        return SPHX_OK;
+    }
+
+    int gnn_pack()
+    {
+        auto pack = [&](int K, int off, int pk) {
+            gnn::k_pack_w<<<(K * gnn::HID + 255) / 256, 256, 0, s>>>(K, gn.p + off, gn.wt + pk, gn.wn + pk);
+        };
+        pack(32, gn.L.Wn, gn.L.pWn);
+        pack(32, gn.L.We, gn.L.pWe);
+        for (int l = 0; l < 3; ++l) {
+            pack(64, gn.L.Wa[l], gn.L.pWa[l]);
+            pack(64, gn.L.Wb[l], gn.L.pWb[l]);
+            pack(64, gn.L.Wc[l], gn.L.pWc[l]);
+            pack(128, gn.L.Wu[l], gn.L.pWu[l]);
+        }
+        pack(64, gn.L.Wo1, gn.L.pWo1);
+        HIPCHK(hipGetLastError());
+        return SPHX_OK;
+    }
+
+    int gnn_set_params(const float* p, int64_t n) override
+    {
+        if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
+        if (!p || n != gn.L.total) return ctx->fail(SPHX_EINVAL, "parameter array of the wrong size");
+        RETCHK(gnn_fixed_alloc());
+        HIPCHK(hipMemcpyAsync(gn.p, p, sizeof(float) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(gn.m, 0, sizeof(float) * n, s));
+        HIPCHK(hipMemsetAsync(gn.v, 0, sizeof(float) * n, s));
+        HIPCHK(hipMemsetAsync(gn.g, 0, sizeof(float) * n, s));
+        RETCHK(gnn_pack());
+        HIPCHK(hipStreamSynchronize(s));
+        gn.step = 0;
+        gn.ready = true;
+        gn.gen = -1;
+        return SPHX_OK;
+    }
+
+    // which: 0 parameters, 1 gradient of the last training step
+    int gnn_get(int which, float* p, int64_t n) override
+    {
+        if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
+        if (!gn.ready) return ctx->fail(SPHX_ESTATE, "surrogate parameters not set");
+        if (!p || n != gn.L.total) return ctx->fail(SPHX_EINVAL, "parameter array of the wrong size");
+        HIPCHK(hipMemcpyAsync(p, which == 0 ? gn.p : gn.g, sizeof(float) * n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return SPHX_OK;
+    }
+
+    // The CSR graph and the features of the current configuration.
+    int gnn_graph(bool train)
+    {
+        RETCHK(gnn_nodes(train));
+        const int N = ntot;
+        gnn::k_gnn_count<real><<<nblk(N), BLOCK, 0, s>>>(dP, tcase, ntiles, ncnt, wcnt, gn.ecount);
+        const int nb = (N + SCAN_TILE - 1) / SCAN_TILE;
+        k_scan_tiles<<<nb, BLOCK, 0, s>>>(gn.ecount, gn.eoff, gn.bsumN, N);
+        k_scan_top<<<1, BLOCK, 0, s>>>(gn.bsumN, nb);
+        k_scan_add<<<nb, BLOCK, 0, s>>>(gn.eoff, gn.bsumN, N, nb);
+        HIPCHK(hipGetLastError());
+        int32_t etot = 0;
+        HIPCHK(hipMemcpyAsync(&etot, gn.eoff + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        gn.E = etot;
+        RETCHK(gnn_edges_alloc(gn.E, train));
+        if constexpr (D == 2) {
+            if (ln == 4)
+                gnn::k_gnn_edges<real, 4><<<nblk(N), BLOCK, 0, s>>>(dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt,
+                                                                   geo[cur], wgeo, st[cur], gn.edst, gn.erev, gn.G,
+                                                                   gn.F);
+            else
+                gnn::k_gnn_edges<real, 8><<<nblk(N), BLOCK, 0, s>>>(dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt,
+                                                                   geo[cur], wgeo, st[cur], gn.edst, gn.erev, gn.G,
+                                                                   gn.F);
+        }
+        HIPCHK(hipGetLastError());
+        return SPHX_OK;
+    }
+
+    template <int K, int EPI>
+    void gemm(long long M, const float* A, int lda, const uint16_t* Bt, const float* bias, float* Cm, int ldc,
+              float* C2 = nullptr, int ldc2 = 0)
+    {
+        if (M <= 0) return;
+        gnn::k_gemm64<K, EPI><<<(int)((M + 63) / 64), 256, 0, s>>>((int)M, A, lda, Bt, bias, Cm, ldc, C2, ldc2);
+    }
+
+    // dW (KIN x 64) and optionally db (64) from X^T dZ over M rows.
+    template <int KIN>
+    void wgrad(long long M, const float* X, int ldx, const float* dZ, int ldz, float* dW, float* db)
+    {
+        if (M <= 0) return;
+        int rows = (int)((M + PART_BLOCKS - 1) / PART_BLOCKS);
+        rows = std::max(256, (rows + 31) / 32 * 32);
+        const int nb = (int)((M + rows - 1) / rows);
+        gnn::k_wgrad<KIN><<<nb, 256, 0, s>>>((int)M, rows, X, ldx, dZ, ldz, gn.part, gn.bpart);
+        gnn::k_reduce_parts<<<(KIN * gnn::HID + 255) / 256, 256, 0, s>>>(nb, KIN * gnn::HID, gn.part, dW, 0);
+        if (db) gnn::k_reduce_parts<<<1, 256, 0, s>>>(nb, gnn::HID, gn.bpart, db, 0);
+    }
+
+    void elem64(long long M, const float* src, int lds, const float* mask, int ldm, float* out, int ldo)
+    {
+        if (M <= 0) return;
+        const long long n = M * gnn::HID;
+        if (mask)
+            gnn::k_relu_mask<<<(int)((n + 255) / 256), 256, 0, s>>>((int)M, src, lds, mask, ldm, out, ldo);
+        else
+            gnn::k_copy64<<<(int)((n + 255) / 256), 256, 0, s>>>((int)M, src, lds, out, ldo);
+    }
+
+    int gnn_forward_impl(bool train)
+    {
+        RETCHK(gnn_graph(train));
+        const GnnLayout& L = gn.L;
+        const int N = ntot;
+        const long long E = gn.E;
+        float* p = gn.p;
+        constexpr int H = gnn::HID;
+        gemm<32, gnn::EPI_RELU>(N, gn.F, 32, gn.wt + L.pWn, p + L.bn, gn.X[0], 2 * H);
+        elem64(N, gn.X[0], 2 * H, nullptr, 0, gn.Hs, H);
+        gemm<32, gnn::EPI_RELU>(E, gn.G, 32, gn.wt + L.pWe, p + L.be, gn.E0, H);
+        for (int l = 0; l < 3; ++l) {
+            gemm<64, gnn::EPI_STORE>(N, gn.X[l], 2 * H, gn.wt + L.pWa[l], p + L.bm[l], gn.P, H);
+            gemm<64, gnn::EPI_STORE>(N, gn.X[l], 2 * H, gn.wt + L.pWb[l], nullptr, gn.Q, H);
+            gemm<64, gnn::EPI_STORE>(E, gn.E0, H, gn.wt + L.pWc[l], nullptr, gn.R, H);
+            gnn::k_gnn_msg<<<(N + 3) / 4, 256, 0, s>>>(N, gn.eoff, gn.edst, gn.P, gn.Q, gn.R, p + L.qw[l],
+                                                       train ? gn.pre[l] : nullptr, gn.X[l]);
+            gemm<128, gnn::EPI_RESID>(N, gn.X[l], 2 * H, gn.wt + L.pWu[l], p + L.bu[l], gn.Hs, H, gn.Z[l], H);
+            if (l < 2) elem64(N, gn.Hs, H, nullptr, 0, gn.X[l + 1], 2 * H);
+        }
+        gemm<64, gnn::EPI_RELU>(N, gn.Hs, H, gn.wt + L.pWo1, p + L.bo1, gn.D1, H);
+        gnn::k_gnn_out<<<nblk(N), BLOCK, 0, s>>>(N, gn.D1, p + L.Wo2, p + L.bo2, gn.Y);
+        HIPCHK(hipGetLastError());
+        gn.gen = conf_gen;
+        return SPHX_OK;
+    }
+
+    int gnn_backward_impl()
+    {
+        const GnnLayout& L = gn.L;
+        const int N = ntot;
+        const long long E = gn.E;
+        float *p = gn.p, *g = gn.g;
+        constexpr int H = gnn::HID;
+        // decoder
+        {
+            const int rows = std::max(256, (N + PART_BLOCKS - 1) / PART_BLOCKS);
+            const int nb = (N + rows - 1) / rows;
+            gnn::k_gnn_out_wgrad<<<nb, 256, 0, s>>>(N, rows, gn.D1, gn.dY, gn.part);
+            gnn::k_reduce_parts<<<1, 256, 0, s>>>(nb, H * 3 + 3, gn.part, g + L.Wo2, 0);
+            const long long n = (long long)N * H;
+            gnn::k_gnn_out_bwd<<<(int)((n + 255) / 256), 256, 0, s>>>(N, gn.D1, gn.dY, p + L.Wo2, gn.dZ);
+        }
+        wgrad<64>(N, gn.Hs, H, gn.dZ, H, g + L.Wo1, g + L.bo1);
+        gemm<64, gnn::EPI_STORE>(N, gn.dZ, H, gn.wn + L.pWo1, nullptr, gn.dH, H);
+        for (int l = 2; l >= 0; --l) {
+            elem64(N, gn.dH, H, gn.Z[l], H, gn.dZ, H);
+            wgrad<128>(N, gn.X[l], 2 * H, gn.dZ, H, g + L.Wu[l], g + L.bu[l]);
+            gemm<64, gnn::EPI_ACCUM>(N, gn.dZ, H, gn.wn + L.pWu[l], nullptr, gn.dH, H);
+            gemm<64, gnn::EPI_STORE>(N, gn.dZ, H, gn.wn + L.pWu[l] + 64 * H, nullptr, gn.dA, H);
+            gnn::k_gnn_msg_bwd<<<(N + 3) / 4, 256, 0, s>>>(N, gn.eoff, gn.edst, gn.pre[l], gn.dA, H, gn.dM, gn.dPb,
+                                                           gn.wsum);
+            gnn::k_gnn_dq<<<(N + 3) / 4, 256, 0, s>>>(N, gn.eoff, gn.edst, gn.erev, gn.dM, gn.dQb);
+            {
+                const int rows = std::max(256, (N + PART_BLOCKS - 1) / PART_BLOCKS);
+                const int nb = (N + rows - 1) / rows;
+                gnn::k_colsum64<<<nb, 64, 0, s>>>(N, rows, gn.wsum, H, gn.bpart);
+                gnn::k_reduce_parts<<<1, 256, 0, s>>>(nb, H, gn.bpart, g + L.qw[l], 0);
+            }
+            wgrad<64>(N, gn.X[l], 2 * H, gn.dPb, H, g + L.Wa[l], g + L.bm[l]);
+            wgrad<64>(N, gn.X[l], 2 * H, gn.dQb, H, g + L.Wb[l], nullptr);
+            wgrad<64>(E, gn.E0, H, gn.dM, H, g + L.Wc[l], nullptr);
+            gemm<64, gnn::EPI_ACCUM>(N, gn.dPb, H, gn.wn + L.pWa[l], nullptr, gn.dH, H);
+            gemm<64, gnn::EPI_ACCUM>(N, gn.dQb, H, gn.wn + L.pWb[l], nullptr, gn.dH, H);
+            if (l == 2) gemm<64, gnn::EPI_STORE>(E, gn.dM, H, gn.wn + L.pWc[l], nullptr, gn.dE0, H);
+            else gemm<64, gnn::EPI_ACCUM>(E, gn.dM, H, gn.wn + L.pWc[l], nullptr, gn.dE0, H);
+        }
+        // encoders (dM is free again: it takes dZe)
+        elem64(E, gn.dE0, H, gn.E0, H, gn.dM, H);
+        wgrad<32>(E, gn.G, 32, gn.dM, H, g + L.We, g + L.be);
+        elem64(N, gn.dH, H, gn.X[0], 2 * H, gn.dZ, H);
+        wgrad<32>(N, gn.F, 32, gn.dZ, H, g + L.Wn, g + L.bn);
+        HIPCHK(hipGetLastError());
+        return SPHX_OK;
+    }
+
+    int gnn_forward() override
+    {
+        RETCHK(gnn_check_ready());
+        RETCHK(gnn_forward_impl(false));
+        HIPCHK(hipStreamSynchronize(s));
+        return SPHX_OK;
+    }
+
+    int gnn_get_output(int c, double* out) override
+    {
+        RETCHK(check_case(c));
+        if (!out) return ctx->fail(SPHX_EINVAL, "NULL output");
+        if (gn.gen != conf_gen || gn.gen < 0) return ctx->fail(SPHX_ESTATE, "no surrogate output for this configuration");
+        const KP<real>& P = hP[c];
+        if (P.nf == 0) return SPHX_OK;
+        k_unsort_vec<float><<<nblk(P.nf), BLOCK, 0, s>>>(P.fbase, P.nf, gnn::NOUT, id[cur], gn.Y, outbuf);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out, outbuf, sizeof(double) * (size_t)P.nf * gnn::NOUT, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return SPHX_OK;
+    }
+
+    int gnn_set_target(int c, const double* t) override
+    {
+        RETCHK(check_case(c));
+        if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
+        if (!t) return ctx->fail(SPHX_EINVAL, "NULL target");
+        if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
+        RETCHK(gnn_nodes(false));
+        const KP<real>& P = hP[c];
+        if (P.nf > 0) {
+            RETCHK(ensure_stage((size_t)P.nf * gnn::NOUT));
+            HIPCHK(hipMemcpyAsync(stage, t, sizeof(double) * (size_t)P.nf * gnn::NOUT, hipMemcpyHostToDevice, s));
+            gnn::k_gnn_load_target<real><<<nblk(P.nf), BLOCK, 0, s>>>(dP, c, id[cur], stage, gn.T);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        gn.target_gen[c] = conf_gen;
+        return SPHX_OK;
+    }
+
+    int gnn_train_step(double lr, double* loss) override
+    {
+        RETCHK(gnn_check_ready());
+        RETCHK(gnn_nodes(true));
+        for (int c = 0; c < C; ++c)
+            if (gn.target_gen[c] != conf_gen)
+                return ctx->fail(SPHX_ESTATE, case_tag(c) + "no training target set on the current configuration");
+        long long count = 0;
+        for (int c = 0; c < C; ++c) count += hP[c].nf;
+        RETCHK(gnn_forward_impl(true));
+        const int nbl = nblk(ntot);
+        gnn::k_gnn_loss<real><<<nbl, 256, 0, s>>>(dP, tcase, ntiles, 1.0 / (3.0 * (double)count), gn.Y, gn.T, gn.dY,
+                                                  gn.lpart);
+        HIPCHK(hipGetLastError());
+        RETCHK(gnn_backward_impl());
+        gn.step += 1;
+        const double b1 = 0.9, b2 = 0.999;
+        const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)gn.step)));
+        const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)gn.step)));
+        gnn::k_adam<<<(gn.L.total + 255) / 256, 256, 0, s>>>(gn.L.total, gn.p, gn.g, gn.m, gn.v, (float)lr, (float)b1,
+                                                            (float)b2, 1e-8f, c1, c2);
+        HIPCHK(hipGetLastError());
+        RETCHK(gnn_pack());
+        std::vector<double> lp(nbl);
+        HIPCHK(hipMemcpyAsync(lp.data(), gn.lpart, sizeof(double) * nbl, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double sum = 0.0;
+        for (double v : lp) sum += v;
+        if (loss) *loss = sum / (3.0 * (double)count);
+        gn.gen = -1;  // the outputs belong to the parameters before the step
+        return SPHX_OK;
+    }
+
+    // Surrogate windows: each predicts every case's mean rates over the next
+    // two advection steps (dt = 2 dt_ad from the current |v|max) and applies
+    // them where the predicted density stays within max_drho of rho0 (and,
+    // with plain_every > 0, except every plain_every-th window); the other
+    // cases take the two steps with the plain scheme.
+    int surrogate_advance(int32_t windows, double max_drho, int32_t plain_every, int64_t* n_fallback,
+                          int64_t* n_surrogate) override
+    {
+        if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
+        if (!gn.ready) return ctx->fail(SPHX_ESTATE, "surrogate parameters not set");
+        if (windows < 0) return ctx->fail(SPHX_EINVAL, "negative window count");
+        RETCHK(all_have_fluid());
+        if (!configured) RETCHK(build_neighbors());
+        long long nfb = 0, nsu = 0;
+        std::vector<double> dtc(C);
+        std::vector<int32_t> acc(C);
+        std::vector<double> tm;
+        for (int w = 0; w < windows; ++w) {
+            RETCHK(sync_ctrl());
+            const bool plain_turn = plain_every > 0 && (w % plain_every) == plain_every - 1;
+            if (plain_turn) {  // a plain window for every case: no prediction needed
+                std::vector<long long> steps(C, 2);
+                for (int c = 0; c < C; ++c) nfb += hctrl[c].err ? 0 : 1;
+                int rc = advance_cases(steps, std::numeric_limits<double>::infinity(), nullptr, nullptr);
+                if (rc != SPHX_OK && rc != SPHX_EESCAPE && rc != SPHX_ENAN && rc != SPHX_EOVERFLOW) return rc;
+                continue;
+            }
+            RETCHK(gnn_forward_impl(false));
+            for (int c = 0; c < C; ++c) dtc[c] = 2.0 * hP[c].cfl_ad_h / std::fmax(hctrl[c].vmax, hP[c].u_ref);
+            HIPCHK(hipMemcpyAsync(gn.dtc, dtc.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+            gnn::k_gnn_check<real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, gn.dtc, gn.Y, st[cur], gn.tmax);
+            HIPCHK(hipGetLastError());
+            tm.resize(std::max(ntiles, 1));
+            HIPCHK(hipMemcpyAsync(tm.data(), gn.tmax, sizeof(double) * ntiles, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            bool any_acc = false, any_rej = false;
+            for (int c = 0; c < C; ++c) {
+                double mx = 0.0;
+                for (int t = hP[c].fbase / TILE; t < (hP[c].fbase + hP[c].fcap) / TILE; ++t) mx = std::fmax(mx, tm[t]);
+                acc[c] = !hctrl[c].err && mx <= max_drho;
+                any_acc |= acc[c] != 0;
+                any_rej |= !acc[c] && !hctrl[c].err;
+            }
+            if (any_acc) {
+                HIPCHK(hipMemcpyAsync(gn.accept, acc.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+                gnn::k_gnn_apply<real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, gn.dtc, gn.accept, gn.Y,
+                                                                     x[cur][0], x[cur][1], st[cur]);
+                HIPCHK(hipGetLastError());
+                for (int c = 0; c < C; ++c) {
+                    hctrl[c].rebuild = acc[c];
+                    hctrl[c].midstep = 0;
+                    if (acc[c]) {
+                        hctrl[c].t += dtc[c];
+                        hctrl[c].steps_done += 2;
+                        ++nsu;
+                    }
+                }
+                RETCHK(push_ctrl());
+                RETCHK(enqueue_rebuild(0, cur));
+                cur ^= 1;
+                ++conf_gen;
+                k_vmax<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, -1, gn.accept, ctrl, st[cur]);
+                k_vmax_fin<real><<<(C + 63) / 64, 64, 0, s>>>(ctrl, C, -1, gn.accept);
+                HIPCHK(hipGetLastError());
+                RETCHK(sync_ctrl());
+            }
+            if (any_rej) {
+                std::vector<long long> steps(C);
+                for (int c = 0; c < C; ++c) {
+                    steps[c] = acc[c] ? 0 : 2;
+                    nfb += acc[c] ? 0 : 1;
+                }
+                int rc = advance_cases(steps, std::numeric_limits<double>::infinity(), nullptr, nullptr);
+                if (rc != SPHX_OK && rc != SPHX_EESCAPE && rc != SPHX_ENAN && rc != SPHX_EOVERFLOW) return rc;
+            }
+        }
+        if (n_fallback) *n_fallback = nfb;
+        if (n_surrogate) *n_surrogate = nsu;
+        RETCHK(sync_ctrl());
+        return first_error();
+    }
 };
 
 // ---------------------------------------------------------------------
@@ -1280,5 +1819,29 @@ int sphx_counts(sphx_ctx* ctx, int64_t* out) { ENG_CALL(counts(-1, out)); }
 int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out) { ENG_CALL(counts(c, out)); }
 
 int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes) { ENG_CALL(autotune(reps, lanes)); }
+
+int sphx_set_params_case(sphx_ctx* ctx, int32_t c, const sphx_params* params) { ENG_CALL(set_params_case(c, params)); }
+
+int64_t sphx_gnn_num_params(void) { return GnnLayout().total; }
+
+int sphx_gnn_set_params(sphx_ctx* ctx, const float* params, int64_t n) { ENG_CALL(gnn_set_params(params, n)); }
+
+int sphx_gnn_get_params(sphx_ctx* ctx, float* params, int64_t n) { ENG_CALL(gnn_get(0, params, n)); }
+
+int sphx_gnn_get_grad(sphx_ctx* ctx, float* grad, int64_t n) { ENG_CALL(gnn_get(1, grad, n)); }
+
+int sphx_gnn_forward(sphx_ctx* ctx) { ENG_CALL(gnn_forward()); }
+
+int sphx_gnn_get_output_case(sphx_ctx* ctx, int32_t c, double* out) { ENG_CALL(gnn_get_output(c, out)); }
+
+int sphx_gnn_set_target_case(sphx_ctx* ctx, int32_t c, const double* target) { ENG_CALL(gnn_set_target(c, target)); }
+
+int sphx_gnn_train_step(sphx_ctx* ctx, double lr, double* loss) { ENG_CALL(gnn_train_step(lr, loss)); }
+
+int sphx_surrogate_advance(sphx_ctx* ctx, int32_t windows, double max_drho, int32_t plain_every, int64_t* n_fallback,
+                           int64_t* n_surrogate)
+{
+    ENG_CALL(surrogate_advance(windows, max_drho, plain_every, n_fallback, n_surrogate));
+}
 
 }  // extern "C"

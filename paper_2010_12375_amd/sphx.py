@@ -24,12 +24,15 @@ SPHX_FIELD_POS, SPHX_FIELD_VEL, SPHX_FIELD_RHO, SPHX_FIELD_P, SPHX_FIELD_DRHO = 
 ERROR_NAMES = {SPHX_EINVAL: "EINVAL", SPHX_ENOMEM: "ENOMEM", SPHX_EHIP: "EHIP", SPHX_EESCAPE: "EESCAPE",
                SPHX_ENAN: "ENAN", SPHX_ECAP: "ECAP", SPHX_EOVERFLOW: "EOVERFLOW", SPHX_ESTATE: "ESTATE"}
 
-EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_destroy", "sphx_last_error",
+EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_set_params_case", "sphx_destroy", "sphx_last_error",
             "sphx_set_fluid", "sphx_set_fluid_case", "sphx_set_walls", "sphx_set_walls_case",
             "sphx_build_neighbors", "sphx_get_neighbors", "sphx_get_neighbors_case", "sphx_density_reinit",
             "sphx_time_steps", "sphx_time_steps_case", "sphx_compute_rates", "sphx_compute_rates_case",
             "sphx_advance", "sphx_case_status", "sphx_get_field", "sphx_get_field_case", "sphx_diagnostics",
-            "sphx_diagnostics_case", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune")
+            "sphx_diagnostics_case", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune",
+            "sphx_gnn_num_params", "sphx_gnn_set_params", "sphx_gnn_get_params", "sphx_gnn_get_grad",
+            "sphx_gnn_forward", "sphx_gnn_get_output_case", "sphx_gnn_set_target_case", "sphx_gnn_train_step",
+            "sphx_surrogate_advance")
 
 
 class SphxError(RuntimeError):
@@ -71,6 +74,7 @@ def load(path=None):
         "sphx_create": [C.POINTER(sphx_params), vp, C.POINTER(vp)],
         "sphx_create_batch": [C.POINTER(sphx_params), i32, vp, C.POINTER(vp)],
         "sphx_num_cases": [vp],
+        "sphx_set_params_case": [vp, i32, C.POINTER(sphx_params)],
         "sphx_set_fluid": [vp, i64, vp, vp, vp, vp],
         "sphx_set_fluid_case": [vp, i32, i64, vp, vp, vp, vp],
         "sphx_set_walls": [vp, i64, vp, vp],
@@ -93,11 +97,21 @@ def load(path=None):
         "sphx_counts": [vp, pi64],
         "sphx_counts_case": [vp, i32, pi64],
         "sphx_autotune": [vp, i32, C.POINTER(i32)],
+        "sphx_gnn_set_params": [vp, vp, i64],
+        "sphx_gnn_get_params": [vp, vp, i64],
+        "sphx_gnn_get_grad": [vp, vp, i64],
+        "sphx_gnn_forward": [vp],
+        "sphx_gnn_get_output_case": [vp, i32, vp],
+        "sphx_gnn_set_target_case": [vp, i32, vp],
+        "sphx_gnn_train_step": [vp, d, pd],
+        "sphx_surrogate_advance": [vp, i32, d, i32, pi64, pi64],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.restype = C.c_int
         f.argtypes = args
+    L.sphx_gnn_num_params.restype = i64
+    L.sphx_gnn_num_params.argtypes = []
     L.sphx_destroy.restype = None
     L.sphx_destroy.argtypes = [vp]
     L.sphx_last_error.restype = C.c_char_p
@@ -197,6 +211,10 @@ class Simulation:
                                                 _ptr(drho)), "sphx_set_fluid_case")
         self.nf[case] = pos.shape[0]
 
+    def set_params(self, params, case=0):
+        """Replace case `case`'s parameters (same cell grid)."""
+        self._check(self._L.sphx_set_params_case(self._h, case, C.byref(params)), "sphx_set_params_case")
+
     def set_walls(self, pos, normal, case=0):
         pos, normal = _f64(pos), _f64(normal)
         self._check(self._L.sphx_set_walls_case(self._h, case, pos.shape[0], _ptr(pos), _ptr(normal)),
@@ -281,6 +299,47 @@ class Simulation:
         else:
             self._check(self._L.sphx_counts_case(self._h, case, out), "sphx_counts_case")
         return dict(fluid=out[0], wall=out[1], inner_pairs=out[2], contact_pairs=out[3])
+
+    # -- message-passing surrogate (2D) --
+    def gnn_num_params(self):
+        return int(self._L.sphx_gnn_num_params())
+
+    def gnn_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._L.sphx_gnn_set_params(self._h, _ptr(p), p.size), "sphx_gnn_set_params")
+
+    def gnn_get_params(self):
+        p = np.zeros(self.gnn_num_params(), dtype=np.float32)
+        self._check(self._L.sphx_gnn_get_params(self._h, _ptr(p), p.size), "sphx_gnn_get_params")
+        return p
+
+    def gnn_get_grad(self):
+        p = np.zeros(self.gnn_num_params(), dtype=np.float32)
+        self._check(self._L.sphx_gnn_get_grad(self._h, _ptr(p), p.size), "sphx_gnn_get_grad")
+        return p
+
+    def gnn_forward(self):
+        self._check(self._L.sphx_gnn_forward(self._h), "sphx_gnn_forward")
+
+    def gnn_output(self, case=0):
+        out = np.zeros((self.nf[case], 3), dtype=np.float64)
+        self._check(self._L.sphx_gnn_get_output_case(self._h, case, _ptr(out)), "sphx_gnn_get_output_case")
+        return out
+
+    def gnn_set_target(self, target, case=0):
+        t = np.ascontiguousarray(target, dtype=np.float64)
+        self._check(self._L.sphx_gnn_set_target_case(self._h, case, _ptr(t)), "sphx_gnn_set_target_case")
+
+    def gnn_train_step(self, lr):
+        loss = C.c_double()
+        self._check(self._L.sphx_gnn_train_step(self._h, float(lr), C.byref(loss)), "sphx_gnn_train_step")
+        return loss.value
+
+    def surrogate_advance(self, windows, max_drho=0.01, plain_every=0):
+        a, b = C.c_int64(), C.c_int64()
+        self._check(self._L.sphx_surrogate_advance(self._h, int(windows), float(max_drho), int(plain_every),
+                                                   C.byref(a), C.byref(b)), "sphx_surrogate_advance")
+        return a.value, b.value
 
     def autotune(self, reps=10):
         lanes = C.c_int32()

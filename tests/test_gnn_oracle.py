@@ -22,7 +22,7 @@ def small_graph(seed=0):
     o.build_config()
     g = G.graph_from_oracle(o)
     o.close()
-    prm = dict(h=case.h, rho0=case.rho0, u_ref=case.u_ref, g=1.0)
+    prm = dict(h=case.h, rho0=case.rho0, u_ref=case.u_ref, g=1.0, c0=case.c0, gvec=case.gravity)
     F, E = G.features(g, case.fluid_pos, vel, rho, case.wall_pos, prm)
     return case, g, F, E, prm
 
@@ -64,6 +64,28 @@ def test_features_of_the_sph_graph():
     for (a, b), k in list(key.items())[:2000]:
         kr = key[(b, a)]
         assert np.allclose(Ei[k, 0:2], -Ei[kr, 0:2], atol=1e-12) and Ei[k, 2] == pytest.approx(Ei[kr, 2], rel=1e-12)
+        assert Ei[k, 7] == pytest.approx(-Ei[kr, 7], rel=1e-12, abs=1e-12)
+
+
+def test_pressure_feature_is_hydrostatic_height_difference():
+    """In a hydrostatic column (p = rho0 g (H - y)) the pressure feature of
+    every fluid-fluid edge is (y_i - y_j)/h, and of a wall edge the wall's
+    one-sided state: rho_i g.(x_w - x_i)/(rho0 g h)."""
+    case = wl.hydrostatic_column_2d(dp=0.05)
+    H = case.column[1]
+    rho = case.rho0 + case.rho0 * 1.0 * (H - case.fluid_pos[:, 1]) / case.c0 ** 2
+    o = O.Oracle(case)
+    o.set_fluid(case.fluid_pos, None, rho, None)
+    o.build_config()
+    g = G.graph_from_oracle(o)
+    o.close()
+    prm = dict(h=case.h, rho0=case.rho0, u_ref=case.u_ref, g=1.0, c0=case.c0, gvec=case.gravity)
+    F, E = G.features(g, case.fluid_pos, np.zeros_like(case.fluid_pos), rho, case.wall_pos, prm)
+    inner = ~g.wall
+    dy = case.fluid_pos[g.src[inner], 1] - case.fluid_pos[g.dst[inner], 1]
+    assert np.allclose(E[inner, 7], dy / case.h, rtol=1e-9, atol=1e-9)
+    wy = case.wall_pos[g.dst[~inner], 1] - case.fluid_pos[g.src[~inner], 1]
+    assert np.allclose(E[~inner, 7], -rho[g.src[~inner]] * wy / (case.rho0 * case.h), rtol=1e-12)
 
 
 def test_backward_matches_finite_differences():
@@ -114,7 +136,7 @@ def test_translation_invariance():
     case, g, F, E, prm = small_graph(3)
     vel, rho, _ = developed_state(case, seed=3)
     F2, E2 = G.features(g, case.fluid_pos + 0.37, vel, rho, case.wall_pos + 0.37, prm)
-    assert np.allclose(F2, F) and np.allclose(E2, E, atol=1e-12)
+    assert np.allclose(F2, F) and np.allclose(E2, E, atol=1e-9)
 
 
 def test_bias_only_network_closed_form():
@@ -151,4 +173,4 @@ def test_apply_is_exact_for_constant_rates():
     a = Y[:, :2]
     assert np.allclose(x2, x + v * dt + 0.5 * a * dt * dt, rtol=1e-14, atol=1e-15)
     assert np.allclose(v2, v + a * dt, rtol=1e-14, atol=1e-15)
-    assert np.allclose(r2, rho + Y[:, 2] * 20.0 * dt, rtol=1e-14, atol=1e-15)
+    assert np.allclose(r2, rho + Y[:, 2] * 0.02 * dt, rtol=1e-14, atol=1e-15)
