@@ -278,6 +278,14 @@ int sphx_gnn_get_output_case(sphx_ctx* ctx, int32_t c, double* out);
 int sphx_gnn_set_target_case(sphx_ctx* ctx, int32_t c, const double* target);
 int sphx_gnn_train_step(sphx_ctx* ctx, double lr, double* loss);
 
+/* Per-launch device time (ms, HIP events over `reps` launches) of the
+ * surrogate's kernels on the current configuration: ms[0] the edge product
+ * R = E0 Wc, ms[1] the message sums of one layer, ms[2] the node update
+ * product, ms[3] one whole forward pass including the graph and features
+ * (the last includes a host synchronisation per pass). sizes (may be NULL):
+ * [0] node rows, [1] edges. */
+int sphx_gnn_profile(sphx_ctx* ctx, int32_t reps, double* ms, int64_t* sizes);
+
 /* `windows` surrogate windows: each predicts every case's mean rates over
  * dt = 2 dt_ad (from its current |v|max) and, for the cases whose predicted
  * max |rho/rho0 - 1| stays <= max_drho, applies v += a dt, x += (v + v')/2 dt,

@@ -75,6 +75,7 @@ struct EngineBase {
     virtual int gnn_get_output(int c, double* out) = 0;
     virtual int gnn_set_target(int c, const double* t) = 0;
     virtual int gnn_train_step(double lr, double* loss) = 0;
+    virtual int gnn_profile(int32_t reps, double* ms, int64_t* sizes) = 0;
     virtual int surrogate_advance(int32_t windows, double max_drho, int32_t plain_every, int64_t* n_fallback,
                                   int64_t* n_surrogate) = 0;
 };
@@ -1591,6 +1592,47 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
+    // Per-launch device time of the surrogate's kernels on the current
+    // configuration: ms[0] edge product R = E0 Wc, ms[1] message sums (one
+    // layer), ms[2] node update product [H | A] Wu, ms[3] a whole forward pass
+    // (graph and features included); sizes[0] nodes, sizes[1] edges.
+    int gnn_profile(int32_t reps, double* ms, int64_t* sizes) override
+    {
+        RETCHK(gnn_check_ready());
+        if (reps < 1 || !ms) return ctx->fail(SPHX_EINVAL, "bad profile arguments");
+        RETCHK(gnn_forward_impl(false));
+        const GnnLayout& L = gn.L;
+        const int N = ntot;
+        const long long E = gn.E;
+        constexpr int H = gnn::HID;
+        float* p = gn.p;
+        RETCHK(time_launches(reps, &ms[0], [&] { gemm<64, gnn::EPI_STORE>(E, gn.E0, H, gn.wt + L.pWc[0], nullptr, gn.R, H); }));
+        RETCHK(time_launches(reps, &ms[1], [&] {
+            gnn::k_gnn_msg<<<(N + 3) / 4, 256, 0, s>>>(N, gn.eoff, gn.edst, gn.P, gn.Q, gn.R, p + L.qw[0], nullptr,
+                                                       gn.X[0]);
+        }));
+        RETCHK(time_launches(reps, &ms[2], [&] {
+            gemm<128, gnn::EPI_STORE>(N, gn.X[0], 2 * H, gn.wt + L.pWu[0], p + L.bu[0], gn.Z[0], H);
+        }));
+        hipEvent_t ev[2];
+        HIPCHK(hipEventCreate(&ev[0]));
+        HIPCHK(hipEventCreate(&ev[1]));
+        HIPCHK(hipEventRecord(ev[0], s));
+        for (int r = 0; r < reps; ++r) RETCHK(gnn_forward_impl(false));
+        HIPCHK(hipEventRecord(ev[1], s));
+        HIPCHK(hipEventSynchronize(ev[1]));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        ms[3] = (double)t / reps;
+        if (sizes) {
+            sizes[0] = N;
+            sizes[1] = E;
+        }
+        return SPHX_OK;
+    }
+
     // Surrogate windows: each predicts every case's mean rates over the next
     // two advection steps (dt = 2 dt_ad from the current |v|max) and applies
     // them where the predicted density stays within max_drho of rho0 (and,
@@ -1837,6 +1879,8 @@ int sphx_gnn_get_output_case(sphx_ctx* ctx, int32_t c, double* out) { ENG_CALL(g
 int sphx_gnn_set_target_case(sphx_ctx* ctx, int32_t c, const double* target) { ENG_CALL(gnn_set_target(c, target)); }
 
 int sphx_gnn_train_step(sphx_ctx* ctx, double lr, double* loss) { ENG_CALL(gnn_train_step(lr, loss)); }
+
+int sphx_gnn_profile(sphx_ctx* ctx, int32_t reps, double* ms, int64_t* sizes) { ENG_CALL(gnn_profile(reps, ms, sizes)); }
 
 int sphx_surrogate_advance(sphx_ctx* ctx, int32_t windows, double max_drho, int32_t plain_every, int64_t* n_fallback,
                            int64_t* n_surrogate)

@@ -32,7 +32,7 @@ EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_set_para
             "sphx_diagnostics_case", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune",
             "sphx_gnn_num_params", "sphx_gnn_set_params", "sphx_gnn_get_params", "sphx_gnn_get_grad",
             "sphx_gnn_forward", "sphx_gnn_get_output_case", "sphx_gnn_set_target_case", "sphx_gnn_train_step",
-            "sphx_surrogate_advance")
+            "sphx_gnn_profile", "sphx_surrogate_advance")
 
 
 class SphxError(RuntimeError):
@@ -105,6 +105,7 @@ def load(path=None):
         "sphx_gnn_set_target_case": [vp, i32, vp],
         "sphx_gnn_train_step": [vp, d, pd],
         "sphx_surrogate_advance": [vp, i32, d, i32, pi64, pi64],
+        "sphx_gnn_profile": [vp, i32, pd, pi64],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -334,6 +335,12 @@ class Simulation:
         loss = C.c_double()
         self._check(self._L.sphx_gnn_train_step(self._h, float(lr), C.byref(loss)), "sphx_gnn_train_step")
         return loss.value
+
+    def gnn_profile(self, reps=20):
+        ms = (C.c_double * 4)()
+        sz = (C.c_int64 * 2)()
+        self._check(self._L.sphx_gnn_profile(self._h, int(reps), ms, sz), "sphx_gnn_profile")
+        return dict(edge_gemm=ms[0], messages=ms[1], node_gemm=ms[2], forward=ms[3], nodes=sz[0], edges=sz[1])
 
     def surrogate_advance(self, windows, max_drho=0.01, plain_every=0):
         a, b = C.c_int64(), C.c_int64()
