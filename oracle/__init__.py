@@ -30,7 +30,8 @@ class orc_params(C.Structure):
                 ("h", C.c_double), ("rho0", C.c_double), ("c0", C.c_double),
                 ("u_ref", C.c_double), ("cfl_ad", C.c_double), ("cfl_ac", C.c_double),
                 ("g", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("sigma0", C.c_double)]
+                ("sigma0", C.c_double), ("eta", C.c_double), ("p_background", C.c_double),
+                ("reinit_mode", C.c_int32), ("pad_", C.c_int32)]
 
 
 _lib = None
@@ -137,6 +138,9 @@ def params_from_case(case, sigma0=0.0):
     p.dp, p.h, p.rho0, p.c0 = case.dp, case.h, case.rho0, case.c0
     p.u_ref, p.cfl_ad, p.cfl_ac = case.u_ref, case.cfl_ad, case.cfl_ac
     p.sigma0 = sigma0
+    p.eta = float(getattr(case, "eta", 0.0))
+    p.p_background = float(getattr(case, "p_background", 0.0))
+    p.reinit_mode = int(getattr(case, "reinit_mode", 0))
     return p
 
 

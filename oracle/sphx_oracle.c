@@ -54,6 +54,10 @@ typedef struct {
     double g[3];         /* gravity vector */
     double lo[3], hi[3]; /* domain box for binning and escape checks */
     double sigma0;       /* reference kernel sum; <= 0: lattice sum computed here */
+    double eta;          /* dynamic viscosity (0: inviscid) */
+    double p_background; /* background pressure of the transport-velocity correction (0: off) */
+    int32_t reinit_mode; /* 0: free-surface re-initialisation, 1: flow without free surface */
+    int32_t pad_;
 } orc_params;
 
 typedef struct {
@@ -76,6 +80,9 @@ typedef struct {
     int32_t *in_idx, *ct_idx; /* ascending ids per particle */
     int configured;
     double t;
+    /* per advection step: viscous acceleration and transport-velocity
+     * acceleration of the current configuration, stride 3 */
+    double *av, *atv;
 } orc_sim;
 
 /* ------------------------------------------------------------------ */
@@ -201,6 +208,7 @@ void orc_destroy(orc_sim *s)
     free_config(s);
     free(s->x); free(s->v); free(s->rho); free(s->drho);
     free(s->xw); free(s->nrm);
+    free(s->av); free(s->atv);
     free(s);
 }
 
@@ -237,7 +245,7 @@ int orc_set_fluid(orc_sim *s, int64_t n, const double *pos, const double *vel,
                   const double *rho, const double *drho)
 {
     if (!s || n < 0 || (n > 0 && !pos) || n > INT32_MAX) return ORC_EINVAL;
-    free(s->x); free(s->v); free(s->rho); free(s->drho);
+    free(s->x); free(s->v); free(s->rho); free(s->drho); free(s->av); free(s->atv);
     free_config(s);
     s->nf = n;
     size_t m = (size_t)(n > 0 ? n : 1);
@@ -245,7 +253,9 @@ int orc_set_fluid(orc_sim *s, int64_t n, const double *pos, const double *vel,
     s->v = (double *)calloc(3 * m, sizeof(double));
     s->rho = (double *)calloc(m, sizeof(double));
     s->drho = (double *)calloc(m, sizeof(double));
-    if (!s->x || !s->v || !s->rho || !s->drho) return ORC_ENOMEM;
+    s->av = (double *)calloc(3 * m, sizeof(double));
+    s->atv = (double *)calloc(3 * m, sizeof(double));
+    if (!s->x || !s->v || !s->rho || !s->drho || !s->av || !s->atv) return ORC_ENOMEM;
     for (int64_t i = 0; i < n; ++i) {
         for (int k = 0; k < s->d; ++k) {
             s->x[3 * i + k] = pos[s->d * i + k];
@@ -491,7 +501,8 @@ int64_t orc_get_neighbors(const orc_sim *s, int kind, int64_t *off, int64_t *idx
 }
 
 /* ------------------------------------------------------------------ */
-/* Density re-initialisation for free-surface flow, Eq. (eqrhosum).
+/* Density re-initialisation, Eq. (eqrhosum) for free-surface flow and
+ * Eq. (eqrhosumnosurface) for flow without free surface (reinit_mode 1).
  * Reading: the kernel sum includes the particle itself (W(0)) and the wall
  * neighbours; the reference sum is the lattice sum with self. */
 void orc_density_reinit(orc_sim *s)
@@ -508,7 +519,8 @@ void orc_density_reinit(orc_sim *s)
             pair_geo g = frozen_geo(s, i, s->xw + 3 * (int64_t)s->ct_idx[q]);
             sigma += orc_kernel_W(s->d, s->p.h, g.r);
         }
-        s->rho[i] = fmax(s->rho[i], s->p.rho0 * sigma / s->sigma0);
+        double rho_sum = s->p.rho0 * sigma / s->sigma0;
+        s->rho[i] = s->p.reinit_mode ? rho_sum : fmax(s->rho[i], rho_sum);
     }
 }
 
@@ -545,8 +557,54 @@ static void wall_states(const orc_sim *s, int64_t w, const pair_geo *g,
     *rhoR = s->p.rho0 + *PR / (s->p.c0 * s->p.c0);
 }
 
+/* Physical shear force, Eq. (eqviscous), and the transport-velocity
+ * acceleration, Eq. (transport), of the current configuration:
+ *   av_i  = 2 sum_j m_j eta/(rho_i rho_j) (v_i - v_j)/r_ij W'_ij,
+ *   atv_i = -2 sum_j m_j p0/(rho_i rho_j) grad_i W_ij
+ *         =  2 sum_j m_j p0/(rho_i rho_j) W'_ij e_ij.
+ * Reading: for a wall neighbour m_j/rho_j is the wall volume and the wall
+ * velocity is zero (static wall); both are evaluated once per advection step,
+ * after the density re-initialisation, on the frozen configuration (the
+ * advection criterion carries the viscous time scale h^2/nu). */
+static void advection_forces(orc_sim *s)
+{
+    const double m = s->mass, eta = s->p.eta, p0 = s->p.p_background;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < s->nf; ++i) {
+        const double *vi = s->v + 3 * i;
+        double rho_i = s->rho[i];
+        double av[3] = {0.0, 0.0, 0.0}, at[3] = {0.0, 0.0, 0.0};
+        for (int64_t q = s->in_off[i]; q < s->in_off[i + 1]; ++q) {
+            int64_t j = s->in_idx[q];
+            pair_geo g = frozen_geo(s, i, s->xs + 3 * j);
+            const double *vj = s->v + 3 * j;
+            double cv = 2.0 * m * eta / (rho_i * s->rho[j]) / g.r * g.dW;
+            double ct = 2.0 * m * p0 / (rho_i * s->rho[j]) * g.dW;
+            for (int k = 0; k < 3; ++k) {
+                av[k] += cv * (vi[k] - vj[k]);
+                at[k] += ct * g.e[k];
+            }
+        }
+        for (int64_t q = s->ct_off[i]; q < s->ct_off[i + 1]; ++q) {
+            int64_t w = s->ct_idx[q];
+            pair_geo g = frozen_geo(s, i, s->xw + 3 * w);
+            double cv = 2.0 * s->vol_w * eta / rho_i / g.r * g.dW;
+            double ct = 2.0 * s->vol_w * p0 / rho_i * g.dW;
+            for (int k = 0; k < 3; ++k) {
+                av[k] += cv * vi[k];
+                at[k] += ct * g.e[k];
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            s->av[3 * i + k] = av[k];
+            s->atv[3 * i + k] = at[k];
+        }
+    }
+}
+
 /* Momentum equation, Eq. (riemannsph) second line, plus gravity (external
- * force): dv_i/dt = g - 2 sum_j m_j P* / (rho_i rho_j) grad_i W_ij
+ * force) and the shear force of the advection step (Eq. eqviscous, zero for
+ * inviscid flow): dv_i/dt = g + av_i - 2 sum_j m_j P* / (rho_i rho_j) grad_i W_ij
  *                 = g + 2 sum_j m_j P* / (rho_i rho_j) W'_ij e_ij,
  * with U_L = v_i . e_ij, U_R = v_j . e_ij, P_L = p_i, P_R = p_j. For a wall
  * neighbour m_j/rho_j is the wall particle volume. */
@@ -557,7 +615,7 @@ static void momentum_rate(const orc_sim *s, double *a)
     for (int64_t i = 0; i < s->nf; ++i) {
         const double *vi = s->v + 3 * i;
         double rho_i = s->rho[i], p_i = eos_p(s, rho_i);
-        double acc[3] = {s->p.g[0], s->p.g[1], s->p.g[2]};
+        double acc[3] = {s->p.g[0] + s->av[3 * i], s->p.g[1] + s->av[3 * i + 1], s->p.g[2] + s->av[3 * i + 2]};
         for (int64_t q = s->in_off[i]; q < s->in_off[i + 1]; ++q) {
             int64_t j = s->in_idx[q];
             pair_geo g = frozen_geo(s, i, s->xs + 3 * j);
@@ -629,21 +687,25 @@ static double vmax(const orc_sim *s)
 }
 
 /* Dual-criteria time steps, Eqs. (dt-advection) and (dt-relax).
- * Reading: inviscid flow, so the h^2/nu term is absent; |v|max in the
- * advection criterion is floored at the reference speed (the flow speed the
- * sound speed was chosen for, Section 2.1) so that a fluid at rest has a
- * finite step. */
+ * Reading: |v|max in the advection criterion is floored at the reference
+ * speed (the flow speed the sound speed was chosen for, Section 2.1) so that
+ * a fluid at rest has a finite step; nu = eta / rho0, and the h^2/nu term is
+ * absent for inviscid flow. */
 void orc_time_steps(const orc_sim *s, double *dt_ad, double *dt_ac)
 {
     double vm = vmax(s);
     *dt_ad = s->p.cfl_ad * s->p.h / fmax(vm, s->p.u_ref);
+    if (s->p.eta > 0.0) *dt_ad = fmin(*dt_ad, s->p.cfl_ad * s->p.h * s->p.h / (s->p.eta / s->p.rho0));
     *dt_ac = s->p.cfl_ac * s->p.h / (s->p.c0 + vm);
 }
 
 /* One acoustic sub-step of size dt: position-based Verlet, Section 7,
  * Eqs. (verlet-first-half), (verlet-first-mediate), (verlet-first-final).
  * Reading: the first half-step uses the density rate of the previous
- * sub-step; the last half-step uses the new velocity v^{n+1}.
+ * sub-step; the last half-step uses the new velocity v^{n+1}. With the
+ * transport-velocity correction the positions move with the transport
+ * velocity v + dt atv (Eq. transport over the sub-step), i.e. both position
+ * half-steps gain dt^2 atv / 2.
  * When a and drho_out are given they receive the two rates. */
 static int substep(orc_sim *s, double dt, double *a, double *drho_out)
 {
@@ -660,6 +722,9 @@ static int substep(orc_sim *s, double dt, double *a, double *drho_out)
         for (int k = 0; k < s->d; ++k) s->x[3 * i + k] += 0.5 * dt * s->v[3 * i + k];
         s->rho[i] += 0.5 * dt * s->drho[i];
     }
+    if (s->p.p_background != 0.0)
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < s->d; ++k) s->x[3 * i + k] += dt * dt * s->atv[3 * i + k];
     if (drho_out) memcpy(drho_out, s->drho, sizeof(double) * (size_t)n);
     for (int64_t i = 0; i < n; ++i) {
         if (isnan(s->rho[i])) return ORC_ENAN;
@@ -670,7 +735,8 @@ static int substep(orc_sim *s, double dt, double *a, double *drho_out)
 }
 
 /* The two rates of one sub-step of size dt from the current state, which is
- * left unchanged: dvdt n*dim (gravity included), drhodt n. */
+ * left unchanged: dvdt n*dim (gravity and the shear force of the current
+ * state included), drhodt n. */
 int orc_compute_rates(orc_sim *s, double dt, double *dvdt, double *drhodt)
 {
     if (!s || !s->configured) return ORC_EINVAL;
@@ -688,6 +754,7 @@ int orc_compute_rates(orc_sim *s, double dt, double *dvdt, double *drhodt)
     memcpy(v0, s->v, 3 * n * sizeof(double));
     memcpy(r0, s->rho, n * sizeof(double));
     memcpy(d0, s->drho, n * sizeof(double));
+    advection_forces(s);
     int rc = substep(s, dt, a, drhodt);
     for (int64_t i = 0; i < s->nf; ++i)
         for (int k = 0; k < s->d; ++k) dvdt[s->d * i + k] = a[3 * i + k];
@@ -700,7 +767,8 @@ int orc_compute_rates(orc_sim *s, double dt, double *dvdt, double *drhodt)
 }
 
 /* One advection step (Section 2.4) clipped to t_stop: the advection step
- * size, density re-initialisation at the start of the step, acoustic
+ * size, density re-initialisation and the shear and transport-velocity
+ * accelerations at the start of the step, acoustic
  * sub-steps until the advection step is covered (the last one clipped to
  * land on it), then the configuration update. Reading: each sub-step size
  * is min(dt_ac, remaining), with |v|max taken at the start of the sub-step;
@@ -720,6 +788,7 @@ int orc_advance(orc_sim *s, double t_stop, int32_t *nsub_out, double *t_out)
             t_end = t_stop;
         }
         orc_density_reinit(s);
+        advection_forces(s);
         size_t n = (size_t)(s->nf > 0 ? s->nf : 1);
         double *a = (double *)malloc(3 * n * sizeof(double));
         if (!a) return ORC_ENOMEM;

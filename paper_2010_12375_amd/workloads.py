@@ -64,6 +64,9 @@ class Case:
     column: tuple = ()             # (L, H[, W]) of the water column
     tank: tuple = ()               # (DL, DH[, DW]) of the tank interior
     seed: int = 0
+    eta: float = 0.0               # dynamic viscosity (0: inviscid)
+    p_background: float = 0.0      # transport-velocity background pressure (0: off)
+    reinit_mode: int = 0           # 0: free-surface density re-init, 1: no free surface
 
     @property
     def n_fluid(self) -> int:
@@ -191,6 +194,35 @@ def ensemble_cases(n_cases=64, seed=0, precision=FP32) -> List[Case]:
                             name=f"ens{c:02d}_dp{dp:g}_a{a:.3f}")
         out.append(case)
     return out
+
+
+def taylor_green_2d(dp=0.02, Re=100.0, U=1.0, seed=0, jitter=0.0, tvf=True, precision=FP64):
+    """Decaying Taylor-Green vortex in the periodic unit square (flow
+    without free surface): u = -U cos(2 pi x) sin(2 pi y), v = U sin(2 pi x)
+    cos(2 pi y), p = rho0 U^2 (cos(4 pi x) + cos(4 pi y)) / 4, viscosity
+    eta = rho0 U L / Re with L = 1, no gravity, c0 = 10 U; the velocity
+    decays as exp(-8 pi^2 nu t). With `tvf` the transport-velocity
+    correction uses the background pressure rho0 c0^2."""
+    n = int(round(1.0 / dp))
+    pos = _lattice((n, n), dp)
+    if jitter:
+        pos = _jitter(pos, dp, seed, jitter)
+    c0 = 10.0 * U
+    rho0 = 1.0
+    return Case(name=f"taylorgreen2d_dp{dp:g}_Re{Re:g}", dim=2, dp=dp, h=1.3 * dp, rho0=rho0, c0=c0, u_ref=U,
+                cfl_ad=0.25, cfl_ac=0.6, gravity=(0.0, 0.0, 0.0), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.0),
+                periodic=(1, 1, 0), fluid_pos=pos, wall_pos=np.zeros((0, 2)), wall_normal=np.zeros((0, 2)),
+                precision=precision, column=(1.0, 1.0), seed=seed, eta=rho0 * U / Re,
+                p_background=rho0 * c0 * c0 if tvf else 0.0, reinit_mode=1)
+
+
+def taylor_green_state(case, U=1.0):
+    """Initial velocity and density (from the pressure through the EoS)."""
+    x, y = case.fluid_pos[:, 0], case.fluid_pos[:, 1]
+    vel = np.stack([-U * np.cos(2 * np.pi * x) * np.sin(2 * np.pi * y),
+                    U * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)], axis=1)
+    p = case.rho0 * U * U * (np.cos(4 * np.pi * x) + np.cos(4 * np.pi * y)) / 4.0
+    return vel, case.rho0 + p / case.c0 ** 2
 
 
 def hydrostatic_column_2d(dp=0.05, L=1.0, H=1.0, seed=0, jitter=0.0):

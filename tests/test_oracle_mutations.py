@@ -35,15 +35,24 @@ MUTATIONS = [
     ("continuity_left_state", "sum += m / rho_j * (Us - UL) * g.dW;", "sum += m / rho_j * (Us - UR) * g.dW;", None),
     ("continuity_factor_two", "drho[i] = 2.0 * rho_i * sum;", "drho[i] = rho_i * sum;", None),
     ("reinit_without_self", "double sigma = W0;", "double sigma = 0.0;", None),
-    ("reinit_without_walls", "            sigma += orc_kernel_W(s->d, s->p.h, g.r);\n        }\n        s->rho[i]",
-     "        }\n        s->rho[i]", None),
+    ("reinit_without_walls", "            sigma += orc_kernel_W(s->d, s->p.h, g.r);\n        }\n        double rho_sum",
+     "        }\n        double rho_sum", None),
     ("predicate_not_strict", "< s->rc2) idx[w++] = j;", "<= s->rc2) idx[w++] = j;", None),
     ("verlet_full_first_position", "s->x[3 * i + k] += 0.5 * dt * s->v[3 * i + k];\n    }\n    momentum_rate",
      "s->x[3 * i + k] += dt * s->v[3 * i + k];\n    }\n    momentum_rate", None),
     ("acoustic_step_without_flow_speed", "/ (s->p.c0 + vm);", "/ (s->p.c0);", None),
     ("advection_step_no_floor", "/ fmax(vm, s->p.u_ref);", "/ fmax(vm, 1e-300);", None),
     ("eos_sign", "(rho - s->p.rho0); }", "(s->p.rho0 - rho); }", None),
-    ("gravity_dropped", "double acc[3] = {s->p.g[0], s->p.g[1], s->p.g[2]};", "double acc[3] = {0, 0, 0};", None),
+    ("gravity_dropped", "double acc[3] = {s->p.g[0] + s->av[3 * i], s->p.g[1] + s->av[3 * i + 1], s->p.g[2] + s->av[3 * i + 2]};",
+     "double acc[3] = {s->av[3 * i], s->av[3 * i + 1], s->av[3 * i + 2]};", None),
+    ("viscous_sign", "av[k] += cv * (vi[k] - vj[k]);", "av[k] += cv * (vj[k] - vi[k]);", None),
+    ("viscous_factor_two", "double cv = 2.0 * m * eta", "double cv = m * eta", None),
+    ("viscous_wall_dropped", "av[k] += cv * vi[k];", "av[k] += 0.0 * cv * vi[k];", None),
+    ("viscous_not_applied", "s->p.g[0] + s->av[3 * i],", "s->p.g[0],", None),
+    ("viscous_time_step_missing", "if (s->p.eta > 0.0) *dt_ad", "if (0) *dt_ad", None),
+    ("transport_sign", "s->x[3 * i + k] += dt * dt * s->atv[3 * i + k];", "s->x[3 * i + k] -= dt * dt * s->atv[3 * i + k];", None),
+    ("no_surface_reinit_keeps_max", "s->rho[i] = s->p.reinit_mode ? rho_sum : fmax(s->rho[i], rho_sum);",
+     "s->rho[i] = fmax(s->rho[i], rho_sum);", None),
 ]
 
 
@@ -65,6 +74,7 @@ def test_pins_catch_planted_mistake(name, old, new, occ):
         env = dict(os.environ, SPHX_ORACLE_LIB=so, OMP_NUM_THREADS="2")
         # a planted mistake that makes a pin run forever also counts as caught
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            "--timeout", "60", "--timeout-method", "thread", os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                            "--timeout", "60", "--timeout-method", "thread", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_viscous.py")],
                            env=env, capture_output=True, text=True, cwd=ROOT, timeout=900)
         assert r.returncode != 0, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
