@@ -78,6 +78,12 @@ typedef struct {
     double lo[3], hi[3]; /* domain box: binning grid; fluid outside it is an escape */
     double sigma0;       /* reference kernel sum of Eq. eqrhosum; <= 0: the lattice sum
                             over the dp lattice, self included, computed by the library */
+    double eta;          /* dynamic viscosity of Eq. eqviscous (0: inviscid); adds the
+                            h^2/nu limit (nu = eta/rho0) to the advection step */
+    double p_background; /* background pressure p0 of the transport-velocity correction,
+                            Eq. transport (0: off; for flows without free surface) */
+    int32_t reinit_mode; /* 0: Eq. eqrhosum (free surface), 1: Eq. eqrhosumnosurface */
+    int32_t pad_;        /* unused, 0 */
 } sphx_params;
 
 typedef struct {
@@ -223,13 +229,14 @@ int sphx_profile(sphx_ctx* ctx, int32_t reps, double* ms);
 int sphx_counts(sphx_ctx* ctx, int64_t* out);
 int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out);
 
-/* Choose the lanes per particle of the pair kernels (4 or 8) by timing
+/* Choose the lanes per particle of the pair kernels (4, 8 or 16) by timing
  * `reps` launches of the pressure and density relaxation of the batch with
- * each, and rebuild the configuration for the faster one (*lanes, may be
- * NULL). The lists are the same; the per-particle sums are combined in a
+ * each, and rebuild the configuration for the fastest one (*lanes, may be
+ * NULL; times, may be NULL: 3 entries, ms per relaxation pair for 4, 8, 16
+ * lanes). The lists are the same; the per-particle sums are combined in a
  * different order, so later results can differ from the default's at
  * rounding level. Requires a configuration. */
-int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes);
+int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes, double* times);
 
 /* ---------------------------------------------------------------------
  * Message-passing surrogate (2D contexts only; SPHX_EINVAL in 3D).

@@ -43,7 +43,10 @@ constexpr int NBR_SHIFT = 26;
 constexpr uint32_t NBR_MASK = (1u << NBR_SHIFT) - 1u;
 constexpr int TILE = 64;    // particle slots per tile; cases own whole tiles
 constexpr int BLOCK = 256;  // threads per block of every particle kernel
-constexpr int BATCH = 4;    // list entries / candidate rounds loaded ahead per lane
+#ifndef SPHX_PAIR_BATCH
+#define SPHX_PAIR_BATCH 4
+#endif
+constexpr int BATCH = SPHX_PAIR_BATCH;  // list entries / candidate rounds loaded ahead per lane
 constexpr uint32_t NO_ENTRY = 0xffffffffu;  // stencil code 63 never occurs
 constexpr int VSLOTS = 64;  // slots the density relaxation folds its block maxima into
 
@@ -105,6 +108,10 @@ template <typename real> struct KP {
     double rc2, sigma0, rho0d;
     double cfl_ad_h, cfl_ac_h, u_ref, c0d;
     int maxn, maxw;                           // list capacity per particle (same for every case)
+    real eta, p0;                             // dynamic viscosity, transport background pressure
+    double visc_dt;                           // CFL_ad h^2 / nu (0: inviscid)
+    int reinit_mode;                          // 0: free surface (max), 1: no free surface
+    int adv_forces;                           // eta > 0 or p0 != 0
     int case_id;
     int fbase, nf, fcap;                      // fluid slots [fbase, fbase + fcap), the first nf used
     int wbase, nw;                            // wall slots [wbase, wbase + nw)
@@ -724,7 +731,8 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
 // S5: the dual-criteria clock (Eqs. dt-advection, dt-relax).
 
 // Sub-step 0 of a new advection step (one thread): dt_ad from |v|max floored
-// at U_ref, clipped to the stop time, and the first acoustic step
+// at U_ref and, for viscous flow, the h^2/nu limit, clipped to the stop
+// time, and the first acoustic step
 // min(dt_ac, dt_ad). Inactive when the clock has reached the stop time, the
 // step target is reached or an error is pending.
 template <typename real>
@@ -734,6 +742,7 @@ __device__ void prepare_step(const KP<real>& P, Ctrl* __restrict__ ctrl)
     const double t = ctrl->t, t_stop = ctrl->t_stop, vmax = ctrl->vmax;
     if (ctrl->err == 0 && t < t_stop && ctrl->steps_done < ctrl->steps_target) {
         double dt_ad = P.cfl_ad_h / fmax(vmax, P.u_ref);
+        if (P.visc_dt > 0.0) dt_ad = fmin(dt_ad, P.visc_dt);
         double t_end = t + dt_ad;
         if (t_end >= t_stop) {
             dt_ad = t_stop - t;
@@ -892,10 +901,87 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
     real dev_sum = (real)(P.rho0d * (sigma / P.sigma0 - 1.0));
     R4<real> s = st[i];
     if (D == 2) {
-        if (dev_sum > s.z) { s.z = dev_sum; st[i] = s; }
+        if (P.reinit_mode || dev_sum > s.z) { s.z = dev_sum; st[i] = s; }
     } else {
-        if (dev_sum > s.w) { s.w = dev_sum; st[i] = s; }
+        if (P.reinit_mode || dev_sum > s.w) { s.w = dev_sum; st[i] = s; }
     }
+}
+
+// Shear force, Eq. (eqviscous), and transport-velocity acceleration,
+// Eq. (transport), of each particle on the frozen configuration, once per
+// advection step after the re-initialisation (`gate`: for the cases starting
+// a step), for the cases that have either:
+//   av  = 2 sum_j m eta/(rho_i rho_j) (v_i - v_j)/r W'   (walls: V_w/rho_i, v_w = 0)
+//   atv = 2 sum_j m p0/(rho_i rho_j) W' e_ij             (walls: V_w/rho_i)
+// into avt[2 i] and avt[2 i + 1]. T lanes share a particle.
+template <int D, typename real, int T>
+__global__ __launch_bounds__(BLOCK) void k_adv_forces(
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, const Ctrl* __restrict__ ctrl_all, int gate,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
+    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
+    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, R4<real>* __restrict__ avt)
+{
+    const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
+    const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
+    const Ctrl* ctrl = ctrl_all + P.case_id;
+    if (!P.adv_forces) return;
+    if (gate && (!ctrl->ss[0].active || ctrl->midstep || ctrl->err)) return;
+    const int i = i0 + (int)threadIdx.x / T;
+    const int l = threadIdx.x % T;
+    if (i >= P.fbase + P.nf) return;
+    using G = typename GeoSel<D, real>::T;
+    const G oi = geo[i];
+    const R4<real> si = st[i];
+    const real vi[3] = {si.x, si.y, D == 3 ? si.z : (real)0};
+    const real rho_i = P.rho0 + (D == 2 ? si.z : si.w);
+    const real inv_rho_i = (real)1 / rho_i;
+    real av[3] = {0, 0, 0}, at[3] = {0, 0, 0};
+    struct FluidJ { G o; R4<real> s; };
+    for_pairs<T, BATCH>(
+        nbr, i, ncnt[i], P.maxn, l,
+        [&](uint32_t e) {
+            uint32_t j = e & NBR_MASK;
+            FluidJ r;
+            r.o = geo[j];
+            r.s = st[j];
+            return r;
+        },
+        [&](uint32_t e, const FluidJ& r) {
+            Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+            const R4<real>& sj = r.s;
+            const real rho_j = P.rho0 + (D == 2 ? sj.z : sj.w);
+            const real w = P.m * inv_rho_i / rho_j * q.dW;
+            const real cv = (real)2 * P.eta * w / q.r;
+            const real ct = (real)2 * P.p0 * w;
+            av[0] += cv * (vi[0] - sj.x);
+            av[1] += cv * (vi[1] - sj.y);
+            if (D == 3) av[2] += cv * (vi[2] - sj.z);
+            at[0] += ct * q.e[0];
+            at[1] += ct * q.e[1];
+            if (D == 3) at[2] += ct * q.e[2];
+        });
+    for_pairs<T, BATCH>(
+        wnb, i, wcnt[i], P.maxw, l, [&](uint32_t e) { return wgeo[e & NBR_MASK]; },
+        [&](uint32_t e, const G& ow) {
+            Pair<D, real> q = pair_geo<D, real>(P, oi, ow, e >> NBR_SHIFT);
+            const real w = P.vw * inv_rho_i * q.dW;
+            const real cv = (real)2 * P.eta * w / q.r;
+            const real ct = (real)2 * P.p0 * w;
+            av[0] += cv * vi[0];
+            av[1] += cv * vi[1];
+            if (D == 3) av[2] += cv * vi[2];
+            at[0] += ct * q.e[0];
+            at[1] += ct * q.e[1];
+            if (D == 3) at[2] += ct * q.e[2];
+        });
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        av[k] = group_sum<T>(av[k]);
+        at[k] = group_sum<T>(at[k]);
+    }
+    if (l != 0) return;
+    avt[2 * (size_t)i] = R4<real>{av[0], av[1], av[2], (real)0};
+    avt[2 * (size_t)i + 1] = R4<real>{at[0], at[1], at[2], (real)0};
 }
 
 // ---------------------------------------------------------------------
@@ -911,7 +997,8 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
-    real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all)
+    real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all,
+    const R4<real>* __restrict__ avt)
 {
     const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
     const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
@@ -1023,6 +1110,12 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     acc[0] += P.g[0];
     acc[1] += P.g[1];
     acc[2] += P.g[2];
+    if (avt && P.adv_forces) {  // shear force of the advection step
+        const R4<real> a = avt[2 * (size_t)i];
+        acc[0] += a.x;
+        acc[1] += a.y;
+        acc[2] += a.z;
+    }
     R4<real> o;
     o.x = vi[0] + dt * acc[0];
     o.y = vi[1] + dt * acc[1];
@@ -1055,7 +1148,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
     double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
-    unsigned long long* __restrict__ vslot_all, int q)
+    unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i0 = pair_block_first<T>(b);
@@ -1137,6 +1230,14 @@ __global__ __launch_bounds__(BLOCK) void k_density(
             x0[i] = x0[i] + hd * (double)vi[0];
             x1[i] = x1[i] + hd * (double)vi[1];
             if (D == 3) x2[i] = x2[i] + hd * (double)vi[2];
+            if (avt && P.p0 != (real)0) {
+                // positions move with the transport velocity v + dt atv
+                const R4<real> a = avt[2 * (size_t)i + 1];
+                const double d2 = dtd * dtd;
+                x0[i] = x0[i] + d2 * (double)a.x;
+                x1[i] = x1[i] + d2 * (double)a.y;
+                if (D == 3) x2[i] = x2[i] + d2 * (double)a.z;
+            }
             R4<real> sn;
             sn.x = vi[0];
             sn.y = vi[1];

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -67,7 +68,7 @@ struct EngineBase {
     virtual int diagnostics(int c, sphx_diag* out) = 0;
     virtual int profile(int32_t reps, double* ms) = 0;
     virtual int counts(int c, int64_t* out) = 0;
-    virtual int autotune(int32_t reps, int32_t* lanes) = 0;
+    virtual int autotune(int32_t reps, int32_t* lanes, double* times) = 0;
     virtual int set_params_case(int c, const sphx_params* q) = 0;
     virtual int gnn_set_params(const float* p, int64_t n) = 0;
     virtual int gnn_get(int which, float* p, int64_t n) = 0;
@@ -131,6 +132,7 @@ struct Engine final : EngineBase {
     int32_t* id[2] = {};
     int32_t* cell[2] = {};
     R4<real>* hf = nullptr;
+    R4<real>* avt = nullptr;  // per particle: shear and transport accelerations of the advection step
     uint32_t* nbr = nullptr;
     int32_t* ncnt = nullptr;
     uint32_t* wnb = nullptr;
@@ -301,6 +303,13 @@ struct Engine final : EngineBase {
         P.u_ref = q.u_ref;
         P.maxn = maxn;
         P.maxw = maxw;
+        if (!(q.eta >= 0.0) || !std::isfinite(q.eta) || !std::isfinite(q.p_background))
+            return ctx->fail(SPHX_EINVAL, case_tag(c) + "bad viscosity or background pressure");
+        P.eta = (real)q.eta;
+        P.p0 = (real)q.p_background;
+        P.visc_dt = q.eta > 0.0 ? q.cfl_ad * h * h / (q.eta / q.rho0) : 0.0;
+        P.reinit_mode = q.reinit_mode ? 1 : 0;
+        P.adv_forces = (q.eta > 0.0 || q.p_background != 0.0) ? 1 : 0;
         P.case_id = c;
         P.cbase = cbase;
         P.ncell = (int)nc;
@@ -344,6 +353,24 @@ struct Engine final : EngineBase {
 
     int nblk_scan() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
     int pair_blocks() const { return (int)((long long)ntot * ln / BLOCK); }
+
+    // Whether any case has a shear force or a transport-velocity correction.
+    bool any_adv() const
+    {
+        for (int c = 0; c < C; ++c)
+            if (hP[c].adv_forces) return true;
+        return false;
+    }
+    R4<real>* avt_arg() const { return any_adv() ? avt : nullptr; }
+
+    // Call f with the lanes per particle of the pair kernels as a constant.
+    template <typename F>
+    void by_lanes(F&& f)
+    {
+        if (ln == 4) f(std::integral_constant<int, 4>{});
+        else if (ln == 8) f(std::integral_constant<int, 8>{});
+        else f(std::integral_constant<int, 16>{});
+    }
 
     int upload_params()
     {
@@ -492,6 +519,7 @@ struct Engine final : EngineBase {
         }
         RETCHK(dalloc(L, tcase, n / TILE));
         RETCHK(dalloc(L, hf, n));
+        RETCHK(dalloc(L, avt, 2 * (size_t)n));
         RETCHK(dalloc(L, nbr, (size_t)maxn * n));
         RETCHK(dalloc(L, ncnt, n));
         RETCHK(dalloc(L, wnb, (size_t)maxw * n));
@@ -712,8 +740,7 @@ struct Engine final : EngineBase {
         k_place_fluid<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, ntot, perm, key, fstart, x[a][0],
                                                      x[a][1], x[a][2], st[a], dr3[a], id[a], geo[a], x[b][0], x[b][1],
                                                      x[b][2], st[b], dr3[b], id[b], cell[b], geo[b]);
-        if (ln == 4) launch_neighbors<4>(force, b);
-        else launch_neighbors<8>(force, b);
+        by_lanes([&](auto t) { launch_neighbors<decltype(t)::value>(force, b); });
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -722,18 +749,18 @@ struct Engine final : EngineBase {
     void launch_substep(int a, int q, int adv, int finalize, real* acc, real* dro)
     {
         const int nb = pair_blocks();
+        R4<real>* av = avt_arg();
         k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a],
-                                                    dr3[a], hf, acc, q, adv, vslot);
+                                                    dr3[a], hf, acc, q, adv, vslot, av);
         k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                   hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro, vslot, q);
+                                                   hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro, vslot, q, av);
     }
 
     // Pressure and density relaxation of sub-step q on set a; `adv`: close
     // sub-step q - 1 first (inside the pressure relaxation).
     int enqueue_substep(int a, int q, int adv, int finalize, real* acc, real* dro)
     {
-        if (ln == 4) launch_substep<4>(a, q, adv, finalize, acc, dro);
-        else launch_substep<8>(a, q, adv, finalize, acc, dro);
+        by_lanes([&](auto t) { launch_substep<decltype(t)::value>(a, q, adv, finalize, acc, dro); });
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -741,10 +768,24 @@ struct Engine final : EngineBase {
     int enqueue_reinit(int gate, int a)
     {
         const int nb = pair_blocks();
-        if (ln == 4)
-            k_reinit<D, real, 4><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
-        else
-            k_reinit<D, real, 8><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
+        by_lanes([&](auto t) {
+            k_reinit<D, real, decltype(t)::value><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt,
+                                                                      wnb, wcnt, st[a]);
+        });
+        HIPCHK(hipGetLastError());
+        return SPHX_OK;
+    }
+
+    // Shear and transport accelerations of the advection step (after the
+    // re-initialisation); `gate`: for the cases starting a step.
+    int enqueue_adv_forces(int gate, int a)
+    {
+        if (!any_adv()) return SPHX_OK;
+        const int nb = pair_blocks();
+        by_lanes([&](auto t) {
+            k_adv_forces<D, real, decltype(t)::value><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr,
+                                                                          ncnt, wnb, wcnt, st[a], avt);
+        });
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -755,6 +796,7 @@ struct Engine final : EngineBase {
     int enqueue_step(int a)
     {
         RETCHK(enqueue_reinit(1, a));
+        RETCHK(enqueue_adv_forces(1, a));
         for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr));
         k_step_end<real><<<C, 64, 0, s>>>(dP, ctrl, vslot, nsub_q - 1);
         HIPCHK(hipGetLastError());
@@ -815,7 +857,10 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
-    size_t ell_index(int i, int k, int mx) const { return ln == 4 ? ell_at<4>(i, k, mx) : ell_at<8>(i, k, mx); }
+    size_t ell_index(int i, int k, int mx) const
+    {
+        return ln == 4 ? ell_at<4>(i, k, mx) : ln == 8 ? ell_at<8>(i, k, mx) : ell_at<16>(i, k, mx);
+    }
 
     int get_neighbors(int c, int kind, int64_t* off, int64_t* idx, int64_t cap_idx, int64_t* n_out) override
     {
@@ -878,7 +923,10 @@ struct Engine final : EngineBase {
         RETCHK(sync_ctrl());
         const KP<real>& P = hP[c];
         double vmax = hctrl[c].vmax;
-        if (dt_ad) *dt_ad = P.cfl_ad_h / std::fmax(vmax, P.u_ref);
+        if (dt_ad) {
+            *dt_ad = P.cfl_ad_h / std::fmax(vmax, P.u_ref);
+            if (P.visc_dt > 0.0) *dt_ad = std::fmin(*dt_ad, P.visc_dt);
+        }
         if (dt_ac) *dt_ac = P.cfl_ac_h / (P.c0d + vmax);
         return SPHX_OK;
     }
@@ -917,6 +965,7 @@ struct Engine final : EngineBase {
         }
         hctrl[c].err = 0;
         RETCHK(push_ctrl());
+        RETCHK(enqueue_adv_forces(0, cur));
         RETCHK(enqueue_substep(cur, 0, 0, 0, acc_out, drho_out));
         const KP<real>& P = hP[c];
         if (dvdt && P.nf > 0) {
@@ -1084,11 +1133,12 @@ struct Engine final : EngineBase {
         const int a = cur;
         RETCHK(time_launches(reps, &ms[0], [&] {
             k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                        st[a], dr3[a], hf, nullptr, 0, 0, vslot);
+                                                        st[a], dr3[a], hf, nullptr, 0, 0, vslot, avt_arg());
         }));
         RETCHK(time_launches(reps, &ms[1], [&] {
             k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                       hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], nullptr, vslot, 0);
+                                                       hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], nullptr, vslot, 0,
+                                                       avt_arg());
         }));
         // the list build is idempotent on the current set
         RETCHK(time_launches(reps, &ms[2], [&] { launch_neighbors<T>(1, a); }));
@@ -1115,8 +1165,9 @@ struct Engine final : EngineBase {
             hctrl[c].err = 0;
         }
         RETCHK(push_ctrl());
-        if (ln == 4) RETCHK(profile_t<4>(reps, ms));
-        else RETCHK(profile_t<8>(reps, ms));
+        int rc_t = SPHX_OK;
+        by_lanes([&](auto t) { rc_t = profile_t<decltype(t)::value>(reps, ms); });
+        RETCHK(rc_t);
         RETCHK(sync_ctrl());
         int rc = first_error();
         RETCHK(restore_state(saved));
@@ -1152,26 +1203,35 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
-    // Pick the lanes per particle of the pair kernels (4 or 8) by timing one
-    // pressure and one density relaxation of every case with each; the lists
+    // Pick the lanes per particle of the pair kernels (4, 8 or 16) by timing
+    // the pressure and density relaxations of every case with each; the lists
     // are rebuilt in the chosen layout (the same lists; sums are combined in
     // a different order, so results change at rounding level).
-    int autotune(int32_t reps, int32_t* lanes) override
+    int autotune(int32_t reps, int32_t* lanes, double* times) override
     {
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
         if (reps < 1) return ctx->fail(SPHX_EINVAL, "bad repetition count");
-        const int cand[2] = {4, 8};
+        const int cand[3] = {4, 8, 16};
+        double tk[3] = {1e300, 1e300, 1e300};
+        // each candidate timed twice, in forward then in reverse order (the
+        // first launches after a rebuild run on a cold GPU); its best counts
+        for (int pass = 0; pass < 2; ++pass)
+            for (int kk = 0; kk < 3; ++kk) {
+                const int k = pass == 0 ? kk : 2 - kk;
+                ln = cand[k];
+                drop_graphs();
+                RETCHK(build_neighbors());
+                double ms[4];
+                RETCHK(profile(reps, ms));
+                tk[k] = std::fmin(tk[k], ms[0] + ms[1]);
+            }
         double best = 1e300;
-        int best_ln = ln;
-        for (int t : cand) {
-            ln = t;
-            RETCHK(build_neighbors());
-            double ms[4];
-            RETCHK(profile(reps, ms));
-            double tt = ms[0] + ms[1];
-            if (tt < best) {
-                best = tt;
-                best_ln = t;
+        int best_ln = cand[0];
+        for (int k = 0; k < 3; ++k) {
+            if (times) times[k] = tk[k];
+            if (tk[k] < best) {
+                best = tk[k];
+                best_ln = cand[k];
             }
         }
         ln = best_ln;
@@ -1207,6 +1267,7 @@ struct Engine final : EngineBase {
         hP[c].wbase = old.wbase;
         hP[c].nw = old.nw;
         RETCHK(upload_params());
+        drop_graphs();  // the queue may gain or lose the advection-step forces
         configured = false;
         return SPHX_OK;
     }
@@ -1398,14 +1459,11 @@ struct Engine final : EngineBase {
         gn.E = etot;
         RETCHK(gnn_edges_alloc(gn.E, train));
         if constexpr (D == 2) {
-            if (ln == 4)
-                gnn::k_gnn_edges<real, 4><<<nblk(N), BLOCK, 0, s>>>(dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt,
-                                                                   geo[cur], wgeo, st[cur], gn.edst, gn.erev, gn.G,
-                                                                   gn.F);
-            else
-                gnn::k_gnn_edges<real, 8><<<nblk(N), BLOCK, 0, s>>>(dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt,
-                                                                   geo[cur], wgeo, st[cur], gn.edst, gn.erev, gn.G,
-                                                                   gn.F);
+            by_lanes([&](auto t) {
+                gnn::k_gnn_edges<real, decltype(t)::value><<<nblk(N), BLOCK, 0, s>>>(
+                    dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt, geo[cur], wgeo, st[cur], gn.edst, gn.erev, gn.G,
+                    gn.F);
+            });
         }
         HIPCHK(hipGetLastError());
         return SPHX_OK;
@@ -1661,7 +1719,11 @@ struct Engine final : EngineBase {
                 continue;
             }
             RETCHK(gnn_forward_impl(false));
-            for (int c = 0; c < C; ++c) dtc[c] = 2.0 * hP[c].cfl_ad_h / std::fmax(hctrl[c].vmax, hP[c].u_ref);
+            for (int c = 0; c < C; ++c) {
+                double dt_ad = hP[c].cfl_ad_h / std::fmax(hctrl[c].vmax, hP[c].u_ref);
+                if (hP[c].visc_dt > 0.0) dt_ad = std::fmin(dt_ad, hP[c].visc_dt);
+                dtc[c] = 2.0 * dt_ad;
+            }
             HIPCHK(hipMemcpyAsync(gn.dtc, dtc.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
             gnn::k_gnn_check<real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, gn.dtc, gn.Y, st[cur], gn.tmax);
             HIPCHK(hipGetLastError());
@@ -1860,7 +1922,10 @@ int sphx_counts(sphx_ctx* ctx, int64_t* out) { ENG_CALL(counts(-1, out)); }
 
 int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out) { ENG_CALL(counts(c, out)); }
 
-int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes) { ENG_CALL(autotune(reps, lanes)); }
+int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes, double* times)
+{
+    ENG_CALL(autotune(reps, lanes, times));
+}
 
 int sphx_set_params_case(sphx_ctx* ctx, int32_t c, const sphx_params* params) { ENG_CALL(set_params_case(c, params)); }
 

@@ -46,7 +46,8 @@ class sphx_params(C.Structure):
                 ("nsub_queue", C.c_int32), ("dp", C.c_double), ("h", C.c_double), ("rho0", C.c_double),
                 ("c0", C.c_double), ("u_ref", C.c_double), ("cfl_ad", C.c_double), ("cfl_ac", C.c_double),
                 ("gravity", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("sigma0", C.c_double)]
+                ("sigma0", C.c_double), ("eta", C.c_double), ("p_background", C.c_double),
+                ("reinit_mode", C.c_int32), ("pad_", C.c_int32)]
 
 
 class sphx_diag(C.Structure):
@@ -96,7 +97,7 @@ def load(path=None):
         "sphx_profile": [vp, i32, pd],
         "sphx_counts": [vp, pi64],
         "sphx_counts_case": [vp, i32, pi64],
-        "sphx_autotune": [vp, i32, C.POINTER(i32)],
+        "sphx_autotune": [vp, i32, C.POINTER(i32), pd],
         "sphx_gnn_set_params": [vp, vp, i64],
         "sphx_gnn_get_params": [vp, vp, i64],
         "sphx_gnn_get_grad": [vp, vp, i64],
@@ -143,6 +144,9 @@ def params_from_case(case, precision=None, nsub_queue=0, sigma0=0.0):
     p.dp, p.h, p.rho0, p.c0 = case.dp, case.h, case.rho0, case.c0
     p.u_ref, p.cfl_ad, p.cfl_ac = case.u_ref, case.cfl_ad, case.cfl_ac
     p.sigma0 = sigma0
+    p.eta = float(getattr(case, "eta", 0.0))
+    p.p_background = float(getattr(case, "p_background", 0.0))
+    p.reinit_mode = int(getattr(case, "reinit_mode", 0))
     return p
 
 
@@ -348,7 +352,10 @@ class Simulation:
                                                    C.byref(a), C.byref(b)), "sphx_surrogate_advance")
         return a.value, b.value
 
-    def autotune(self, reps=10):
+    def autotune(self, reps=10, with_times=False):
         lanes = C.c_int32()
-        self._check(self._L.sphx_autotune(self._h, int(reps), C.byref(lanes)), "sphx_autotune")
+        times = (C.c_double * 3)()
+        self._check(self._L.sphx_autotune(self._h, int(reps), C.byref(lanes), times), "sphx_autotune")
+        if with_times:
+            return lanes.value, dict(zip((4, 8, 16), times[:]))
         return lanes.value

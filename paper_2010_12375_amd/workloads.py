@@ -202,7 +202,9 @@ def taylor_green_2d(dp=0.02, Re=100.0, U=1.0, seed=0, jitter=0.0, tvf=True, prec
     cos(2 pi y), p = rho0 U^2 (cos(4 pi x) + cos(4 pi y)) / 4, viscosity
     eta = rho0 U L / Re with L = 1, no gravity, c0 = 10 U; the velocity
     decays as exp(-8 pi^2 nu t). With `tvf` the transport-velocity
-    correction uses the background pressure rho0 c0^2."""
+    correction uses the background pressure 0.1 rho0 c0^2 (the paper gives no
+    value; rho0 c0^2 makes the correction applied over each acoustic sub-step
+    overshoot, 0.1 rho0 c0^2 stays stable)."""
     n = int(round(1.0 / dp))
     pos = _lattice((n, n), dp)
     if jitter:
@@ -213,7 +215,7 @@ def taylor_green_2d(dp=0.02, Re=100.0, U=1.0, seed=0, jitter=0.0, tvf=True, prec
                 cfl_ad=0.25, cfl_ac=0.6, gravity=(0.0, 0.0, 0.0), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.0),
                 periodic=(1, 1, 0), fluid_pos=pos, wall_pos=np.zeros((0, 2)), wall_normal=np.zeros((0, 2)),
                 precision=precision, column=(1.0, 1.0), seed=seed, eta=rho0 * U / Re,
-                p_background=rho0 * c0 * c0 if tvf else 0.0, reinit_mode=1)
+                p_background=0.1 * rho0 * c0 * c0 if tvf else 0.0, reinit_mode=1)
 
 
 def taylor_green_state(case, U=1.0):

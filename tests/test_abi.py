@@ -45,7 +45,7 @@ def test_binding_layout_matches_header_structs():
         for part in decl.split(" ", 1)[1].split(","):
             names.append(re.sub(r"\[.*\]", "", part).strip())
     assert names == [f[0] for f in sphx.sphx_params._fields_]
-    assert ctypes.sizeof(sphx.sphx_params) == 4 * 6 + 8 * (7 + 9 + 1)
+    assert ctypes.sizeof(sphx.sphx_params) == 4 * 8 + 8 * (7 + 9 + 3)
     assert ctypes.sizeof(sphx.sphx_diag) == 8 * 12
 
 

@@ -201,7 +201,7 @@ def test_autotune_keeps_lists_and_rates():
     g.build_neighbors()
     lanes = g.autotune(5)
     say("autotuned lanes", lanes)
-    assert lanes in (4, 8)
+    assert lanes in (4, 8, 16)
     for k, (c, st) in enumerate(zip(cases, states)):
         o = oracle_for(c, st)
         o.build_config()
