@@ -34,6 +34,11 @@ class orc_params(C.Structure):
                 ("reinit_mode", C.c_int32), ("pad_", C.c_int32)]
 
 
+class orc_wall_motion(C.Structure):
+    _fields_ = [("amp", C.c_double * 3), ("omega", C.c_double), ("roll", C.c_double),
+                ("pivot", C.c_double * 3)]
+
+
 _lib = None
 
 
@@ -68,6 +73,10 @@ def lib():
         L.orc_set_fluid.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_set_walls.restype = C.c_int
         L.orc_set_walls.argtypes = [vp, i64, vp, vp]
+        L.orc_set_wall_motion.restype = C.c_int
+        L.orc_set_wall_motion.argtypes = [vp, C.POINTER(orc_wall_motion), vp]
+        L.orc_wall_kinematics.restype = C.c_int
+        L.orc_wall_kinematics.argtypes = [vp, d, vp, vp, vp]
         L.orc_build_config.restype = C.c_int
         L.orc_build_config.argtypes = [vp]
         L.orc_get_neighbors.restype = i64
@@ -145,7 +154,7 @@ def params_from_case(case, sigma0=0.0):
 
 
 class Oracle:
-    """One FP64 oracle simulation (fluid body + static wall body)."""
+    """One FP64 oracle simulation (fluid body + wall body, static or moving)."""
 
     def __init__(self, case=None, params=None, sigma0=0.0, with_walls=True):
         self._L = lib()
@@ -206,6 +215,31 @@ class Oracle:
         normal = _f64(normal)
         self._check(self._L.orc_set_walls(self._h, pos.shape[0], _ptr(pos), _ptr(normal)),
                     "set_walls")
+
+    def set_wall_motion(self, amp=(0.0, 0.0, 0.0), omega=0.0, roll=0.0, pivot=(0.0, 0.0, 0.0),
+                        moving=None, static=False):
+        """Prescribed rigid wall motion (static=True: walls static again);
+        `moving`: one flag per wall particle (None: all move)."""
+        if static:
+            self._check(self._L.orc_set_wall_motion(self._h, None, None), "set_wall_motion")
+            return
+        m = orc_wall_motion()
+        for k in range(3):
+            m.amp[k] = float(amp[k]) if k < len(amp) else 0.0
+            m.pivot[k] = float(pivot[k]) if k < len(pivot) else 0.0
+        m.omega, m.roll = float(omega), float(roll)
+        flags = None if moving is None else np.ascontiguousarray(moving, dtype=np.int32)
+        self._flags = flags
+        self._check(self._L.orc_set_wall_motion(self._h, C.byref(m), _ptr(flags)), "set_wall_motion")
+
+    def wall_kinematics(self, t, n_wall):
+        """(positions, normals, velocities) of the wall particles at time t."""
+        pos = np.zeros((n_wall, self.dim))
+        nrm = np.zeros((n_wall, self.dim))
+        vel = np.zeros((n_wall, self.dim))
+        self._check(self._L.orc_wall_kinematics(self._h, float(t), _ptr(pos), _ptr(nrm), _ptr(vel)),
+                    "wall_kinematics")
+        return pos, nrm, vel
 
     def build_config(self):
         self._check(self._L.orc_build_config(self._h), "build_config")

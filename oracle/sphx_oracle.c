@@ -3,7 +3,8 @@
  * compressible SPH step of the SPHinXsys paper (Zhang et al., arXiv
  * 2010.12375): Sections 1.1 (kernel sums and gradients), 2.1 (EoS),
  * 2.2 (Riemann-based continuity and momentum equations, density
- * re-initialisation), 2.3 (one-sided Riemann wall condition), 2.4
+ * re-initialisation), 2.3 (one-sided Riemann wall condition, with static or
+ * moving walls), 2.4
  * (dual-criteria time stepping) and 7 (position-based Verlet).
  *
  * TEST INFRASTRUCTURE. This library is the checker for the HIP path, not
@@ -60,6 +61,18 @@ typedef struct {
     int32_t pad_;
 } orc_params;
 
+/* Prescribed rigid motion of a wall body (moving walls of Section 2.3, used
+ * for sloshing tanks and wave makers). Reading: displacement
+ * d(t) = amp sin(omega t) and rotation angle theta(t) = roll sin(omega t)
+ * about the z axis through the moving centre pivot + d(t); positions and
+ * normals follow the rotation, z is unchanged. */
+typedef struct {
+    double amp[3];   /* translation amplitude */
+    double omega;    /* angular frequency */
+    double roll;     /* rotation amplitude (radians) about the z axis */
+    double pivot[3]; /* rotation centre at t = 0 */
+} orc_wall_motion;
+
 typedef struct {
     orc_params p;
     int d;
@@ -71,9 +84,17 @@ typedef struct {
     /* fluid state, stride 3 per particle, ascending original id */
     int64_t nf;
     double *x, *v, *rho, *drho;
-    /* static wall particles: position and unit normal pointing into the fluid */
+    /* wall particles: position and unit normal pointing into the fluid, as
+     * given (xw0, nrm0) and at the last configuration update (xw, nrm) */
     int64_t nw;
     double *xw, *nrm;
+    double *xw0, *nrm0;
+    /* wall motion: flags per wall (1: follows the motion), the motion and
+     * the rotation centre at the last configuration update */
+    int moving;
+    int32_t *wmov;
+    orc_wall_motion mo;
+    double wc[3];
     /* configuration: positions frozen at the last update and neighbour lists */
     double *xs;
     int64_t *in_off, *ct_off; /* CSR offsets, nf + 1 each */
@@ -207,7 +228,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     free_config(s);
     free(s->x); free(s->v); free(s->rho); free(s->drho);
-    free(s->xw); free(s->nrm);
+    free(s->xw); free(s->nrm); free(s->xw0); free(s->nrm0); free(s->wmov);
     free(s->av); free(s->atv);
     free(s);
 }
@@ -278,18 +299,116 @@ int orc_set_walls(orc_sim *s, int64_t n, const double *pos, const double *normal
             double xk = pos[s->d * i + k];
             if (!(xk >= s->p.lo[k] && xk < s->p.hi[k])) return ORC_EINVAL;
         }
-    free(s->xw); free(s->nrm);
+    free(s->xw); free(s->nrm); free(s->xw0); free(s->nrm0); free(s->wmov);
+    s->wmov = NULL;
+    s->moving = 0;
     free_config(s);
     s->nw = n;
     size_t m = (size_t)(n > 0 ? n : 1);
     s->xw = (double *)calloc(3 * m, sizeof(double));
     s->nrm = (double *)calloc(3 * m, sizeof(double));
-    if (!s->xw || !s->nrm) return ORC_ENOMEM;
+    s->xw0 = (double *)calloc(3 * m, sizeof(double));
+    s->nrm0 = (double *)calloc(3 * m, sizeof(double));
+    if (!s->xw || !s->nrm || !s->xw0 || !s->nrm0) return ORC_ENOMEM;
     for (int64_t i = 0; i < n; ++i)
         for (int k = 0; k < s->d; ++k) {
-            s->xw[3 * i + k] = pos[s->d * i + k];
-            s->nrm[3 * i + k] = normal[s->d * i + k];
+            s->xw[3 * i + k] = s->xw0[3 * i + k] = pos[s->d * i + k];
+            s->nrm[3 * i + k] = s->nrm0[3 * i + k] = normal[s->d * i + k];
         }
+    return ORC_OK;
+}
+
+/* Moving walls: the motion (NULL: the walls are static again) and one flag
+ * per wall particle in the order given to orc_set_walls (NULL: every wall
+ * particle moves; 0 keeps a particle static, e.g. a fixed obstacle in a
+ * moving tank). In 2D the z components of amp and pivot are ignored. */
+int orc_set_wall_motion(orc_sim *s, const orc_wall_motion *m, const int32_t *flags)
+{
+    if (!s) return ORC_EINVAL;
+    free_config(s);
+    free(s->wmov);
+    s->wmov = NULL;
+    s->moving = 0;
+    for (int64_t w = 0; w < s->nw; ++w)
+        for (int k = 0; k < 3; ++k) {
+            s->xw[3 * w + k] = s->xw0[3 * w + k];
+            s->nrm[3 * w + k] = s->nrm0[3 * w + k];
+        }
+    if (!m) return ORC_OK;
+    s->wmov = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s->nw > 0 ? s->nw : 1));
+    if (!s->wmov) return ORC_ENOMEM;
+    for (int64_t w = 0; w < s->nw; ++w) s->wmov[w] = flags ? (flags[w] != 0) : 1;
+    s->mo = *m;
+    if (s->d == 2) {
+        s->mo.amp[2] = 0.0;
+        s->mo.pivot[2] = 0.0;
+    }
+    s->moving = 1;
+    return ORC_OK;
+}
+
+/* Rotation centre pivot + d(t) of the wall motion. */
+static void wall_centre(const orc_sim *s, double t, double c[3])
+{
+    double sn = sin(s->mo.omega * t);
+    for (int k = 0; k < 3; ++k) c[k] = s->mo.pivot[k] + s->mo.amp[k] * sn;
+}
+
+/* Position and normal of wall particle w at time t under the rigid motion:
+ * x = (pivot + d(t)) + R(theta(t)) (x0 - pivot), n = R(theta(t)) n0, with R
+ * the rotation by theta in the x-y plane. */
+static void wall_pose(const orc_sim *s, int64_t w, double t, double *x, double *n)
+{
+    const double *x0 = s->xw0 + 3 * w, *n0 = s->nrm0 + 3 * w;
+    if (!s->moving || !s->wmov[w]) {
+        for (int k = 0; k < 3; ++k) {
+            x[k] = x0[k];
+            n[k] = n0[k];
+        }
+        return;
+    }
+    double sn = sin(s->mo.omega * t);
+    double th = s->mo.roll * sn;
+    double ct = cos(th), st = sin(th);
+    double d0 = x0[0] - s->mo.pivot[0], d1 = x0[1] - s->mo.pivot[1];
+    x[0] = (s->mo.pivot[0] + s->mo.amp[0] * sn) + (ct * d0 - st * d1);
+    x[1] = (s->mo.pivot[1] + s->mo.amp[1] * sn) + (st * d0 + ct * d1);
+    x[2] = (s->mo.pivot[2] + s->mo.amp[2] * sn) + (x0[2] - s->mo.pivot[2]);
+    n[0] = ct * n0[0] - st * n0[1];
+    n[1] = st * n0[0] + ct * n0[1];
+    n[2] = n0[2];
+}
+
+/* Velocity at time t of a wall particle at x on a body whose rotation
+ * centre is at c: v = d'(t) + theta'(t) z x (x - c), the time derivative of
+ * the rigid motion. */
+static void wall_velocity(const orc_sim *s, const double *x, const double *c, double t, double *v)
+{
+    double co = cos(s->mo.omega * t);
+    double om = s->mo.roll * s->mo.omega * co;
+    double r0 = x[0] - c[0], r1 = x[1] - c[1];
+    v[0] = s->mo.amp[0] * s->mo.omega * co - om * r1;
+    v[1] = s->mo.amp[1] * s->mo.omega * co + om * r0;
+    v[2] = s->mo.amp[2] * s->mo.omega * co;
+}
+
+/* Pose and velocity of every wall particle at time t (for tests): pos, nrm
+ * and vel n*dim each, any of them NULL. */
+int orc_wall_kinematics(const orc_sim *s, double t, double *pos, double *nrm, double *vel)
+{
+    if (!s) return ORC_EINVAL;
+    double c[3] = {0.0, 0.0, 0.0};
+    if (s->moving) wall_centre(s, t, c);
+    for (int64_t w = 0; w < s->nw; ++w) {
+        double x[3], n[3], v[3] = {0.0, 0.0, 0.0};
+        wall_pose(s, w, t, x, n);
+        if (s->moving && s->wmov[w]) wall_velocity(s, x, c, t, v);
+        for (int k = 0; k < s->d; ++k) {
+            if (pos) pos[s->d * w + k] = x[k];
+            if (nrm) nrm[s->d * w + k] = n[k];
+            if (vel) vel[s->d * w + k] = v[k];
+        }
+    }
     return ORC_OK;
 }
 
@@ -469,6 +588,16 @@ int orc_build_config(orc_sim *s)
             }
             if (!(*xk >= s->p.lo[k] && *xk < s->p.hi[k])) return ORC_EESCAPE;
         }
+    /* Reading: moving walls take their pose at the time of the update and
+     * keep it, like the fluid positions, until the next update. */
+    if (s->moving) {
+        wall_centre(s, s->t, s->wc);
+        for (int64_t w = 0; w < s->nw; ++w) {
+            wall_pose(s, w, s->t, s->xw + 3 * w, s->nrm + 3 * w);
+            for (int k = 0; k < s->d; ++k)
+                if (!(s->xw[3 * w + k] >= s->p.lo[k] && s->xw[3 * w + k] < s->p.hi[k])) return ORC_EESCAPE;
+        }
+    }
     size_t m = (size_t)(s->nf > 0 ? s->nf : 1);
     s->xs = (double *)malloc(3 * m * sizeof(double));
     if (!s->xs) return ORC_ENOMEM;
@@ -539,16 +668,30 @@ void orc_kernel_sums(const orc_sim *s, double *sigma)
 }
 
 /* ------------------------------------------------------------------ */
+/* Velocity at time t of wall particle w of the current configuration (zero
+ * for a static wall). Reading: the pose (position, normal and lever arm
+ * about the rotation centre) is the one frozen at the configuration update;
+ * only the rates d'(t), theta'(t) are taken at time t. */
+static void config_wall_velocity(const orc_sim *s, int64_t w, double t, double *v)
+{
+    v[0] = v[1] = v[2] = 0.0;
+    if (s->moving && s->wmov[w]) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);
+}
+
 /* One-sided wall Riemann states, Eqs. (eqriepartial), (eqrienoslip),
- * (eqriepright). Reading: n_w is the unit wall normal pointing into the
- * fluid; the wall is static (u_w = -n_w . v_w = 0); r_fw = x_w - x_i is the
- * frozen configuration vector r_iw e_iw; rho_R follows from the EoS. */
-static void wall_states(const orc_sim *s, int64_t w, const pair_geo *g,
+ * (eqriepright), at time t. Reading: n_w is the unit wall normal pointing
+ * into the fluid; the wall velocity enters through u_w = -n_w . v_w (the
+ * same projection as U_L; zero for a static wall); r_fw = x_w - x_i is the
+ * frozen configuration vector r_iw e_iw; P_R uses gravity only, as printed
+ * (no wall-acceleration term); rho_R follows from the EoS. */
+static void wall_states(const orc_sim *s, int64_t w, const pair_geo *g, double t,
                         double rho_i, double p_i, const double *v_i,
                         double *UL, double *PL, double *rhoR, double *UR, double *PR)
 {
     const double *n = s->nrm + 3 * w;
-    double uw = 0.0;
+    double vw[3];
+    config_wall_velocity(s, w, t, vw);
+    double uw = -dot3(n, vw);
     *UL = -dot3(n, v_i);
     *UR = -(*UL) + 2.0 * uw;
     *PL = p_i;
@@ -562,8 +705,9 @@ static void wall_states(const orc_sim *s, int64_t w, const pair_geo *g,
  *   av_i  = 2 sum_j m_j eta/(rho_i rho_j) (v_i - v_j)/r_ij W'_ij,
  *   atv_i = -2 sum_j m_j p0/(rho_i rho_j) grad_i W_ij
  *         =  2 sum_j m_j p0/(rho_i rho_j) W'_ij e_ij.
- * Reading: for a wall neighbour m_j/rho_j is the wall volume and the wall
- * velocity is zero (static wall); both are evaluated once per advection step,
+ * Reading: for a wall neighbour m_j/rho_j is the wall volume and v_j the
+ * wall velocity at the start of the step (no slip); both are evaluated once
+ * per advection step,
  * after the density re-initialisation, on the frozen configuration (the
  * advection criterion carries the viscous time scale h^2/nu). */
 static void advection_forces(orc_sim *s)
@@ -588,10 +732,12 @@ static void advection_forces(orc_sim *s)
         for (int64_t q = s->ct_off[i]; q < s->ct_off[i + 1]; ++q) {
             int64_t w = s->ct_idx[q];
             pair_geo g = frozen_geo(s, i, s->xw + 3 * w);
+            double vw[3];
+            config_wall_velocity(s, w, s->t, vw);
             double cv = 2.0 * s->vol_w * eta / rho_i / g.r * g.dW;
             double ct = 2.0 * s->vol_w * p0 / rho_i * g.dW;
             for (int k = 0; k < 3; ++k) {
-                av[k] += cv * vi[k];
+                av[k] += cv * (vi[k] - vw[k]);
                 at[k] += ct * g.e[k];
             }
         }
@@ -608,7 +754,7 @@ static void advection_forces(orc_sim *s)
  *                 = g + 2 sum_j m_j P* / (rho_i rho_j) W'_ij e_ij,
  * with U_L = v_i . e_ij, U_R = v_j . e_ij, P_L = p_i, P_R = p_j. For a wall
  * neighbour m_j/rho_j is the wall particle volume. */
-static void momentum_rate(const orc_sim *s, double *a)
+static void momentum_rate(const orc_sim *s, double t, double *a)
 {
     const double m = s->mass, c = s->p.c0;
 #pragma omp parallel for schedule(static)
@@ -630,7 +776,7 @@ static void momentum_rate(const orc_sim *s, double *a)
             int64_t w = s->ct_idx[q];
             pair_geo g = frozen_geo(s, i, s->xw + 3 * w);
             double UL, PL, rhoR, UR, PR, Us, Ps;
-            wall_states(s, w, &g, rho_i, p_i, vi, &UL, &PL, &rhoR, &UR, &PR);
+            wall_states(s, w, &g, t, rho_i, p_i, vi, &UL, &PL, &rhoR, &UR, &PR);
             orc_riemann(rho_i, UL, PL, rhoR, UR, PR, c, &Us, &Ps);
             double coef = 2.0 * s->vol_w * Ps / rho_i * g.dW;
             for (int k = 0; k < 3; ++k) acc[k] += coef * g.e[k];
@@ -644,7 +790,7 @@ static void momentum_rate(const orc_sim *s, double *a)
  * Reading: for a wall neighbour m_j/rho_j is the wall volume and
  * v_i . e_ij is replaced by the wall-normal left state U_L of the same
  * one-sided problem that gives U*. */
-static void continuity_rate(const orc_sim *s, double *drho)
+static void continuity_rate(const orc_sim *s, double t, double *drho)
 {
     const double m = s->mass, c = s->p.c0;
 #pragma omp parallel for schedule(static)
@@ -665,7 +811,7 @@ static void continuity_rate(const orc_sim *s, double *drho)
             int64_t w = s->ct_idx[q];
             pair_geo g = frozen_geo(s, i, s->xw + 3 * w);
             double UL, PL, rhoR, UR, PR, Us, Ps;
-            wall_states(s, w, &g, rho_i, p_i, vi, &UL, &PL, &rhoR, &UR, &PR);
+            wall_states(s, w, &g, t, rho_i, p_i, vi, &UL, &PL, &rhoR, &UR, &PR);
             orc_riemann(rho_i, UL, PL, rhoR, UR, PR, c, &Us, &Ps);
             sum += s->vol_w * (Us - UL) * g.dW;
         }
@@ -706,18 +852,21 @@ void orc_time_steps(const orc_sim *s, double *dt_ad, double *dt_ac)
  * transport-velocity correction the positions move with the transport
  * velocity v + dt atv (Eq. transport over the sub-step), i.e. both position
  * half-steps gain dt^2 atv / 2.
+ * Reading for moving walls: the pressure relaxation meets v^n and so takes
+ * the wall velocity at the sub-step's start t + tau, the density relaxation
+ * meets v^{n+1} and takes it at its end t + (tau + dt).
  * When a and drho_out are given they receive the two rates. */
-static int substep(orc_sim *s, double dt, double *a, double *drho_out)
+static int substep(orc_sim *s, double tau, double dt, double *a, double *drho_out)
 {
     int64_t n = s->nf;
     for (int64_t i = 0; i < n; ++i) {
         s->rho[i] += 0.5 * dt * s->drho[i];
         for (int k = 0; k < s->d; ++k) s->x[3 * i + k] += 0.5 * dt * s->v[3 * i + k];
     }
-    momentum_rate(s, a);
+    momentum_rate(s, s->t + tau, a);
     for (int64_t i = 0; i < n; ++i)
         for (int k = 0; k < s->d; ++k) s->v[3 * i + k] += dt * a[3 * i + k];
-    continuity_rate(s, s->drho);
+    continuity_rate(s, s->t + (tau + dt), s->drho);
     for (int64_t i = 0; i < n; ++i) {
         for (int k = 0; k < s->d; ++k) s->x[3 * i + k] += 0.5 * dt * s->v[3 * i + k];
         s->rho[i] += 0.5 * dt * s->drho[i];
@@ -755,7 +904,7 @@ int orc_compute_rates(orc_sim *s, double dt, double *dvdt, double *drhodt)
     memcpy(r0, s->rho, n * sizeof(double));
     memcpy(d0, s->drho, n * sizeof(double));
     advection_forces(s);
-    int rc = substep(s, dt, a, drhodt);
+    int rc = substep(s, 0.0, dt, a, drhodt);
     for (int64_t i = 0; i < s->nf; ++i)
         for (int k = 0; k < s->d; ++k) dvdt[s->d * i + k] = a[3 * i + k];
     memcpy(s->x, x0, 3 * n * sizeof(double));
@@ -804,7 +953,7 @@ int orc_advance(orc_sim *s, double t_stop, int32_t *nsub_out, double *t_out)
                 dt = rem;
                 last = 1;
             }
-            rc = substep(s, dt, a, NULL);
+            rc = substep(s, tau, dt, a, NULL);
             nsub++;
             if (rc) { free(a); return rc; }
             tau += dt;

@@ -39,6 +39,18 @@ FP32 = 1
 
 
 @dataclasses.dataclass
+class WallMotion:
+    """Prescribed rigid wall motion: displacement amp sin(omega t) and
+    rotation roll sin(omega t) (radians, in the x-y plane) about the centre
+    pivot + displacement."""
+
+    amp: tuple = (0.0, 0.0, 0.0)
+    omega: float = 0.0
+    roll: float = 0.0
+    pivot: tuple = (0.0, 0.0, 0.0)
+
+
+@dataclasses.dataclass
 class Case:
     """One simulation input: parameters plus fluid and wall particles."""
 
@@ -67,6 +79,8 @@ class Case:
     eta: float = 0.0               # dynamic viscosity (0: inviscid)
     p_background: float = 0.0      # transport-velocity background pressure (0: off)
     reinit_mode: int = 0           # 0: free-surface density re-init, 1: no free surface
+    wall_motion: Optional[WallMotion] = None   # None: static walls
+    wall_moving: Optional[np.ndarray] = None   # per wall particle 0/1 (None: all follow the motion)
 
     @property
     def n_fluid(self) -> int:
@@ -243,3 +257,124 @@ def hydrostatic_column_2d(dp=0.05, L=1.0, H=1.0, seed=0, jitter=0.0):
                 lo=(-pad, -pad, 0.0), hi=(L + pad, DH + pad, 0.0), periodic=(0, 0, 0),
                 fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=FP64,
                 column=(nx * dp, ny * dp), tank=(L, DH), seed=seed, **prm)
+
+
+# --- moving walls and obstacles ------------------------------------------
+
+def motion_reach(wall_pos, motion, moving=None):
+    """Per axis, the largest distance a wall particle can move from its
+    given position under `motion` (translation amplitude plus the chord of
+    the largest rotation)."""
+    d = wall_pos.shape[1]
+    reach = np.array([abs(float(motion.amp[k])) for k in range(d)])
+    if motion.roll:
+        sel = wall_pos if moving is None else wall_pos[np.asarray(moving) != 0]
+        if len(sel):
+            arm = np.sqrt(((sel[:, :2] - np.asarray(motion.pivot[:2])) ** 2).sum(1)).max()
+            reach[:2] += abs(float(motion.roll)) * arm
+    return reach
+
+
+def sloshing_first_mode(L, H, g=1.0):
+    """Angular frequency of the first sloshing mode of a rectangular tank of
+    length L filled to depth H (linear water-wave dispersion relation)."""
+    k = math.pi / L
+    return math.sqrt(g * k * math.tanh(k * H))
+
+
+def sloshing_2d(dp, seed=0, L=2.0, H=1.0, DH=2.0, amp=0.05, roll=0.0, omega=None, precision=FP64,
+                jitter=0.01, name=None, layers=4):
+    """2D sloshing tank: a closed L x DH tank filled to depth H, excited by a
+    horizontal sway amp * L * sin(omega t) and a roll about the centre of the
+    still water line, omega the first sloshing mode by default. The whole
+    tank wall is one rigid moving body; the domain box holds the tank over
+    its whole motion."""
+    nx = int(round(L / dp))
+    ny = int(round(H / dp))
+    pos = _lattice((nx, ny), dp)
+    if jitter:
+        pos = _jitter(pos, dp, seed, jitter)
+    wpos, wn = tank_walls_2d(L, DH, dp, layers)
+    prm = _params(2, dp, H)
+    om = sloshing_first_mode(L, H) if omega is None else float(omega)
+    mo = WallMotion(amp=(amp * L, 0.0, 0.0), omega=om, roll=float(roll), pivot=(0.5 * L, H, 0.0))
+    reach = motion_reach(wpos, mo)
+    pad = layers * dp + 2.0 * prm["h"]
+    lo = (-pad - reach[0], -pad - reach[1], 0.0)
+    hi = (L + pad + reach[0], DH + pad + reach[1], 0.0)
+    return Case(name=name or f"sloshing2d_dp{dp:g}", gravity=(0.0, -1.0, 0.0), lo=lo, hi=hi,
+                periodic=(0, 0, 0), fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision,
+                column=(nx * dp, ny * dp), tank=(L, DH), seed=seed, wall_motion=mo, **prm)
+
+
+def sloshing_3d(dp, seed=0, L=2.0, H=1.0, DH=2.0, W=0.5, amp=0.05, roll=0.0, omega=None, precision=FP32,
+                jitter=0.01, name=None, layers=4):
+    """3D sloshing tank, periodic in the width z: the 2D tank extruded."""
+    nx, ny, nz = int(round(L / dp)), int(round(H / dp)), int(round(W / dp))
+    pos = _lattice((nx, ny, nz), dp)
+    if jitter:
+        pos = _jitter(pos, dp, seed, jitter)
+    w2, n2 = tank_walls_2d(L, DH, dp, layers)
+    zs = (np.arange(nz, dtype=np.float64) + 0.5) * dp
+    wpos = np.concatenate([np.column_stack([w2, np.full(len(w2), z)]) for z in zs])
+    wn = np.concatenate([np.column_stack([n2, np.zeros(len(n2))]) for _ in zs])
+    prm = _params(3, dp, H)
+    om = sloshing_first_mode(L, H) if omega is None else float(omega)
+    mo = WallMotion(amp=(amp * L, 0.0, 0.0), omega=om, roll=float(roll), pivot=(0.5 * L, H, 0.0))
+    reach = motion_reach(wpos, mo)
+    pad = layers * dp + 2.0 * prm["h"]
+    lo = (-pad - reach[0], -pad - reach[1], 0.0)
+    hi = (L + pad + reach[0], DH + pad + reach[1], nz * dp)
+    return Case(name=name or f"sloshing3d_dp{dp:g}", gravity=(0.0, -1.0, 0.0), lo=lo, hi=hi,
+                periodic=(0, 0, 1), fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision,
+                column=(nx * dp, ny * dp, nz * dp), tank=(L, DH, nz * dp), seed=seed, wall_motion=mo, **prm)
+
+
+def obstacle_walls_2d(x0, x1, top, dp, layers=4):
+    """Wall particles of a rectangular obstacle [x0, x1] x [0, top] standing
+    on the tank floor: lattice points inside it within `layers` spacings of
+    its exposed faces (left, right, top); normals point out of the nearest
+    exposed face(s), the normalised sum where two are equally near."""
+    k = np.arange(int(round(x0 / dp)), int(round(x1 / dp)))
+    l = np.arange(0, int(round(top / dp)))
+    X, Y = np.meshgrid((k + 0.5) * dp, (l + 0.5) * dp, indexing="ij")
+    X, Y = X.reshape(-1), Y.reshape(-1)
+    dl, dr, dt = X - x0, x1 - X, top - Y
+    dmin = np.minimum(np.minimum(dl, dr), dt)
+    keep = dmin < layers * dp
+    X, Y, dl, dr, dt, dmin = X[keep], Y[keep], dl[keep], dr[keep], dt[keep], dmin[keep]
+    tol = 1e-9 * dp
+    nx = np.where(np.abs(dl - dmin) < tol, -1.0, 0.0) + np.where(np.abs(dr - dmin) < tol, 1.0, 0.0)
+    ny = np.where(np.abs(dt - dmin) < tol, 1.0, 0.0)
+    nn = np.sqrt(nx * nx + ny * ny)
+    return np.stack([X, Y], axis=1), np.stack([nx / nn, ny / nn], axis=1)
+
+
+def dam_break_obstacle_2d(dp, seed=0, obstacle=(3.0, 3.2, 0.4), precision=FP64, t_end=None, name=None):
+    """2D dam break hitting a fixed rectangular obstacle on the tank floor
+    (the paper's dam break with an obstacle, Section 10.1): the standard
+    column and tank plus the obstacle's wall particles."""
+    case = dam_break_2d(dp, seed=seed, precision=precision, t_end=t_end,
+                        name=name or f"dambreak_obstacle2d_dp{dp:g}")
+    opos, on = obstacle_walls_2d(obstacle[0], obstacle[1], obstacle[2], dp)
+    case.wall_pos = np.concatenate([case.wall_pos, opos])
+    case.wall_normal = np.concatenate([case.wall_normal, on])
+    return case
+
+
+def piston_2d(dp, V=0.2, L=2.0, W=0.4, omega=0.5, precision=FP64, layers=4, name=None):
+    """Fluid at rest in a channel periodic across its width W (no gravity),
+    pushed from x = 0 by a piston (a wall slab of `layers` spacings) moving
+    in +x with velocity V cos(omega t) (displacement V/omega sin(omega t)),
+    its far end x = L a free surface."""
+    nx, ny = int(round(L / dp)), int(round(W / dp))
+    pos = _lattice((nx, ny), dp)
+    wpos = _lattice((layers, ny), dp) - np.array([layers * dp, 0.0])
+    wn = np.tile([1.0, 0.0], (len(wpos), 1))
+    prm = _params(2, dp, 1.0)
+    mo = WallMotion(amp=(V / omega, 0.0, 0.0), omega=omega)
+    pad = layers * dp + 2.0 * prm["h"]
+    return Case(name=name or f"piston2d_dp{dp:g}", gravity=(0.0, 0.0, 0.0),
+                lo=(-pad, 0.0, 0.0), hi=(L + V / omega + pad + 1.0, W, 0.0), periodic=(0, 1, 0),
+                fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision, column=(L, W),
+                wall_motion=mo, **prm)

@@ -1,0 +1,160 @@
+"""Pins of the oracle's moving walls (Section 2.3: the wall velocity u_w in the
+right state of the one-sided Riemann problem, Eq. eqrienoslip; the no-slip
+viscous wall term of Eq. eqviscous with a moving wall), on the CPU, against
+what the mathematics fixes: Galilean invariance, the time derivative of the
+prescribed rigid motion, rigidity of the posed wall body, and the acoustic
+impedance of a piston."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2010_12375_amd import workloads as wl
+from parity import developed_state
+
+
+def _rates(case, vel, rho, drho, motion=None, eta=0.0, t=0.0):
+    p = O.params_from_case(case)
+    p.eta = eta
+    o = O.Oracle(params=p)
+    o.set_fluid(case.fluid_pos, vel=vel, rho=rho, drho=drho)
+    o.set_walls(case.wall_pos, case.wall_normal)
+    if motion is not None:
+        o.set_wall_motion(**motion)
+    o.t = t
+    o.build_config()
+    return o.compute_rates(0.0)
+
+
+@pytest.mark.parametrize("eta", [0.0, 0.01])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_translating_walls_and_fluid_are_galilean_invariant(dim, eta):
+    """Fluid and walls translating together with velocity U (walls by the
+    prescribed motion at t = 0, where its velocity is amp * omega) give
+    exactly the rates of the same state at rest: every relative velocity the
+    Riemann states (and the no-slip shear) see is zero in both. A wrong sign
+    or factor of u_w in U_R, or a wall velocity missing from the shear term,
+    breaks it."""
+    if dim == 2:
+        case = wl.dam_break_2d(0.05, seed=3)
+        U = np.array([0.7, -0.4])
+    else:
+        case = wl.dam_break_3d(0.1, seed=3, W=0.3, DL=2.4, DH=1.3, precision=wl.FP64)
+        U = np.array([0.7, -0.4, 0.0])
+    _, rho, drho = developed_state(case, seed=5)
+    n = case.n_fluid
+    omega = 0.7
+    a0, d0 = _rates(case, np.zeros((n, dim)), rho, drho, eta=eta)
+    mo = dict(amp=tuple(U / omega) + ((0.0,) if dim == 2 else ()), omega=omega, pivot=(0.0, 0.0, 0.0))
+    a1, d1 = _rates(case, np.tile(U, (n, 1)), rho, drho, motion=mo, eta=eta)
+    g = 1.0
+    assert np.abs(a1 - a0).max() <= 1e-10 * (np.abs(a0).max() + g)
+    assert np.abs(d1 - d0).max() <= 1e-10 * (np.abs(d0).max() + np.sqrt((d0 ** 2).mean()))
+    # the motion does matter: walls moving while the fluid rests
+    a2, d2 = _rates(case, np.zeros((n, dim)), rho, drho, motion=mo, eta=eta)
+    assert np.abs(d2 - d0).max() > 1e-3 * np.abs(d0).max()
+
+
+def test_wall_kinematics_is_the_derivative_of_the_rigid_motion():
+    """Sway plus roll: the reported wall velocity is the time derivative of
+    the posed positions (central differences), the body stays rigid
+    (pairwise distances), normals stay unit and rotate with it (normal times
+    a relative position is invariant), and walls flagged static stay put."""
+    case = wl.sloshing_2d(0.05, roll=0.1)
+    moving = np.ones(case.n_wall, dtype=np.int32)
+    moving[::7] = 0
+    o = O.Oracle(case)
+    m = case.wall_motion
+    o.set_wall_motion(amp=m.amp, omega=m.omega, roll=m.roll, pivot=m.pivot, moving=moving)
+    x0, n0, v0 = o.wall_kinematics(0.0, case.n_wall)
+    assert np.array_equal(x0[moving == 0], case.wall_pos[moving == 0])
+    mv = moving == 1
+    a, b = np.nonzero(mv)[0][:40], np.nonzero(mv)[0][-40:]
+    for t in (0.3, 1.1, 2.6):
+        eps = 1e-6
+        xp, _, _ = o.wall_kinematics(t + eps, case.n_wall)
+        xm, _, _ = o.wall_kinematics(t - eps, case.n_wall)
+        x, n, v = o.wall_kinematics(t, case.n_wall)
+        fd = (xp - xm) / (2 * eps)
+        assert np.abs(fd - v).max() < 1e-7 * max(1.0, np.abs(v).max())
+        assert np.abs(v[~mv]).max() == 0.0
+        assert np.array_equal(x[~mv], case.wall_pos[~mv])
+        assert np.allclose(np.linalg.norm(n, axis=1), 1.0, atol=1e-14)
+        d_t = np.linalg.norm(x[a] - x[b], axis=1)
+        d_0 = np.linalg.norm(case.wall_pos[a] - case.wall_pos[b], axis=1)
+        assert np.allclose(d_t, d_0, atol=1e-13)
+        inv_t = (n[a] * (x[b] - x[a])).sum(1)
+        inv_0 = (case.wall_normal[a] * (case.wall_pos[b] - case.wall_pos[a])).sum(1)
+        assert np.allclose(inv_t, inv_0, atol=1e-13)
+    # the rotation is about z by roll sin(omega t): check one normal's angle
+    t = 0.9
+    _, n, _ = o.wall_kinematics(t, case.n_wall)
+    k = int(np.nonzero(mv)[0][0])
+    ang = np.arctan2(n[k, 1], n[k, 0]) - np.arctan2(case.wall_normal[k, 1], case.wall_normal[k, 0])
+    assert ang == pytest.approx(m.roll * np.sin(m.omega * t), abs=1e-13)
+
+
+def test_piston_drives_the_acoustic_impedance_pressure():
+    """A piston pushed impulsively into fluid at rest with speed V: behind
+    the wave it sends, pressure and velocity obey the simple-wave relation of
+    the isothermal EoS, p = rho0 c0^2 (exp(v/c0) - 1) (= rho0 c0 v to first
+    order), within 1 % on average, and both sit at the piston's values
+    within 6 % (the impulsive start leaves a few per cent of ringing behind
+    the front). Pins the sign and the size of the wall velocity in both
+    relaxations."""
+    V = 0.2
+    case = wl.piston_2d(0.02, V=V)
+    o = O.Oracle(case)
+    m = case.wall_motion
+    o.set_wall_motion(amp=m.amp, omega=m.omega, pivot=m.pivot)
+    o.build_config()
+    t_end = 0.04  # the wave has travelled about 0.8
+    while o.t < t_end - 1e-12:
+        o.advance(t_end)
+    x = o.field(O.FIELD_POS)
+    v = o.field(O.FIELD_VEL)
+    p = o.field(O.FIELD_P)
+    piston = V / m.omega * np.sin(m.omega * o.t)
+    band = (x[:, 0] > piston + 0.05) & (x[:, 0] < piston + 0.55)
+    wave = case.rho0 * case.c0 ** 2 * (np.exp(v[band, 0] / case.c0) - 1.0)
+    assert (p[band] / wave).mean() == pytest.approx(1.0, abs=0.01)
+    v_piston = V * np.cos(m.omega * o.t)
+    p_piston = case.rho0 * case.c0 ** 2 * (np.exp(v_piston / case.c0) - 1.0)
+    assert p[band].mean() == pytest.approx(p_piston, rel=0.06)
+    assert v[band, 0].mean() == pytest.approx(v_piston, rel=0.06)
+    ahead = x[:, 0] > piston + 1.2
+    assert np.abs(v[ahead]).max() < 0.01 * V  # not yet reached
+
+
+def test_sloshing_run_keeps_mass_and_fluid_inside_the_tank():
+    case = wl.sloshing_2d(0.05, roll=0.05)
+    o = O.Oracle(case)
+    m = case.wall_motion
+    o.set_wall_motion(amp=m.amp, omega=m.omega, roll=m.roll, pivot=m.pivot)
+    o.build_config()
+    d0 = o.diagnostics()
+    while o.t < 1.0 - 1e-12:
+        o.advance(1.0)
+    d1 = o.diagnostics()
+    assert d1["mass"] == d0["mass"]
+    x = o.field(O.FIELD_POS)
+    # back in the tank frame the fluid stays inside the tank
+    sn = np.sin(m.omega * o.t)
+    th = m.roll * sn
+    c = np.array(m.pivot[:2]) + np.array(m.amp[:2]) * sn
+    R = np.array([[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]])
+    xb = (x - c) @ R.T + np.array(m.pivot[:2])
+    assert xb[:, 0].min() > -0.01 and xb[:, 0].max() < case.tank[0] + 0.01
+    assert xb[:, 1].min() > -0.01
+
+
+def test_walls_flagged_static_give_the_static_rates():
+    """A motion whose every wall particle is flagged static changes nothing:
+    the rates equal those without motion, bit for bit, at a time where the
+    motion itself is far from rest."""
+    case = wl.sloshing_2d(0.05, roll=0.1)
+    vel, rho, drho = developed_state(case, seed=2)
+    m = case.wall_motion
+    mo = dict(amp=m.amp, omega=m.omega, roll=m.roll, pivot=m.pivot, moving=np.zeros(case.n_wall, np.int32))
+    a0, d0 = _rates(case, vel, rho, drho, t=0.8)
+    a1, d1 = _rates(case, vel, rho, drho, motion=mo, t=0.8)
+    assert np.array_equal(a0, a1) and np.array_equal(d0, d1)

@@ -53,6 +53,21 @@ MUTATIONS = [
     ("transport_sign", "s->x[3 * i + k] += dt * dt * s->atv[3 * i + k];", "s->x[3 * i + k] -= dt * dt * s->atv[3 * i + k];", None),
     ("no_surface_reinit_keeps_max", "s->rho[i] = s->p.reinit_mode ? rho_sum : fmax(s->rho[i], rho_sum);",
      "s->rho[i] = fmax(s->rho[i], rho_sum);", None),
+    ("wall_velocity_sign", "*UR = -(*UL) + 2.0 * uw;", "*UR = -(*UL) - 2.0 * uw;", None),
+    ("wall_velocity_factor", "*UR = -(*UL) + 2.0 * uw;", "*UR = -(*UL) + uw;", None),
+    ("wall_velocity_dropped", "double uw = -dot3(n, vw);", "double uw = 0.0 * dot3(n, vw);", None),
+    ("moving_wall_shear_velocity_dropped", "av[k] += cv * (vi[k] - vw[k]);", "av[k] += cv * vi[k];", None),
+    ("wall_speed_without_omega", "v[0] = s->mo.amp[0] * s->mo.omega * co - om * r1;",
+     "v[0] = s->mo.amp[0] * co - om * r1;", None),
+    ("roll_lever_sign", "v[1] = s->mo.amp[1] * s->mo.omega * co + om * r0;",
+     "v[1] = s->mo.amp[1] * s->mo.omega * co - om * r0;", None),
+    ("pose_rotation_transposed", "x[0] = (s->mo.pivot[0] + s->mo.amp[0] * sn) + (ct * d0 - st * d1);",
+     "x[0] = (s->mo.pivot[0] + s->mo.amp[0] * sn) + (ct * d0 + st * d1);", None),
+    ("normal_not_rotated", "n[0] = ct * n0[0] - st * n0[1];", "n[0] = n0[0];", None),
+    ("static_flag_ignored", "if (s->moving && s->wmov[w]) wall_velocity(s, x, c, t, v);",
+     "if (s->moving) wall_velocity(s, x, c, t, v);", None),
+    ("static_flag_ignored_in_states", "if (s->moving && s->wmov[w]) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);",
+     "if (s->moving) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);", None),
 ]
 
 
@@ -75,6 +90,7 @@ def test_pins_catch_planted_mistake(name, old, new, occ):
         # a planted mistake that makes a pin run forever also counts as caught
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             "--timeout", "60", "--timeout-method", "thread", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_viscous.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_viscous.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_moving_walls.py")],
                            env=env, capture_output=True, text=True, cwd=ROOT, timeout=900)
         assert r.returncode != 0, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
