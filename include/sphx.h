@@ -139,13 +139,50 @@ int sphx_set_fluid(sphx_ctx* ctx, int64_t n, const double* pos, const double* ve
 int sphx_set_fluid_case(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* vel,
                         const double* rho, const double* drho);
 
-/* Static wall particles: pos n*dim and unit normals n*dim pointing into the
- * fluid (Section 2.3 wall normal). Every wall particle must lie inside the
- * domain box. Invalidates the neighbour configuration. */
+/* Wall particles: pos n*dim and unit normals n*dim pointing into the fluid
+ * (Section 2.3 wall normal), in their reference pose. Every wall particle
+ * must lie inside the domain box. The walls are static until
+ * sphx_set_wall_motion* gives them a motion (a new wall set drops the
+ * case's motion). Invalidates the neighbour configuration. */
 int sphx_set_walls(sphx_ctx* ctx, int64_t n, const double* pos, const double* normal);
 
 /* The same for case c (inside case c's box). */
 int sphx_set_walls_case(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* normal);
+
+/* Prescribed rigid motion of a wall body (Section 2.3: the wall velocity
+ * u_w of the right state U_R = -U_L + 2 u_w, Eq. eqrienoslip; moving tanks
+ * and wave makers of the sloshing cases, Section 10.1):
+ *   displacement d(t) = amp sin(omega t),
+ *   rotation theta(t) = roll sin(omega t) (radians) in the x-y plane about
+ *   the centre pivot + d(t),
+ *   x_w(t) = pivot + d(t) + R(theta(t)) (x_w0 - pivot), n_w(t) = R(theta) n_w0,
+ *   v_w(t) = d'(t) + theta'(t) z x (x_w - pivot - d(t)).
+ * The walls take their pose at every configuration update (at the clock of
+ * their case) and keep it, with the rest of the frozen configuration, for
+ * the advection step; u_w = -n_w . v_w enters the pressure relaxation at the
+ * sub-step's start time and the density relaxation at its end time, and the
+ * no-slip shear of Eq. eqviscous at the step's start time. P_R keeps the
+ * gravity term of Eq. eqriepright only. In 2D the z components of amp and
+ * pivot are ignored. */
+typedef struct {
+    double amp[3];   /* translation amplitude */
+    double omega;    /* angular frequency (>= 0) */
+    double roll;     /* rotation amplitude about the z axis (radians) */
+    double pivot[3]; /* rotation centre at t = 0 */
+} sphx_wall_motion;
+
+/* Give case 0's walls the motion `motion` (NULL: static again). `moving`:
+ * one flag per wall particle in the order of sphx_set_walls (0: the
+ * particle stays static, e.g. a fixed obstacle in a moving tank; NULL: every
+ * wall particle moves). SPHX_EINVAL if the motion could take a wall particle
+ * out of the domain box (bound: |amp_k| + |roll| times its distance from the
+ * pivot in the x-y plane), moves along a periodic axis, or is not finite.
+ * Invalidates the neighbour configuration. The surrogate calls refuse
+ * batches with moving walls. */
+int sphx_set_wall_motion(sphx_ctx* ctx, const sphx_wall_motion* motion, const int32_t* moving);
+
+/* The same for case c. */
+int sphx_set_wall_motion_case(sphx_ctx* ctx, int32_t c, const sphx_wall_motion* motion, const int32_t* moving);
 
 /* Configuration update (Section 2.4: at the advection frequency): wrap
  * periodic coordinates, bin particles into cells of size >= 2h, rebuild the

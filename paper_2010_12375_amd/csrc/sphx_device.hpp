@@ -7,7 +7,8 @@
 // steps (Eqs. dt-advection, dt-relax) and position-based Verlet (Section 7).
 //
 // One launch serves a batch of independent cases, each a fluid body and a
-// static wall body with its own parameters, clock and time steps. Every case
+// wall body (static, or moving with a prescribed rigid motion) with its own
+// parameters, clock and time steps. Every case
 // owns whole tiles of TILE consecutive particle slots, so a wavefront (and a
 // block of a pair kernel) never spans two cases: the case and its parameters
 // are uniform and come from the parameter table with scalar loads.
@@ -112,6 +113,8 @@ template <typename real> struct KP {
     double visc_dt;                           // CFL_ad h^2 / nu (0: inviscid)
     int reinit_mode;                          // 0: free surface (max), 1: no free surface
     int adv_forces;                           // eta > 0 or p0 != 0
+    int wmove;                                // the walls follow the prescribed motion below
+    double wamp[3], womega, wroll, wpivot[3]; // sway amp sin(w t), roll sin(w t) about pivot + sway
     int case_id;
     int fbase, nf, fcap;                      // fluid slots [fbase, fbase + fcap), the first nf used
     int wbase, nw;                            // wall slots [wbase, wbase + nw)
@@ -260,6 +263,60 @@ __device__ __forceinline__ Pair<D, real> pair_geo(const KP<real>& P, const G& oi
     q.e[1] = -dx[1] * rinv;
     q.e[2] = -dx[2] * rinv;
     return q;
+}
+
+// Moving walls (Section 2.3 with u_w != 0). A case's wall body follows a
+// prescribed rigid motion: displacement d(t) = amp sin(w t) and rotation
+// theta(t) = roll sin(w t) in the x-y plane about the moving centre
+// pivot + d(t). Wall particles with flag 0 stay where they were given.
+// The pose is taken at each configuration update and frozen with the rest
+// of the configuration; the velocity rates d'(t), theta'(t) are evaluated
+// at each relaxation's time level. The pose is computed without FP
+// contraction in the operation order the definition is written in.
+template <typename real>
+__device__ __forceinline__ void wall_pose(const KP<real>& P, double t, int moving, const double x0[3],
+                                          const double n0[3], double x[3], double n[3])
+{
+#pragma clang fp contract(off)
+    if (!P.wmove || !moving) {
+        for (int k = 0; k < 3; ++k) {
+            x[k] = x0[k];
+            n[k] = n0[k];
+        }
+        return;
+    }
+    const double sn = sin(P.womega * t);
+    const double th = P.wroll * sn;
+    const double ct = cos(th), st = sin(th);
+    const double d0 = x0[0] - P.wpivot[0], d1 = x0[1] - P.wpivot[1];
+    x[0] = (P.wpivot[0] + P.wamp[0] * sn) + (ct * d0 - st * d1);
+    x[1] = (P.wpivot[1] + P.wamp[1] * sn) + (st * d0 + ct * d1);
+    x[2] = (P.wpivot[2] + P.wamp[2] * sn) + (x0[2] - P.wpivot[2]);
+    n[0] = ct * n0[0] - st * n0[1];
+    n[1] = st * n0[0] + ct * n0[1];
+    n[2] = n0[2];
+}
+
+// Translation velocity d'(t) and rotation rate theta'(t) of the wall motion.
+template <typename real>
+__device__ __forceinline__ void wall_rates(const KP<real>& P, double t, real V[3], real& om)
+{
+    const double co = cos(P.womega * t);
+    V[0] = (real)(P.wamp[0] * P.womega * co);
+    V[1] = (real)(P.wamp[1] * P.womega * co);
+    V[2] = (real)(P.wamp[2] * P.womega * co);
+    om = (real)(P.wroll * P.womega * co);
+}
+
+// Velocity of a wall particle from its motion record k = {m r_x, m r_y, m, 0}
+// (m: follows the motion, r: lever arm from the rotation centre at the
+// configuration update): v_w = m d'(t) + theta'(t) z x (m r).
+template <typename real>
+__device__ __forceinline__ void wall_velocity(const R4<real>& k, const real V[3], real om, real v[3])
+{
+    v[0] = k.z * V[0] - om * k.y;
+    v[1] = k.z * V[1] + om * k.x;
+    v[2] = k.z * V[2];
 }
 
 template <typename real>
@@ -471,19 +528,27 @@ __global__ __launch_bounds__(BLOCK) void k_place_fluid(
     bgeo[s] = g;
 }
 
-// Walls (set-up only; walls are static). `wcase` gives the case of each wall
-// particle in input order.
+// Walls, sorted by cell at set-up and, for moving walls, at every
+// configuration update. Inputs are in the order given (the reference pose);
+// `wcase` gives the case of each wall particle, `wflag` whether it follows
+// its case's motion. Each wall takes its pose at its case's clock, which
+// only changes when the case completes an advection step, so a case that
+// does not update its configuration keeps its wall order bit for bit.
 template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_bin_walls(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ wcase,
-                                                     int n, const double* __restrict__ x0,
-                                                     const double* __restrict__ x1, const double* __restrict__ x2,
-                                                     int32_t* __restrict__ key, int32_t* __restrict__ rank,
-                                                     int32_t* __restrict__ cnt)
+                                                     const Ctrl* __restrict__ ctrl_all,
+                                                     const int32_t* __restrict__ wflag, int n,
+                                                     const double* __restrict__ x0, const double* __restrict__ x1,
+                                                     const double* __restrict__ x2, int32_t* __restrict__ key,
+                                                     int32_t* __restrict__ rank, int32_t* __restrict__ cnt)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const KP<real>& P = Pt[wcase[i]];
-    const double xs[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
+    const double xr[3] = {x0[i], x1[i], D == 3 ? x2[i] : 0.0};
+    const double nz[3] = {0.0, 0.0, 0.0};
+    double xs[3], ns[3];
+    wall_pose(P, ctrl_all[P.case_id].t, wflag[i], xr, nz, xs, ns);
     int c[3] = {0, 0, 0};
     for (int k = 0; k < D; ++k) c[k] = cell_coord(P, k, xs[k]);
     int kc = P.cbase + c[0] + P.n[0] * (c[1] + P.n[1] * c[2]);
@@ -519,23 +584,41 @@ __global__ __launch_bounds__(BLOCK) void k_cell_order(int ncell, const int32_t* 
     }
 }
 
-// Walls: move into cell order, freeze offsets, keep ids relative to the
-// case's first wall particle.
+// Walls: move into cell order in their pose at the case's clock, freeze
+// offsets and normals, keep ids relative to the case's first wall particle;
+// with `bmot`, also the motion record {m r_x, m r_y, m, 0} (m: follows the
+// motion, r: lever arm from the rotation centre).
 template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_gather_wall(
-    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ wcase, int n, const int32_t* __restrict__ perm,
-    const int32_t* __restrict__ key, const double* __restrict__ ax0, const double* __restrict__ ax1,
-    const double* __restrict__ ax2, const double* __restrict__ an0, const double* __restrict__ an1,
-    const double* __restrict__ an2, double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ wcase, const Ctrl* __restrict__ ctrl_all,
+    const int32_t* __restrict__ wflag, int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ key,
+    const double* __restrict__ ax0, const double* __restrict__ ax1, const double* __restrict__ ax2,
+    const double* __restrict__ an0, const double* __restrict__ an1, const double* __restrict__ an2,
+    double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
     typename GeoSel<D, real>::T* __restrict__ bgeo, typename GeoSel<D, real>::T* __restrict__ bnrm,
-    int32_t* __restrict__ bid)
+    int32_t* __restrict__ bid, R4<real>* __restrict__ bmot)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
     const KP<real>& P = Pt[wcase[i]];
     int kc = key[i] - P.cbase;
-    double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
+    const double t = ctrl_all[P.case_id].t;
+    const double xr[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
+    const double nr[3] = {an0[i], an1[i], D == 3 ? an2[i] : 0.0};
+    double x[3], nv[3];
+    const int mv = wflag[i];
+    wall_pose(P, t, mv, xr, nr, x, nv);
+    if (bmot) {
+        R4<real> k = {(real)0, (real)0, (real)0, (real)0};
+        if (P.wmove && mv) {
+            const double sn = sin(P.womega * t);
+            k.x = (real)(x[0] - (P.wpivot[0] + P.wamp[0] * sn));
+            k.y = (real)(x[1] - (P.wpivot[1] + P.wamp[1] * sn));
+            k.z = (real)1;
+        }
+        bmot[s] = k;
+    }
     bx0[s] = x[0];
     bx1[s] = x[1];
     if (D == 3) bx2[s] = x[2];
@@ -546,12 +629,12 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
     typename GeoSel<D, real>::T g, nn;
     g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
     g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
-    nn.x = (real)an0[i];
-    nn.y = (real)an1[i];
+    nn.x = (real)nv[0];
+    nn.y = (real)nv[1];
     if constexpr (D == 3) {
         g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
         g.w = (real)0;
-        nn.z = (real)an2[i];
+        nn.z = (real)nv[2];
         nn.w = (real)0;
     }
     bgeo[s] = g;
@@ -911,7 +994,7 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
 // Eq. (transport), of each particle on the frozen configuration, once per
 // advection step after the re-initialisation (`gate`: for the cases starting
 // a step), for the cases that have either:
-//   av  = 2 sum_j m eta/(rho_i rho_j) (v_i - v_j)/r W'   (walls: V_w/rho_i, v_w = 0)
+//   av  = 2 sum_j m eta/(rho_i rho_j) (v_i - v_j)/r W'   (walls: V_w/rho_i, v_j = v_w)
 //   atv = 2 sum_j m p0/(rho_i rho_j) W' e_ij             (walls: V_w/rho_i)
 // into avt[2 i] and avt[2 i + 1]. T lanes share a particle.
 template <int D, typename real, int T>
@@ -919,7 +1002,8 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, const Ctrl* __restrict__ ctrl_all, int gate,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
-    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, R4<real>* __restrict__ avt)
+    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, R4<real>* __restrict__ avt,
+    const R4<real>* __restrict__ wmot)
 {
     const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
     const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
@@ -936,7 +1020,12 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
     const real rho_i = P.rho0 + (D == 2 ? si.z : si.w);
     const real inv_rho_i = (real)1 / rho_i;
     real av[3] = {0, 0, 0}, at[3] = {0, 0, 0};
+    // moving walls: velocity at the start of the advection step (no slip)
+    const bool mv = wmot != nullptr && P.wmove;
+    real Vw[3] = {0, 0, 0}, omw = 0;
+    if (mv) wall_rates(P, ctrl->t, Vw, omw);
     struct FluidJ { G o; R4<real> s; };
+    struct WallJ { G o; R4<real> k; };
     for_pairs<T, BATCH>(
         nbr, i, ncnt[i], P.maxn, l,
         [&](uint32_t e) {
@@ -961,15 +1050,24 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
             if (D == 3) at[2] += ct * q.e[2];
         });
     for_pairs<T, BATCH>(
-        wnb, i, wcnt[i], P.maxw, l, [&](uint32_t e) { return wgeo[e & NBR_MASK]; },
-        [&](uint32_t e, const G& ow) {
-            Pair<D, real> q = pair_geo<D, real>(P, oi, ow, e >> NBR_SHIFT);
+        wnb, i, wcnt[i], P.maxw, l,
+        [&](uint32_t e) {
+            uint32_t w = e & NBR_MASK;
+            WallJ r;
+            r.o = wgeo[w];
+            if (mv) r.k = wmot[w];
+            return r;
+        },
+        [&](uint32_t e, const WallJ& r) {
+            Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const real w = P.vw * inv_rho_i * q.dW;
             const real cv = (real)2 * P.eta * w / q.r;
             const real ct = (real)2 * P.p0 * w;
-            av[0] += cv * vi[0];
-            av[1] += cv * vi[1];
-            if (D == 3) av[2] += cv * vi[2];
+            real vw[3] = {0, 0, 0};
+            if (mv) wall_velocity(r.k, Vw, omw, vw);
+            av[0] += cv * (vi[0] - vw[0]);
+            av[1] += cv * (vi[1] - vw[1]);
+            if (D == 3) av[2] += cv * (vi[2] - vw[2]);
             at[0] += ct * q.e[0];
             at[1] += ct * q.e[1];
             if (D == 3) at[2] += ct * q.e[2];
@@ -998,7 +1096,7 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
     real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all,
-    const R4<real>* __restrict__ avt)
+    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot)
 {
     const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
     const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
@@ -1037,6 +1135,10 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     using G = typename GeoSel<D, real>::T;
     const real dt = (real)S.dt;
     const real half = (real)0.5 * dt;
+    // moving walls: velocity rates at the sub-step's start (the level of v^n)
+    const bool mv = wmot != nullptr && P.wmove;
+    real Vw[3] = {0, 0, 0}, omw = 0;
+    if (mv) wall_rates(P, ctrl->t + S.tau, Vw, omw);
     const R4<real> si = st[i];
     real vi[3], dev_i;
     if (D == 2) {
@@ -1052,7 +1154,7 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     const G oi = geo[i];
     real acc[3] = {0, 0, 0};
     struct FluidJ { G o; R4<real> s; real dr; };
-    struct WallJ { G o; G n; };
+    struct WallJ { G o; G n; R4<real> k; };
     for_pairs<T, BATCH>(
         nbr, i, ncnt[i], P.maxn, l,
         [&](uint32_t e) {
@@ -1086,13 +1188,20 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
             WallJ r;
             r.o = wgeo[w];
             r.n = wnrm[w];
+            if (mv) r.k = wmot[w];
             return r;
         },
         [&](uint32_t e, const WallJ& r) {
             Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const G& nw = r.n;
             real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
-            real du = (real)2 * UL;  // U_R = -U_L for a static wall
+            real uw = 0;  // u_w = -n_w . v_w, zero for a static wall
+            if (mv) {
+                real vw[3];
+                wall_velocity(r.k, Vw, omw, vw);
+                uw = -(nw.x * vw[0] + nw.y * vw[1] + (D == 3 ? zc(nw) * vw[2] : (real)0));
+            }
+            real du = (real)2 * (UL - uw);  // U_L - U_R with U_R = -U_L + 2 u_w
             real gr = pq.r * (P.g[0] * pq.e[0] + P.g[1] * pq.e[1] + (D == 3 ? P.g[2] * pq.e[2] : (real)0));
             real pR = p_i + rho_i * gr;
             real rhoR = P.rho0 + pR * P.inv_c2;
@@ -1148,7 +1257,8 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
     double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
-    unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt)
+    unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt,
+    const R4<real>* __restrict__ wmot)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i0 = pair_block_first<T>(b);
@@ -1163,6 +1273,10 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const real half = (real)0.5 * dt;
     const int i = i0 + (int)threadIdx.x / T;
     const int l = threadIdx.x % T;
+    // moving walls: velocity rates at the sub-step's end (the level of v^{n+1})
+    const bool mv = wmot != nullptr && P.wmove;
+    real Vw[3] = {0, 0, 0}, omw = 0;
+    if (mv) wall_rates(P, ctrl->t + (S.tau + S.dt), Vw, omw);
     real speed = 0;
     uint32_t bad = 0;
     if (i < P.fbase + P.nf) {
@@ -1176,7 +1290,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
         const G oi = geo[i];
         real sum = 0;
         struct HalfJ { G o; R4<real> h; };
-        struct WallJ { G o; G n; };
+        struct WallJ { G o; G n; R4<real> k; };
         for_pairs<T, BATCH>(
             nbr, i, ncnt[i], P.maxn, l,
             [&](uint32_t e) {
@@ -1206,6 +1320,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
                 WallJ r;
                 r.o = wgeo[w];
                 r.n = wnrm[w];
+                if (mv) r.k = wmot[w];
                 return r;
             },
             [&](uint32_t e, const WallJ& r) {
@@ -1216,7 +1331,12 @@ __global__ __launch_bounds__(BLOCK) void k_density(
                 real pR = p_i + rho_i * gr;
                 real rhoR = P.rho0 + pR * P.inv_c2;
                 real rho_bar = (real)0.5 * (rho_i + rhoR);
-                real us = (p_i - pR) * P.half_inv_c / rho_bar;  // (U_L + U_R)/2 = 0
+                real us = (p_i - pR) * P.half_inv_c / rho_bar;  // + (U_L + U_R)/2 = u_w below
+                if (mv) {
+                    real vw[3];
+                    wall_velocity(r.k, Vw, omw, vw);
+                    us += -(nw.x * vw[0] + nw.y * vw[1] + (D == 3 ? zc(nw) * vw[2] : (real)0));
+                }
                 sum += P.vw * (us - UL) * pq.dW;
             });
         sum = group_sum<T>(sum);

@@ -57,6 +57,7 @@ struct EngineBase {
     virtual int set_fluid(int c, int64_t n, const double* pos, const double* vel, const double* rho,
                           const double* drho) = 0;
     virtual int set_walls(int c, int64_t n, const double* pos, const double* nrm) = 0;
+    virtual int set_wall_motion(int c, const sphx_wall_motion* m, const int32_t* moving) = 0;
     virtual int build_neighbors() = 0;
     virtual int get_neighbors(int c, int kind, int64_t* off, int64_t* idx, int64_t cap, int64_t* n_out) = 0;
     virtual int density_reinit() = 0;
@@ -157,12 +158,17 @@ struct Engine final : EngineBase {
         std::vector<double> pos, vel, rho, drho;
     };
     std::vector<Pending> pend;
-    // walls (static), all cases concatenated
+    // walls, all cases concatenated: as given (reference pose, input order)
+    // and cell-sorted in the pose of the last configuration update
     int nw_tot = 0;
     std::vector<std::vector<double>> wpos_h, wnrm_h;  // per case, as given
+    std::vector<std::vector<int32_t>> wflag_h;         // per case: follows the motion (empty: all)
+    double* wref[6] = {};                              // reference positions and normals, input order
+    int32_t *wflag = nullptr, *wcase = nullptr, *wkey = nullptr, *wrank = nullptr, *wperm = nullptr;
     double* wx[3] = {};
     G* wgeo = nullptr;
     G* wnrm = nullptr;
+    R4<real>* wmot = nullptr;  // motion records (only while some case has moving walls)
     int32_t* wid = nullptr;
     int32_t* wstart = nullptr;
     // control
@@ -324,6 +330,7 @@ struct Engine final : EngineBase {
         pend.assign(C, Pending{});
         wpos_h.assign(C, {});
         wnrm_h.assign(C, {});
+        wflag_h.assign(C, {});
         int cbase = 0;
         for (int c = 0; c < C; ++c) {
             RETCHK(init_case(c, cbase));
@@ -362,6 +369,15 @@ struct Engine final : EngineBase {
         return false;
     }
     R4<real>* avt_arg() const { return any_adv() ? avt : nullptr; }
+
+    // Whether any case has moving walls.
+    bool any_move() const
+    {
+        for (int c = 0; c < C; ++c)
+            if (hP[c].wmove) return true;
+        return false;
+    }
+    R4<real>* wmot_arg() const { return any_move() ? wmot : nullptr; }
 
     // Call f with the lanes per particle of the pair kernels as a constant.
     template <typename F>
@@ -640,17 +656,68 @@ struct Engine final : EngineBase {
         wpos_h[c].assign(pos, pos + n * D);
         wnrm_h[c].assign(nrm, nrm + n * D);
         hP[c].nw = (int)n;
+        hP[c].wmove = 0;  // new walls are static until a motion is given
+        wflag_h[c].clear();
         return upload_walls();
     }
 
-    // Concatenate the walls of every case, sort them by (global) cell and
-    // input order, freeze their offsets.
+    // Prescribed rigid motion of case c's walls (NULL: static again) and
+    // per-wall flags (NULL: every wall particle follows it). The reach of the
+    // motion must stay inside the domain box, and no periodic axis may move.
+    int set_wall_motion(int c, const sphx_wall_motion* m, const int32_t* moving) override
+    {
+        RETCHK(check_case(c));
+        KP<real>& P = hP[c];
+        if (!m) {
+            P.wmove = 0;
+            wflag_h[c].clear();
+            return upload_walls();
+        }
+        sphx_wall_motion q = *m;
+        if (D == 2) q.amp[2] = q.pivot[2] = 0.0;
+        bool finite = std::isfinite(q.omega) && q.omega >= 0.0 && std::isfinite(q.roll);
+        for (int k = 0; k < 3; ++k) finite = finite && std::isfinite(q.amp[k]) && std::isfinite(q.pivot[k]);
+        if (!finite) return ctx->fail(SPHX_EINVAL, case_tag(c) + "bad wall motion");
+        for (int k = 0; k < D; ++k)
+            if (P.periodic[k] && (q.amp[k] != 0.0 || (k < 2 && q.roll != 0.0)))
+                return ctx->fail(SPHX_EINVAL, case_tag(c) + "walls cannot move along a periodic axis");
+        const int nw = P.nw;
+        std::vector<int32_t> fl(nw, 1);
+        if (moving)
+            for (int w = 0; w < nw; ++w) fl[w] = moving[w] != 0;
+        const std::vector<double>& xp = wpos_h[c];
+        for (int w = 0; w < nw; ++w) {
+            if (!fl[w]) continue;
+            const double* x = &xp[(size_t)w * D];
+            double arm = std::hypot(x[0] - q.pivot[0], x[1] - q.pivot[1]);
+            for (int k = 0; k < D; ++k) {
+                // displacement bound: |amp_k| plus the chord |roll| * arm of the rotation
+                double reach = std::fabs(q.amp[k]) + (k < 2 ? std::fabs(q.roll) * arm : 0.0);
+                double margin = 1e-12 * (P.hi[k] - P.lo[k]);
+                if (!(x[k] - reach >= P.lo[k] + margin && x[k] + reach < P.hi[k] - margin))
+                    return ctx->fail(SPHX_EINVAL, case_tag(c) + "the wall motion leaves the domain box");
+            }
+        }
+        P.wmove = 1;
+        for (int k = 0; k < 3; ++k) {
+            P.wamp[k] = q.amp[k];
+            P.wpivot[k] = q.pivot[k];
+        }
+        P.womega = q.omega;
+        P.wroll = q.roll;
+        wflag_h[c] = fl;
+        return upload_walls();
+    }
+
+    // Concatenate the walls of every case (reference pose, input order) and
+    // sort them by (global) cell and input order in their current pose.
     int upload_walls()
     {
         HIPCHK(hipStreamSynchronize(s));
         drop_graphs();
         configured = false;
         free_list(wall_allocs);
+        wmot = nullptr;
         int base = 0;
         for (int c = 0; c < C; ++c) {
             hP[c].wbase = base;
@@ -670,39 +737,52 @@ struct Engine final : EngineBase {
             HIPCHK(hipStreamSynchronize(s));
             return SPHX_OK;
         }
-        int32_t *wkey, *wrank, *wperm, *wcase;
-        std::vector<void*> tmp;
-        RETCHK(dalloc(tmp, wkey, wcap));
-        RETCHK(dalloc(tmp, wrank, wcap));
-        RETCHK(dalloc(tmp, wperm, wcap));
-        RETCHK(dalloc(tmp, wcase, wcap));
+        for (int k = 0; k < 6; ++k) RETCHK(dalloc(L, wref[k], wcap));
+        RETCHK(dalloc(L, wflag, wcap));
+        RETCHK(dalloc(L, wcase, wcap));
+        RETCHK(dalloc(L, wkey, wcap));
+        RETCHK(dalloc(L, wrank, wcap));
+        RETCHK(dalloc(L, wperm, wcap));
+        if (any_move()) RETCHK(dalloc(L, wmot, wcap));
         size_t nn = (size_t)nw_tot;
-        RETCHK(ensure_stage(nn * 6));
         std::vector<double> soa(nn * 6, 0.0);
-        std::vector<int32_t> wc(nn);
+        std::vector<int32_t> wc(nn), wf(nn);
         for (int c = 0; c < C; ++c)
             for (int i = 0; i < hP[c].nw; ++i) {
                 size_t g = (size_t)hP[c].wbase + i;
                 wc[g] = c;
+                wf[g] = wflag_h[c].empty() ? 1 : wflag_h[c][i];
                 for (int k = 0; k < D; ++k) {
                     soa[k * nn + g] = wpos_h[c][(size_t)i * D + k];
                     soa[(3 + k) * nn + g] = wnrm_h[c][(size_t)i * D + k];
                 }
             }
-        HIPCHK(hipMemcpyAsync(stage, soa.data(), nn * 6 * sizeof(double), hipMemcpyHostToDevice, s));
+        for (int k = 0; k < 6; ++k)
+            HIPCHK(hipMemcpyAsync(wref[k], soa.data() + k * nn, nn * sizeof(double), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(wcase, wc.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        double* sx[3] = {stage, stage + nn, stage + 2 * nn};
-        double* sn[3] = {stage + 3 * nn, stage + 4 * nn, stage + 5 * nn};
+        HIPCHK(hipMemcpyAsync(wflag, wf.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        RETCHK(enqueue_wall_sort());
+        HIPCHK(hipStreamSynchronize(s));
+        return SPHX_OK;
+    }
+
+    // Pose, bin and sort the walls of every case at its clock (the cell
+    // counters are consumed and cleared by the scan, so this can sit in a
+    // captured graph).
+    int enqueue_wall_sort()
+    {
+        if (nw_tot == 0) return SPHX_OK;
         const int n = nw_tot;
-        k_bin_walls<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, n, sx[0], sx[1], sx[2], wkey, wrank, cnt);
+        const int D3 = D == 3 ? 2 : 1;
+        k_bin_walls<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, ctrl, wflag, n, wref[0], wref[1], wref[D3], wkey,
+                                                        wrank, cnt);
         RETCHK(enqueue_scan(wstart));
         k_scatter_walls<<<nblk(n), BLOCK, 0, s>>>(n, wkey, wrank, wstart, wperm);
         k_cell_order<<<nblk(ncell), BLOCK, 0, s>>>(ncell, wstart, wperm);
-        k_gather_wall<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, n, wperm, wkey, sx[0], sx[1], sx[2], sn[0], sn[1],
-                                                          sn[2], wx[0], wx[1], wx[2], wgeo, wnrm, wid);
+        k_gather_wall<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, ctrl, wflag, n, wperm, wkey, wref[0], wref[1],
+                                                          wref[D3], wref[3], wref[4], wref[3 + D3], wx[0], wx[1],
+                                                          wx[2], wgeo, wnrm, wid, wmot_arg());
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(s));
-        free_list(tmp);
         return SPHX_OK;
     }
 
@@ -733,6 +813,7 @@ struct Engine final : EngineBase {
         ++conf_gen;
         int b = 1 - a;
         const int nb = nblk(ntot);
+        if (any_move()) RETCHK(enqueue_wall_sort());  // walls in their pose at each case's clock
         k_bin<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, x[a][0], x[a][1], x[a][2], cell[a], key,
                                             rank, cnt);
         RETCHK(enqueue_scan(fstart));
@@ -750,10 +831,12 @@ struct Engine final : EngineBase {
     {
         const int nb = pair_blocks();
         R4<real>* av = avt_arg();
+        R4<real>* wm = wmot_arg();
         k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a],
-                                                    dr3[a], hf, acc, q, adv, vslot, av);
+                                                    dr3[a], hf, acc, q, adv, vslot, av, wm);
         k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                   hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro, vslot, q, av);
+                                                   hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro, vslot, q, av,
+                                                   wm);
     }
 
     // Pressure and density relaxation of sub-step q on set a; `adv`: close
@@ -784,7 +867,7 @@ struct Engine final : EngineBase {
         const int nb = pair_blocks();
         by_lanes([&](auto t) {
             k_adv_forces<D, real, decltype(t)::value><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr,
-                                                                          ncnt, wnb, wcnt, st[a], avt);
+                                                                          ncnt, wnb, wcnt, st[a], avt, wmot_arg());
         });
         HIPCHK(hipGetLastError());
         return SPHX_OK;
@@ -1133,12 +1216,13 @@ struct Engine final : EngineBase {
         const int a = cur;
         RETCHK(time_launches(reps, &ms[0], [&] {
             k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                        st[a], dr3[a], hf, nullptr, 0, 0, vslot, avt_arg());
+                                                        st[a], dr3[a], hf, nullptr, 0, 0, vslot, avt_arg(),
+                                                        wmot_arg());
         }));
         RETCHK(time_launches(reps, &ms[1], [&] {
             k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
                                                        hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], nullptr, vslot, 0,
-                                                       avt_arg());
+                                                       avt_arg(), wmot_arg());
         }));
         // the list build is idempotent on the current set
         RETCHK(time_launches(reps, &ms[2], [&] { launch_neighbors<T>(1, a); }));
@@ -1266,6 +1350,13 @@ struct Engine final : EngineBase {
         hP[c].fcap = old.fcap;
         hP[c].wbase = old.wbase;
         hP[c].nw = old.nw;
+        hP[c].wmove = old.wmove;
+        for (int k = 0; k < 3; ++k) {
+            hP[c].wamp[k] = old.wamp[k];
+            hP[c].wpivot[k] = old.wpivot[k];
+        }
+        hP[c].womega = old.womega;
+        hP[c].wroll = old.wroll;
         RETCHK(upload_params());
         drop_graphs();  // the queue may gain or lose the advection-step forces
         configured = false;
@@ -1391,6 +1482,7 @@ struct Engine final : EngineBase {
     int gnn_check_ready()
     {
         if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
+        if (any_move()) return ctx->fail(SPHX_EINVAL, "the surrogate models static walls only");
         if (!gn.ready) return ctx->fail(SPHX_ESTATE, "surrogate parameters not set");
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
         return SPHX_OK;
@@ -1700,6 +1792,7 @@ struct Engine final : EngineBase {
                           int64_t* n_surrogate) override
     {
         if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
+        if (any_move()) return ctx->fail(SPHX_EINVAL, "the surrogate models static walls only");
         if (!gn.ready) return ctx->fail(SPHX_ESTATE, "surrogate parameters not set");
         if (windows < 0) return ctx->fail(SPHX_EINVAL, "negative window count");
         RETCHK(all_have_fluid());
@@ -1865,6 +1958,16 @@ int sphx_set_walls(sphx_ctx* ctx, int64_t n, const double* pos, const double* no
 int sphx_set_walls_case(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* normal)
 {
     ENG_CALL(set_walls(c, n, pos, normal));
+}
+
+int sphx_set_wall_motion(sphx_ctx* ctx, const sphx_wall_motion* motion, const int32_t* moving)
+{
+    ENG_CALL(set_wall_motion(0, motion, moving));
+}
+
+int sphx_set_wall_motion_case(sphx_ctx* ctx, int32_t c, const sphx_wall_motion* motion, const int32_t* moving)
+{
+    ENG_CALL(set_wall_motion(c, motion, moving));
 }
 
 int sphx_build_neighbors(sphx_ctx* ctx) { ENG_CALL(build_neighbors()); }

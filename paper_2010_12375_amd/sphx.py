@@ -26,6 +26,7 @@ ERROR_NAMES = {SPHX_EINVAL: "EINVAL", SPHX_ENOMEM: "ENOMEM", SPHX_EHIP: "EHIP", 
 
 EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_set_params_case", "sphx_destroy", "sphx_last_error",
             "sphx_set_fluid", "sphx_set_fluid_case", "sphx_set_walls", "sphx_set_walls_case",
+            "sphx_set_wall_motion", "sphx_set_wall_motion_case",
             "sphx_build_neighbors", "sphx_get_neighbors", "sphx_get_neighbors_case", "sphx_density_reinit",
             "sphx_time_steps", "sphx_time_steps_case", "sphx_compute_rates", "sphx_compute_rates_case",
             "sphx_advance", "sphx_case_status", "sphx_get_field", "sphx_get_field_case", "sphx_diagnostics",
@@ -48,6 +49,11 @@ class sphx_params(C.Structure):
                 ("gravity", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("sigma0", C.c_double), ("eta", C.c_double), ("p_background", C.c_double),
                 ("reinit_mode", C.c_int32), ("pad_", C.c_int32)]
+
+
+class sphx_wall_motion(C.Structure):
+    _fields_ = [("amp", C.c_double * 3), ("omega", C.c_double), ("roll", C.c_double),
+                ("pivot", C.c_double * 3)]
 
 
 class sphx_diag(C.Structure):
@@ -80,6 +86,8 @@ def load(path=None):
         "sphx_set_fluid_case": [vp, i32, i64, vp, vp, vp, vp],
         "sphx_set_walls": [vp, i64, vp, vp],
         "sphx_set_walls_case": [vp, i32, i64, vp, vp],
+        "sphx_set_wall_motion": [vp, C.POINTER(sphx_wall_motion), vp],
+        "sphx_set_wall_motion_case": [vp, i32, C.POINTER(sphx_wall_motion), vp],
         "sphx_build_neighbors": [vp],
         "sphx_get_neighbors": [vp, C.c_int, vp, vp, i64, pi64],
         "sphx_get_neighbors_case": [vp, i32, C.c_int, vp, vp, i64, pi64],
@@ -152,7 +160,8 @@ def params_from_case(case, precision=None, nsub_queue=0, sigma0=0.0):
 
 class Simulation:
     """One library context: a batch of cases (one by default), each a fluid
-    body and a static wall body. Per-case methods take `case` (default 0)."""
+    body and a wall body (static or moving). Per-case methods take `case`
+    (default 0)."""
 
     def __init__(self, params, stream=None, lib=None):
         self._L = lib or load()
@@ -182,6 +191,7 @@ class Simulation:
         sim.set_fluid(case.fluid_pos)
         if with_walls and case.n_wall:
             sim.set_walls(case.wall_pos, case.wall_normal)
+            sim.set_case_motion(case)
         return sim
 
     @classmethod
@@ -192,6 +202,7 @@ class Simulation:
             sim.set_fluid(c.fluid_pos, case=k)
             if with_walls and c.n_wall:
                 sim.set_walls(c.wall_pos, c.wall_normal, case=k)
+                sim.set_case_motion(c, case=k)
         return sim
 
     def close(self):
@@ -224,6 +235,28 @@ class Simulation:
         pos, normal = _f64(pos), _f64(normal)
         self._check(self._L.sphx_set_walls_case(self._h, case, pos.shape[0], _ptr(pos), _ptr(normal)),
                     "sphx_set_walls_case")
+
+    def set_wall_motion(self, amp=(0.0, 0.0, 0.0), omega=0.0, roll=0.0, pivot=(0.0, 0.0, 0.0), moving=None,
+                        case=0, static=False):
+        """Prescribed rigid motion of case `case`'s walls (static=True: static
+        again); `moving`: one flag per wall particle (None: all move)."""
+        if static:
+            self._check(self._L.sphx_set_wall_motion_case(self._h, case, None, None), "sphx_set_wall_motion_case")
+            return
+        m = sphx_wall_motion()
+        for k in range(3):
+            m.amp[k] = float(amp[k]) if k < len(amp) else 0.0
+            m.pivot[k] = float(pivot[k]) if k < len(pivot) else 0.0
+        m.omega, m.roll = float(omega), float(roll)
+        flags = None if moving is None else np.ascontiguousarray(moving, dtype=np.int32)
+        self._check(self._L.sphx_set_wall_motion_case(self._h, case, C.byref(m), _ptr(flags)),
+                    "sphx_set_wall_motion_case")
+
+    def set_case_motion(self, c, case=0):
+        """Apply a workload case's wall motion, if it has one."""
+        m = getattr(c, "wall_motion", None)
+        if m is not None:
+            self.set_wall_motion(m.amp, m.omega, m.roll, m.pivot, getattr(c, "wall_moving", None), case=case)
 
     def build_neighbors(self):
         self._check(self._L.sphx_build_neighbors(self._h), "sphx_build_neighbors")

@@ -374,7 +374,8 @@ def piston_2d(dp, V=0.2, L=2.0, W=0.4, omega=0.5, precision=FP64, layers=4, name
     prm = _params(2, dp, 1.0)
     mo = WallMotion(amp=(V / omega, 0.0, 0.0), omega=omega)
     pad = layers * dp + 2.0 * prm["h"]
+    # the box holds the piston over its whole stroke [-V/omega, V/omega]
     return Case(name=name or f"piston2d_dp{dp:g}", gravity=(0.0, 0.0, 0.0),
-                lo=(-pad, 0.0, 0.0), hi=(L + V / omega + pad + 1.0, W, 0.0), periodic=(0, 1, 0),
+                lo=(-pad - V / omega, 0.0, 0.0), hi=(L + V / omega + pad + 1.0, W, 0.0), periodic=(0, 1, 0),
                 fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision, column=(L, W),
                 wall_motion=mo, **prm)

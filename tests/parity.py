@@ -44,6 +44,11 @@ def make_pair(case, precision, state=None, nsub_queue=0, walls=True):
     o.set_fluid(case.fluid_pos, vel, rho, drho)
     if walls and case.n_wall:
         g.set_walls(case.wall_pos, case.wall_normal)
+        m = getattr(case, "wall_motion", None)
+        if m is not None:
+            mv = getattr(case, "wall_moving", None)
+            g.set_wall_motion(m.amp, m.omega, m.roll, m.pivot, mv)
+            o.set_wall_motion(amp=m.amp, omega=m.omega, roll=m.roll, pivot=m.pivot, moving=mv)
     return g, o
 
 

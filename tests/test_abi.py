@@ -47,6 +47,11 @@ def test_binding_layout_matches_header_structs():
     assert names == [f[0] for f in sphx.sphx_params._fields_]
     assert ctypes.sizeof(sphx.sphx_params) == 4 * 8 + 8 * (7 + 9 + 3)
     assert ctypes.sizeof(sphx.sphx_diag) == 8 * 12
+    body = re.search(r"typedef struct \{([^{}]*?)\} sphx_wall_motion;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = [re.sub(r"\[.*\]", "", d.strip().split(" ", 1)[1]).strip() for d in body.split(";") if d.strip()]
+    assert names == [f[0] for f in sphx.sphx_wall_motion._fields_]
+    assert ctypes.sizeof(sphx.sphx_wall_motion) == 8 * 8
 
 
 def test_missing_library_fails_loudly(tmp_path):
