@@ -7,11 +7,14 @@ neighbour lists); the timed region ends with the FP64 diagnostics reduction.
 Inputs are seeded synthetic dam breaks (no dataset), resident in device
 memory before the timed region starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload medium|small|large|ensemble]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload medium|small|large|ensemble|sloshing|surrogate]
 
 Prints one JSON line. value = fluid particles x acoustic sub-steps / wall
 time, in millions per second (summed over the cases for the ensemble of 64
-uneven dam breaks, which all advance in the same launches).
+uneven dam breaks, which all advance in the same launches). The sloshing
+workload is a 2D tank of the same particle count under prescribed sway and
+roll (moving walls re-posed and re-sorted at every configuration update).
 """
 import argparse
 import json
@@ -82,6 +85,9 @@ def cpu_baseline(case, budget_s=15.0):
     advection steps of the same workload (time-boxed)."""
     import oracle as O
     o = O.Oracle(case)
+    m = getattr(case, "wall_motion", None)
+    if m is not None:
+        o.set_wall_motion(amp=m.amp, omega=m.omega, roll=m.roll, pivot=m.pivot)
     o.build_config()
     t0 = time.perf_counter()
     nsub = 0
@@ -230,7 +236,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large", "ensemble", "surrogate"])
+    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large", "ensemble", "sloshing", "surrogate"])
     ap.add_argument("--train-cases", type=int, default=256, help="surrogate: training trajectories")
     ap.add_argument("--test-cases", type=int, default=32, help="surrogate: held-out trajectories")
     ap.add_argument("--train-iters", type=int, default=2000, help="surrogate: Adam steps (16 snapshots each)")
@@ -273,6 +279,8 @@ def main():
         case = wl.config_medium(0)
     elif args.workload == "large":
         case = wl.config_large(0)
+    elif args.workload == "sloshing":
+        case = wl.sloshing_2d(0.00625, roll=0.05, precision=wl.FP32, name="sloshing2d_51k")
     else:
         cases = wl.ensemble_cases(64, seed=0)
         case = cases[0]
@@ -296,6 +304,7 @@ def main():
         sim.set_fluid(case.fluid_pos)
         if case.n_wall:
             sim.set_walls(case.wall_pos, case.wall_normal)
+            sim.set_case_motion(case)
         n_fluid, n_wall, name = case.n_fluid, case.n_wall, case.name
     else:
         sim = sphx.Simulation.from_cases(cases, precision, stream=stream)

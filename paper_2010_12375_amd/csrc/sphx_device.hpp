@@ -997,8 +997,8 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
 //   av  = 2 sum_j m eta/(rho_i rho_j) (v_i - v_j)/r W'   (walls: V_w/rho_i, v_j = v_w)
 //   atv = 2 sum_j m p0/(rho_i rho_j) W' e_ij             (walls: V_w/rho_i)
 // into avt[2 i] and avt[2 i + 1]. T lanes share a particle.
-template <int D, typename real, int T>
-__global__ __launch_bounds__(BLOCK) void k_adv_forces(
+template <int D, typename real, int T, bool MOVE>
+__device__ __forceinline__ void adv_forces_body(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, const Ctrl* __restrict__ ctrl_all, int gate,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
     const real inv_rho_i = (real)1 / rho_i;
     real av[3] = {0, 0, 0}, at[3] = {0, 0, 0};
     // moving walls: velocity at the start of the advection step (no slip)
-    const bool mv = wmot != nullptr && P.wmove;
+    const bool mv = MOVE && P.wmove;
     real Vw[3] = {0, 0, 0}, omw = 0;
     if (mv) wall_rates(P, ctrl->t, Vw, omw);
     struct FluidJ { G o; R4<real> s; };
@@ -1082,14 +1082,36 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
     avt[2 * (size_t)i + 1] = R4<real>{at[0], at[1], at[2], (real)0};
 }
 
+template <int D, typename real, int T, bool MOVE>
+__global__ __launch_bounds__(BLOCK) void k_adv_forces(
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, const Ctrl* __restrict__ ctrl_all, int gate,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
+    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
+    const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, R4<real>* __restrict__ avt,
+    const R4<real>* __restrict__ wmot)
+{
+    if constexpr (MOVE) {
+        // cases with static walls run the static instantiation's code
+        if (!Pt[tcase[pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)) / TILE]].wmove) {
+            adv_forces_body<D, real, T, false>(
+                Pt, tcase, ctrl_all, gate, geo, wgeo, nbr, ncnt, wnb, wcnt, st, avt, wmot);
+            return;
+        }
+    }
+    adv_forces_body<D, real, T, MOVE>(
+        Pt, tcase, ctrl_all, gate, geo, wgeo, nbr, ncnt, wnb, wcnt, st, avt, wmot);
+}
+
+// The pair kernels below take MOVE = true only for batches with moving
+// walls; the static instantiation compiles none of the wall-velocity code.
 // ---------------------------------------------------------------------
 // S6: pressure relaxation. First Verlet half-step of density (position
 // half-steps are applied together in S7), EoS, Riemann momentum equation
 // with fluid and wall neighbours and gravity, velocity update. T lanes share
 // a particle: each takes every T-th neighbour, partial sums are combined
 // with shuffles and lane 0 writes.
-template <int D, typename real, int T>
-__global__ __launch_bounds__(BLOCK) void k_pressure(
+template <int D, typename real, int T, bool MOVE>
+__device__ __forceinline__ void pressure_body(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
@@ -1136,7 +1158,7 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     const real dt = (real)S.dt;
     const real half = (real)0.5 * dt;
     // moving walls: velocity rates at the sub-step's start (the level of v^n)
-    const bool mv = wmot != nullptr && P.wmove;
+    const bool mv = MOVE && P.wmove;
     real Vw[3] = {0, 0, 0}, omw = 0;
     if (mv) wall_rates(P, ctrl->t + S.tau, Vw, omw);
     const R4<real> si = st[i];
@@ -1243,14 +1265,38 @@ __global__ __launch_bounds__(BLOCK) void k_pressure(
     }
 }
 
+template <int D, typename real, int T, bool MOVE>
+__global__ __launch_bounds__(BLOCK) void k_pressure(
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
+    const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
+    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
+    const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
+    real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all,
+    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot)
+{
+    if constexpr (MOVE) {
+        // cases with static walls run the static instantiation's code
+        if (!Pt[tcase[pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)) / TILE]].wmove) {
+            pressure_body<D, real, T, false>(
+                Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all,
+                avt, wmot);
+            return;
+        }
+    }
+    pressure_body<D, real, T, MOVE>(
+        Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all, avt,
+        wmot);
+}
+
 // ---------------------------------------------------------------------
 // S7: density relaxation. Riemann continuity equation with fluid and wall
 // neighbours using v^{n+1}, second Verlet half-steps of position (both
 // position half-steps land here, in the paper's order) and density, and the
 // block maxima of |v| for the next acoustic step. T lanes share a particle
 // as in S6.
-template <int D, typename real, int T>
-__global__ __launch_bounds__(BLOCK) void k_density(
+template <int D, typename real, int T, bool MOVE>
+__device__ __forceinline__ void density_body(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int finalize,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
@@ -1274,7 +1320,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(
     const int i = i0 + (int)threadIdx.x / T;
     const int l = threadIdx.x % T;
     // moving walls: velocity rates at the sub-step's end (the level of v^{n+1})
-    const bool mv = wmot != nullptr && P.wmove;
+    const bool mv = MOVE && P.wmove;
     real Vw[3] = {0, 0, 0}, omw = 0;
     if (mv) wall_rates(P, ctrl->t + (S.tau + S.dt), Vw, omw);
     real speed = 0;
@@ -1391,6 +1437,31 @@ __global__ __launch_bounds__(BLOCK) void k_density(
         unsigned long long* vslot = vslot_all + (size_t)P.case_id * 2 * VSLOTS;
         atomicMax(&vslot[(q & 1) * VSLOTS + (b & (VSLOTS - 1))], speed_bits((real)bm));
     }
+}
+
+template <int D, typename real, int T, bool MOVE>
+__global__ __launch_bounds__(BLOCK) void k_density(
+    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int finalize,
+    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
+    const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
+    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
+    const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
+    double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
+    unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt,
+    const R4<real>* __restrict__ wmot)
+{
+    if constexpr (MOVE) {
+        // cases with static walls run the static instantiation's code
+        if (!Pt[tcase[pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)) / TILE]].wmove) {
+            density_body<D, real, T, false>(
+                Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2,
+                drho_out, vslot_all, q, avt, wmot);
+            return;
+        }
+    }
+    density_body<D, real, T, MOVE>(
+        Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2, drho_out,
+        vslot_all, q, avt, wmot);
 }
 
 // S5 after the last queued density relaxation (one wavefront per case):

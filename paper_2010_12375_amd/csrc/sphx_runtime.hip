@@ -379,6 +379,15 @@ struct Engine final : EngineBase {
     }
     R4<real>* wmot_arg() const { return any_move() ? wmot : nullptr; }
 
+    // Call f with whether the pair kernels need the moving-wall terms as a
+    // constant (the static instantiation carries none of their code).
+    template <typename F>
+    void by_motion(F&& f)
+    {
+        if (wmot_arg()) f(std::true_type{});
+        else f(std::false_type{});
+    }
+
     // Call f with the lanes per particle of the pair kernels as a constant.
     template <typename F>
     void by_lanes(F&& f)
@@ -698,7 +707,8 @@ struct Engine final : EngineBase {
                     return ctx->fail(SPHX_EINVAL, case_tag(c) + "the wall motion leaves the domain box");
             }
         }
-        P.wmove = 1;
+        // a motion that moves no wall particle leaves the case static
+        P.wmove = std::count(fl.begin(), fl.end(), 1) > 0 ? 1 : 0;
         for (int k = 0; k < 3; ++k) {
             P.wamp[k] = q.amp[k];
             P.wpivot[k] = q.pivot[k];
@@ -832,11 +842,14 @@ struct Engine final : EngineBase {
         const int nb = pair_blocks();
         R4<real>* av = avt_arg();
         R4<real>* wm = wmot_arg();
-        k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a],
-                                                    dr3[a], hf, acc, q, adv, vslot, av, wm);
-        k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                   hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], dro, vslot, q, av,
-                                                   wm);
+        by_motion([&](auto mc) {
+            constexpr bool MV = decltype(mc)::value;
+            k_pressure<D, real, T, MV><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+                                                            st[a], dr3[a], hf, acc, q, adv, vslot, av, wm);
+            k_density<D, real, T, MV><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt,
+                                                           wnb, wcnt, hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2],
+                                                           dro, vslot, q, av, wm);
+        });
     }
 
     // Pressure and density relaxation of sub-step q on set a; `adv`: close
@@ -866,8 +879,10 @@ struct Engine final : EngineBase {
         if (!any_adv()) return SPHX_OK;
         const int nb = pair_blocks();
         by_lanes([&](auto t) {
-            k_adv_forces<D, real, decltype(t)::value><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr,
-                                                                          ncnt, wnb, wcnt, st[a], avt, wmot_arg());
+            by_motion([&](auto mc) {
+                k_adv_forces<D, real, decltype(t)::value, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
+                    dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a], avt, wmot_arg());
+            });
         });
         HIPCHK(hipGetLastError());
         return SPHX_OK;
@@ -1215,14 +1230,18 @@ struct Engine final : EngineBase {
         const int nb = pair_blocks();
         const int a = cur;
         RETCHK(time_launches(reps, &ms[0], [&] {
-            k_pressure<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                        st[a], dr3[a], hf, nullptr, 0, 0, vslot, avt_arg(),
-                                                        wmot_arg());
+            by_motion([&](auto mc) {
+                k_pressure<D, real, T, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
+                    dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, nullptr, 0, 0,
+                    vslot, avt_arg(), wmot_arg());
+            });
         }));
         RETCHK(time_launches(reps, &ms[1], [&] {
-            k_density<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                       hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2], nullptr, vslot, 0,
-                                                       avt_arg(), wmot_arg());
+            by_motion([&](auto mc) {
+                k_density<D, real, T, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
+                    dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
+                    x[a][1], x[a][2], nullptr, vslot, 0, avt_arg(), wmot_arg());
+            });
         }));
         // the list build is idempotent on the current set
         RETCHK(time_launches(reps, &ms[2], [&] { launch_neighbors<T>(1, a); }));
