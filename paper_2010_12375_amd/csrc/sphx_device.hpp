@@ -50,6 +50,17 @@ constexpr int BLOCK = 256;  // threads per block of every particle kernel
 constexpr int BATCH = SPHX_PAIR_BATCH;  // list entries / candidate rounds loaded ahead per lane
 constexpr uint32_t NO_ENTRY = 0xffffffffu;  // stencil code 63 never occurs
 constexpr int VSLOTS = 64;  // slots the density relaxation folds its block maxima into
+#ifndef SPHX_PAIR_WAVES
+#define SPHX_PAIR_WAVES 0
+#endif
+#ifndef SPHX_PREFETCH_3D
+#define SPHX_PREFETCH_3D 0
+#endif
+#if SPHX_PAIR_WAVES > 0
+#define SPHX_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(SPHX_PAIR_WAVES)))
+#else
+#define SPHX_PAIR_ATTR
+#endif
 
 enum : uint32_t {
     ERR_ESCAPE = 1u,       // a fluid particle left the domain box
@@ -106,6 +117,7 @@ template <typename real> struct KP {
     real L[3];                                // cell size per axis
     double Ld[3], lo[3], hi[3], period[3], half_period[3];
     int n[3], periodic[3];
+    int band;                                 // rows of cells per band of the cell order (see cell_index)
     double rc2, sigma0, rho0d;
     double cfl_ad_h, cfl_ac_h, u_ref, c0d;
     int maxn, maxw;                           // list capacity per particle (same for every case)
@@ -164,6 +176,11 @@ template <typename T> __device__ __forceinline__ T dmin(T a, T b) { return a < b
 // hardware reciprocal square root (about 1 ulp), far inside the FP32 budget
 __device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+// Quotients inside the pair loops: in FP32 a times the hardware reciprocal
+// of b (within about 1 ulp of the reciprocal; two instructions instead of
+// the correctly rounded division's eleven), in FP64 the division itself.
+__device__ __forceinline__ float div_r(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double div_r(double a, double b) { return a / b; }
 
 __device__ __forceinline__ unsigned long long speed_bits(float s) { return (unsigned long long)__float_as_uint(s); }
 __device__ __forceinline__ unsigned long long speed_bits(double s) { return (unsigned long long)__double_as_longlong(s); }
@@ -212,6 +229,45 @@ __device__ __forceinline__ int cell_coord(const KP<real>& P, int k, double xk)
     if (!(f >= 0.0)) f = 0.0;
     if (f > (double)(P.n[k] - 1)) f = (double)(P.n[k] - 1);
     return (int)f;
+}
+
+// Cell order. Each row of cells along x is contiguous (the neighbour build
+// scans three x-adjacent cells as one range). Rows are grouped into bands of
+// `band` rows along y and ordered band by band, inside a band by z, then y.
+// With a single z layer (2D) this is plain row-major order. In 3D it keeps
+// the rows a particle's neighbours lie in (y +- 1, z +- 1) within about
+// band * n_x cells of its own row, except at band edges, instead of a whole
+// x-y layer away, so that the neighbour records the wavefronts of one XCD
+// gather stay in that XCD's L2.
+template <typename real>
+__device__ __forceinline__ int cell_row(const KP<real>& P, int c1, int c2)
+{
+    const int b = c1 / P.band;
+    const int rows = min(P.band, P.n[1] - b * P.band);
+    return b * P.band * P.n[2] + c2 * rows + (c1 - b * P.band);
+}
+
+template <typename real>
+__device__ __forceinline__ int cell_index(const KP<real>& P, int c0, int c1, int c2)
+{
+    return P.n[0] * cell_row(P, c1, c2) + c0;
+}
+
+// Inverse of cell_index for a cell of the case (local index lc).
+template <typename real>
+__device__ __forceinline__ void cell_coords(const KP<real>& P, int lc, int c[3])
+{
+    const int row = lc / P.n[0];
+    c[0] = lc - row * P.n[0];
+    const int full = P.n[1] / P.band, per = P.band * P.n[2];
+    int b = row / per, rows = P.band, rem = row - b * per;
+    if (b >= full) {  // the last, partial band
+        b = full;
+        rows = P.n[1] - full * P.band;
+        rem = row - full * per;
+    }
+    c[2] = rem / rows;
+    c[1] = b * P.band + (rem - c[2] * rows);
 }
 
 // FP64 neighbour predicate on absolute positions: dx = x_i - x_j with one
@@ -338,14 +394,20 @@ __device__ __forceinline__ bool full_update(const Ctrl* ctrl, int force) { retur
 
 // Wrap periodic coordinates, check escapes, compute the global cell key and
 // an arrival rank inside the cell (one thread per slot). The last tile of a
-// case puts the case's unused slots into its padding cell.
+// case puts the case's unused slots into its padding cell. At the end of a
+// queue (q >= 0) each wavefront decides itself whether its case takes a full
+// update (update_due); escape and NaN bits go to err_pending, which the
+// scan's step_end folds in.
+template <typename real> __device__ __forceinline__ bool update_due(const KP<real>&, const Ctrl* __restrict__,
+                                                                    const unsigned long long* __restrict__, int, int);
 template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_bin(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
                                                int ntiles, Ctrl* __restrict__ ctrl_all, int force,
                                                double* __restrict__ x0, double* __restrict__ x1,
                                                double* __restrict__ x2, const int32_t* __restrict__ cell,
                                                int32_t* __restrict__ key, int32_t* __restrict__ rank,
-                                               int32_t* __restrict__ cnt)
+                                               int32_t* __restrict__ cnt,
+                                               const unsigned long long* __restrict__ vslot_all, int q)
 {
     const int tile = wave_tile();
     if (tile >= ntiles) return;
@@ -353,10 +415,12 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const KP<real>* __restrict__ Pt, 
     Ctrl* ctrl = ctrl_all + P.case_id;
     const int lane = threadIdx.x & 63;
     const int i = tile * TILE + lane;
+    const bool full = update_due(P, ctrl, vslot_all + (size_t)P.case_id * 2 * VSLOTS, force, q);
     if (lane == 0 && i + TILE == P.fbase + P.fcap) cnt[P.cbase + P.ncell] = P.fcap - P.nf;
-    if (i >= P.fbase + P.nf) return;
-    int kc;
-    if (!full_update(ctrl, force)) {
+    const bool act = i < P.fbase + P.nf;  // the active lanes are a prefix of the wavefront
+    int kc = -1;
+    if (!act) {
+    } else if (!full) {
         kc = cell[i];
     } else {
         double* xs[3] = {x0, x1, x2};
@@ -375,11 +439,30 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const KP<real>* __restrict__ Pt, 
             if (!(xk >= P.lo[k] && xk < P.hi[k])) bad |= ERR_ESCAPE;
             c[k] = cell_coord(P, k, xk);
         }
-        if (bad) atomicOr(&ctrl->err, bad);
-        kc = P.cbase + c[0] + P.n[0] * (c[1] + P.n[1] * c[2]);
+        if (bad) atomicOr(&ctrl->err_pending, bad);
+        kc = P.cbase + cell_index(P, c[0], c[1], c[2]);
     }
+    // Arrival ranks, one atomic per run of equal keys among consecutive
+    // lanes (the slots are in the previous cell order, so runs are long):
+    // the run's head adds the run length, each lane takes head's base plus
+    // its distance from the head. Any dense ranking serves; the placement
+    // restores the stable order.
+    const int prev = __shfl_up(kc, 1);
+    const bool head = act && (lane == 0 || prev != kc);
+    const unsigned long long heads = __ballot(head);
+    const int nact = __popcll(__ballot(act));
+    const unsigned long long le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const int h = act ? 63 - __clzll(heads & le) : lane;
+    int base = 0;
+    if (head) {
+        const unsigned long long after = heads & ~le;
+        const int next = after ? __ffsll((long long)after) - 1 : nact;
+        base = atomicAdd(&cnt[kc], next - lane);
+    }
+    base = __shfl(base, h);
+    if (!act) return;
     key[i] = kc;
-    rank[i] = atomicAdd(&cnt[kc], 1);
+    rank[i] = base + (lane - h);
 }
 
 // Exclusive scan of cell counts in three passes (block sums, scan of block
@@ -514,10 +597,9 @@ __global__ __launch_bounds__(BLOCK) void k_place_fluid(
         bgeo[s] = ageo[i];
         return;
     }
-    const int lc = kc - P.cbase;
-    const int c0 = lc % P.n[0];
-    const int c1 = (lc / P.n[0]) % P.n[1];
-    const int c2 = lc / (P.n[0] * P.n[1]);
+    int cc[3];
+    cell_coords(P, kc - P.cbase, cc);
+    const int c0 = cc[0], c1 = cc[1], c2 = cc[2];
     typename GeoSel<D, real>::T g;
     g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
     g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
@@ -551,7 +633,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin_walls(const KP<real>* __restrict_
     wall_pose(P, ctrl_all[P.case_id].t, wflag[i], xr, nz, xs, ns);
     int c[3] = {0, 0, 0};
     for (int k = 0; k < D; ++k) c[k] = cell_coord(P, k, xs[k]);
-    int kc = P.cbase + c[0] + P.n[0] * (c[1] + P.n[1] * c[2]);
+    int kc = P.cbase + cell_index(P, c[0], c[1], c[2]);
     key[i] = kc;
     rank[i] = atomicAdd(&cnt[kc], 1);
 }
@@ -623,9 +705,9 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
     bx1[s] = x[1];
     if (D == 3) bx2[s] = x[2];
     bid[s] = i - P.wbase;
-    int c0 = kc % P.n[0];
-    int c1 = (kc / P.n[0]) % P.n[1];
-    int c2 = kc / (P.n[0] * P.n[1]);
+    int cc[3];
+    cell_coords(P, kc, cc);
+    const int c0 = cc[0], c1 = cc[1], c2 = cc[2];
     typename GeoSel<D, real>::T g, nn;
     g.x = (real)(x[0] - (P.lo[0] + (double)c0 * P.Ld[0]));
     g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
@@ -691,7 +773,8 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const float margin = 8e-6f * Lm * Lm;
     const float rc2f = (float)P.rc2;
     const int kc = cell[i] - P.cbase;
-    const int ci[3] = {kc % P.n[0], (kc / P.n[0]) % P.n[1], kc / (P.n[0] * P.n[1])};
+    int ci[3];
+    cell_coords(P, kc, ci);
     int cnt_f = 0, cnt_w = 0;
     uint32_t over = 0;
 
@@ -797,7 +880,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
             int cy = ci[1] + dy;
             if (P.periodic[1]) cy = cy < 0 ? cy + P.n[1] : (cy >= P.n[1] ? cy - P.n[1] : cy);
             else if (cy < 0 || cy >= P.n[1]) continue;
-            const int rowc = P.cbase + P.n[0] * (cy + P.n[1] * cz);
+            const int rowc = P.cbase + P.n[0] * cell_row(P, cy, cz);
             const uint32_t tag_yz = ((uint32_t)(dy + 1) << 2) | ((uint32_t)(dz + 1) << 4);
             row(BodyTag<0>{}, rowc, tag_yz);
             if (P.nw > 0) row(BodyTag<1>{}, rowc, tag_yz);
@@ -1039,8 +1122,8 @@ __device__ __forceinline__ void adv_forces_body(
             Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const R4<real>& sj = r.s;
             const real rho_j = P.rho0 + (D == 2 ? sj.z : sj.w);
-            const real w = P.m * inv_rho_i / rho_j * q.dW;
-            const real cv = (real)2 * P.eta * w / q.r;
+            const real w = div_r(P.m * inv_rho_i, rho_j) * q.dW;
+            const real cv = div_r((real)2 * P.eta * w, q.r);
             const real ct = (real)2 * P.p0 * w;
             av[0] += cv * (vi[0] - sj.x);
             av[1] += cv * (vi[1] - sj.y);
@@ -1061,7 +1144,7 @@ __device__ __forceinline__ void adv_forces_body(
         [&](uint32_t e, const WallJ& r) {
             Pair<D, real> q = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const real w = P.vw * inv_rho_i * q.dW;
-            const real cv = (real)2 * P.eta * w / q.r;
+            const real cv = div_r((real)2 * P.eta * w, q.r);
             const real ct = (real)2 * P.p0 * w;
             real vw[3] = {0, 0, 0};
             if (mv) wall_velocity(r.k, Vw, omw, vw);
@@ -1198,7 +1281,7 @@ __device__ __forceinline__ void pressure_body(
             real du = UL - UR;
             real beta = dmin((real)3 * dmax(du, (real)0), P.c);
             real ps = (real)0.5 * (p_i + p_j) + (real)0.25 * beta * (rho_i + rho_j) * du;
-            real coef = P.two_m * ps * inv_rho_i / rho_j * pq.dW;
+            real coef = div_r(P.two_m * ps * inv_rho_i, rho_j) * pq.dW;
             acc[0] += coef * pq.e[0];
             acc[1] += coef * pq.e[1];
             if (D == 3) acc[2] += coef * pq.e[2];
@@ -1266,7 +1349,7 @@ __device__ __forceinline__ void pressure_body(
 }
 
 template <int D, typename real, int T, bool MOVE>
-__global__ __launch_bounds__(BLOCK) void k_pressure(
+__global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR void k_pressure(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
@@ -1334,6 +1417,17 @@ __device__ __forceinline__ void density_body(
         const real rho_i = P.rho0 + dev_i;
         const real p_i = P.c2 * dev_i;
         const G oi = geo[i];
+        // the particle's own state for the final half-steps, loaded ahead of
+        // the pair loop so that its latency hides behind it
+        R4<real> so = {};
+        double xo[3] = {0.0, 0.0, 0.0};
+        constexpr bool ahead = D == 2 || SPHX_PREFETCH_3D;
+        if (ahead && l == 0) {
+            so = st[i];
+            xo[0] = x0[i];
+            xo[1] = x1[i];
+            if (D == 3) xo[2] = x2[i];
+        }
         real sum = 0;
         struct HalfJ { G o; R4<real> h; };
         struct WallJ { G o; G n; R4<real> k; };
@@ -1354,9 +1448,9 @@ __device__ __forceinline__ void density_body(
                 real UR = hj.x * pq.e[0] + hj.y * pq.e[1] + (D == 3 ? hj.z * pq.e[2] : (real)0);
                 real rho_j = P.rho0 + dev_j;
                 real p_j = P.c2 * dev_j;
-                real inv_rho_j = (real)1 / rho_j;
+                real inv_rho_j = div_r((real)1, rho_j);
                 real rho_bar = (real)0.5 * (rho_i + rho_j);
-                real us = (real)0.5 * (UL + UR) + (p_i - p_j) * P.half_inv_c / rho_bar;
+                real us = (real)0.5 * (UL + UR) + div_r((p_i - p_j) * P.half_inv_c, rho_bar);
                 sum += P.m * inv_rho_j * (us - UL) * pq.dW;
             });
         for_pairs<T, BATCH>(
@@ -1377,7 +1471,7 @@ __device__ __forceinline__ void density_body(
                 real pR = p_i + rho_i * gr;
                 real rhoR = P.rho0 + pR * P.inv_c2;
                 real rho_bar = (real)0.5 * (rho_i + rhoR);
-                real us = (p_i - pR) * P.half_inv_c / rho_bar;  // + (U_L + U_R)/2 = u_w below
+                real us = div_r((p_i - pR) * P.half_inv_c, rho_bar);  // + (U_L + U_R)/2 = u_w below
                 if (mv) {
                     real vw[3];
                     wall_velocity(r.k, Vw, omw, vw);
@@ -1388,22 +1482,30 @@ __device__ __forceinline__ void density_body(
         sum = group_sum<T>(sum);
         if (l == 0) {
             const real drho = (real)2 * rho_i * sum;
-            const R4<real> so = st[i];
+            if (!ahead) {
+                so = st[i];
+                xo[0] = x0[i];
+                xo[1] = x1[i];
+                if (D == 3) xo[2] = x2[i];
+            }
             const double hd = 0.5 * dtd;
-            x0[i] = x0[i] + hd * (double)so.x;
-            x1[i] = x1[i] + hd * (double)so.y;
-            if (D == 3) x2[i] = x2[i] + hd * (double)so.z;
-            x0[i] = x0[i] + hd * (double)vi[0];
-            x1[i] = x1[i] + hd * (double)vi[1];
-            if (D == 3) x2[i] = x2[i] + hd * (double)vi[2];
+            xo[0] = xo[0] + hd * (double)so.x;
+            xo[1] = xo[1] + hd * (double)so.y;
+            if (D == 3) xo[2] = xo[2] + hd * (double)so.z;
+            xo[0] = xo[0] + hd * (double)vi[0];
+            xo[1] = xo[1] + hd * (double)vi[1];
+            if (D == 3) xo[2] = xo[2] + hd * (double)vi[2];
             if (avt && P.p0 != (real)0) {
                 // positions move with the transport velocity v + dt atv
                 const R4<real> a = avt[2 * (size_t)i + 1];
                 const double d2 = dtd * dtd;
-                x0[i] = x0[i] + d2 * (double)a.x;
-                x1[i] = x1[i] + d2 * (double)a.y;
-                if (D == 3) x2[i] = x2[i] + d2 * (double)a.z;
+                xo[0] = xo[0] + d2 * (double)a.x;
+                xo[1] = xo[1] + d2 * (double)a.y;
+                if (D == 3) xo[2] = xo[2] + d2 * (double)a.z;
             }
+            x0[i] = xo[0];
+            x1[i] = xo[1];
+            if (D == 3) x2[i] = xo[2];
             R4<real> sn;
             sn.x = vi[0];
             sn.y = vi[1];
@@ -1440,7 +1542,7 @@ __device__ __forceinline__ void density_body(
 }
 
 template <int D, typename real, int T, bool MOVE>
-__global__ __launch_bounds__(BLOCK) void k_density(
+__global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR void k_density(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int finalize,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
@@ -1464,18 +1566,16 @@ __global__ __launch_bounds__(BLOCK) void k_density(
         vslot_all, q, avt, wmot);
 }
 
-// S5 after the last queued density relaxation (one wavefront per case):
-// close sub-step q. If the advection step is covered (or was covered
-// earlier in the queue) prepare the next one; otherwise the step continues
-// at the head of the next queue, its next sub-step stored in slot 0.
-// Clears the case's |v| slots.
+// S5 after the last queued density relaxation, for case c, by one
+// wavefront: close sub-step q. If the advection step is covered (or was
+// covered earlier in the queue) prepare the next one; otherwise the step
+// continues at the head of the next queue, its next sub-step stored in
+// slot 0. Clears the case's |v| slots and folds the error bits the cell
+// binning raised into the sticky ones.
 template <typename real>
-__global__ __launch_bounds__(64) void k_step_end(const KP<real>* __restrict__ Pt, Ctrl* __restrict__ ctrl_all,
-                                                 unsigned long long* __restrict__ vslot_all, int q)
+__device__ void step_end(const KP<real>& P, Ctrl* __restrict__ ctrl, unsigned long long* __restrict__ vslot, int q)
 {
-    const KP<real>& P = Pt[blockIdx.x];
-    Ctrl* ctrl = ctrl_all + blockIdx.x;
-    unsigned long long* vslot = vslot_all + (size_t)blockIdx.x * 2 * VSLOTS;
+    const int lane = threadIdx.x & 63;
     const SubState Sp = ctrl->ss[q & 1];  // read by the whole wavefront before lane 0 writes
     const uint32_t err = ctrl->err;
     bool cont = false;
@@ -1484,17 +1584,180 @@ __global__ __launch_bounds__(64) void k_step_end(const KP<real>* __restrict__ Pt
         bool finished;
         SubState n = next_substep(P, ctrl->dt_ad, Sp, vmax, finished);
         cont = !finished;
-        if (threadIdx.x == 0) close_substep(ctrl, 0, n, vmax, finished);
+        if (lane == 0) close_substep(ctrl, 0, n, vmax, finished);
     }
-    vslot[threadIdx.x] = 0ull;
-    vslot[VSLOTS + threadIdx.x] = 0ull;
-    if (threadIdx.x != 0 || err || ctrl->err) return;
+    vslot[lane] = 0ull;
+    vslot[VSLOTS + lane] = 0ull;
+    if (lane != 0) return;
+    const uint32_t pend = ctrl->err_pending;
+    if (pend) {
+        ctrl->err_pending = 0u;
+        ctrl->err |= pend;
+    }
+    if (err || ctrl->err) return;
     if (cont) {
         ctrl->ss[1].active = 0;
         ctrl->midstep = 1;
     } else {
         prepare_step(P, ctrl);
     }
+}
+
+// Whether the configuration update at the end of a queue is a full one for
+// this case: requested, an advection step ended earlier in the queue, or the
+// last queued sub-step q (q >= 0) ends it. The same decision as step_end's,
+// taken from the same state by every wavefront (all 64 lanes active).
+template <typename real>
+__device__ __forceinline__ bool update_due(const KP<real>& P, const Ctrl* __restrict__ ctrl,
+                                           const unsigned long long* __restrict__ vslot, int force, int q)
+{
+    if (force || ctrl->rebuild) return true;
+    if (q < 0) return false;
+    const SubState Sp = ctrl->ss[q & 1];
+    if (!Sp.active || ctrl->err) return false;
+    const double vmax = slot_max<real>(vslot + (q & 1) * VSLOTS);
+    bool finished;
+    (void)next_substep(P, ctrl->dt_ad, Sp, vmax, finished);
+    return finished;
+}
+
+// Single-pass exclusive scan of the cell counts (decoupled look-back), for
+// grids of at most LB_MAX_BLOCKS tiles, where every block finds all its
+// predecessors in one window (no chain of waits): each
+// block takes a ticket (its tile, in the order blocks start), reduces its
+// tile, publishes the aggregate, then adds the aggregates and prefixes of
+// the tiles before it as they appear and publishes its own inclusive prefix.
+// A block only waits for tiles with smaller tickets, whose blocks are
+// already running, so every wait ends; a bounded spin records a fault in
+// *fault instead of waiting for ever. Status words carry an epoch, so no
+// clearing is needed between scans: the last ticket's block advances the
+// epoch and resets the ticket counter. The counts are consumed (zeroed).
+// With q >= 0 the blocks also run step_end for every case (cases spread
+// over the wavefronts of the grid).
+constexpr uint32_t LB_AGG = 1u, LB_PREFIX = 2u;
+constexpr int LB_SPIN_CAP = 1 << 22;
+constexpr int LB_ITEMS = 8;                   // consecutive counts per thread
+constexpr int LB_TILE = BLOCK * LB_ITEMS;     // counts per block
+constexpr int LB_MAX_BLOCKS = 64;             // grids up to one look-back window use the single pass
+
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_scan_lb(int32_t* __restrict__ cnt, int32_t* __restrict__ start, int n,
+                                                   unsigned long long* __restrict__ status, int32_t* __restrict__ ticket,
+                                                   uint32_t* __restrict__ epoch, int32_t* __restrict__ fault,
+                                                   const KP<real>* __restrict__ Pt, Ctrl* __restrict__ ctrl_all,
+                                                   unsigned long long* __restrict__ vslot_all, int q, int ncase)
+{
+    __shared__ int sh[BLOCK];
+    __shared__ int s_ticket, s_excl;
+    __shared__ uint32_t s_epoch;
+    if (threadIdx.x == 0) {
+        s_epoch = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_ticket = atomicAdd(ticket, 1);
+    }
+    __syncthreads();
+    const int b = s_ticket;
+    const uint32_t ep = s_epoch;
+    const int nb = gridDim.x;
+    const int base = b * LB_TILE + threadIdx.x * LB_ITEMS;
+    int v[LB_ITEMS];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+        v[k] = base + k < n ? cnt[base + k] : 0;
+        sum += v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k)
+        if (base + k < n) cnt[base + k] = 0;
+    int total;
+    int ex = block_excl_scan(sum, sh, total);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const unsigned long long tag_agg = (unsigned long long)((ep << 2) | LB_AGG) << 32;
+        const unsigned long long tag_pre = (unsigned long long)((ep << 2) | LB_PREFIX) << 32;
+        int excl = 0;
+        if (b > 0) {
+            if (lane == 0)
+                __hip_atomic_store(&status[b], tag_agg | (uint32_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // windows of 64 predecessors, nearest first, until one has a prefix
+            for (int j = b - 1; j >= 0; j -= 64) {
+                const int k = j - lane;
+                unsigned long long w = 0ull;
+                bool pre = false;
+                int val = 0;
+                if (k >= 0) {
+                    for (int it = 0;; ++it) {
+                        w = __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned long long tag = w & 0xffffffff00000000ull;
+                        if (tag == tag_agg || tag == tag_pre) break;
+                        if (it >= LB_SPIN_CAP) {
+                            atomicOr(fault, 1);
+                            w = tag_pre;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    pre = (w & 0xffffffff00000000ull) == tag_pre;
+                    val = (int)(uint32_t)w;
+                }
+                const unsigned long long pm = __ballot(pre);
+                const int stop = pm ? __ffsll((long long)pm) - 1 : 64;
+                int c = (k >= 0 && lane <= stop) ? val : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+                excl += c;
+                if (pm) break;
+            }
+        }
+        if (lane == 0) {
+            __hip_atomic_store(&status[b], tag_pre | (uint32_t)(excl + total), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = excl;
+        }
+    }
+    __syncthreads();
+    ex += s_excl;
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+        if (base + k < n) start[base + k] = ex;
+        ex += v[k];
+    }
+    if (b == nb - 1 && threadIdx.x == 0) {
+        start[n] = s_excl + total;
+        __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(epoch, ep == 0x3fffffffu ? 1u : ep + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (q < 0) return;
+    const int waves = BLOCK / 64, wid = threadIdx.x / 64;
+    for (int c = b * waves + wid; c < ncase; c += nb * waves)
+        step_end(Pt[c], ctrl_all + c, vslot_all + (size_t)c * 2 * VSLOTS, q);
+}
+
+// Second pass of the two-pass scan used for larger grids (after
+// k_scan_tiles): each block adds the sum of the tile sums before it (read
+// directly, no scan of the sums) to its tile; the last block writes the
+// total. With q >= 0 the blocks also run step_end for every case.
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_scan_fin(int32_t* __restrict__ start, const int32_t* __restrict__ bsum,
+                                                    int n, const KP<real>* __restrict__ Pt,
+                                                    Ctrl* __restrict__ ctrl_all,
+                                                    unsigned long long* __restrict__ vslot_all, int q, int ncase)
+{
+    __shared__ int sh[BLOCK];
+    const int b = blockIdx.x, nb = gridDim.x;
+    int s = 0;
+    for (int k = threadIdx.x; k < b; k += BLOCK) s += bsum[k];
+    int before;
+    (void)block_excl_scan(s, sh, before);
+    const int base = b * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) start[base + k] += before;
+    if (b == nb - 1 && threadIdx.x == 0) start[n] = before + bsum[b];
+    if (q < 0) return;
+    const int waves = BLOCK / 64, wid = threadIdx.x / 64;
+    for (int c = b * waves + wid; c < ncase; c += nb * waves)
+        step_end(Pt[c], ctrl_all + c, vslot_all + (size_t)c * 2 * VSLOTS, q);
 }
 
 // ---------------------------------------------------------------------

@@ -140,6 +140,10 @@ struct Engine final : EngineBase {
     int32_t* wcnt = nullptr;
     int32_t *key = nullptr, *rank = nullptr, *perm = nullptr;
     int32_t *cnt = nullptr, *fstart = nullptr, *bsum = nullptr;
+    // single-pass scan: per-tile status words, ticket counter, epoch, fault flag
+    unsigned long long* lb_status = nullptr;
+    int32_t *lb_ticket = nullptr, *lb_fault = nullptr;
+    uint32_t* lb_epoch = nullptr;
     real* acc_out = nullptr;
     real* drho_out = nullptr;
     double* outbuf = nullptr;
@@ -190,6 +194,8 @@ struct Engine final : EngineBase {
         free_list(gn.fixed);
         free_list(gn.nodes);
         free_list(gn.edges);
+        for (void* p : {(void*)lb_status, (void*)lb_ticket, (void*)lb_fault, (void*)lb_epoch})
+            if (p) (void)hipFree(p);
         for (void* p : {(void*)ctrl, (void*)cnt, (void*)fstart, (void*)bsum, (void*)wstart, (void*)diag_out,
                         (void*)dP, (void*)vslot, (void*)stage})
             (void)hipFree(p);
@@ -285,6 +291,9 @@ struct Engine final : EngineBase {
         }
         if (nc > 50000000LL || (long long)cbase + nc + 1 > 200000000LL)
             return ctx->fail(SPHX_EINVAL, case_tag(c) + "cell grid too large");
+        // cell order: bands of 8 rows along y in 3D (a band's z-neighbour
+        // rows then lie 8 x-rows apart), plain row-major in 2D
+        P.band = (D == 3 && P.n[1] > 8) ? 8 : P.n[1];
         P.rc2 = (2.0 * h) * (2.0 * h);
         if (q.sigma0 > 0) {
             P.sigma0 = q.sigma0;
@@ -350,6 +359,18 @@ struct Engine final : EngineBase {
         HIPCHK(hipMalloc((void**)&fstart, sizeof(int32_t) * ((size_t)ncell + 1)));
         HIPCHK(hipMalloc((void**)&wstart, sizeof(int32_t) * ((size_t)ncell + 1)));
         HIPCHK(hipMalloc((void**)&bsum, sizeof(int32_t) * ((size_t)nblk_scan() + 1)));
+        HIPCHK(hipMalloc((void**)&lb_status, sizeof(unsigned long long) * (size_t)nblk_lb()));
+        HIPCHK(hipMalloc((void**)&lb_ticket, sizeof(int32_t)));
+        HIPCHK(hipMalloc((void**)&lb_fault, sizeof(int32_t)));
+        HIPCHK(hipMalloc((void**)&lb_epoch, sizeof(uint32_t)));
+        HIPCHK(hipMemsetAsync(lb_status, 0, sizeof(unsigned long long) * (size_t)nblk_lb(), s));
+        HIPCHK(hipMemsetAsync(lb_ticket, 0, sizeof(int32_t), s));
+        HIPCHK(hipMemsetAsync(lb_fault, 0, sizeof(int32_t), s));
+        {
+            const uint32_t one = 1u;  // status words of epoch 0 (zeroed) read as empty
+            HIPCHK(hipMemcpyAsync(lb_epoch, &one, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
         HIPCHK(hipMalloc((void**)&diag_out, sizeof(double) * NDIAG * C));
         HIPCHK(hipMemsetAsync(wstart, 0, sizeof(int32_t) * ((size_t)ncell + 1), s));
         HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));
@@ -359,6 +380,7 @@ struct Engine final : EngineBase {
     }
 
     int nblk_scan() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
+    int nblk_lb() const { return (ncell + LB_TILE - 1) / LB_TILE; }
     int pair_blocks() const { return (int)((long long)ntot * ln / BLOCK); }
 
     // Whether any case has a shear force or a transport-velocity correction.
@@ -405,8 +427,11 @@ struct Engine final : EngineBase {
 
     int sync_ctrl()
     {
+        int32_t fault = 0;
         HIPCHK(hipMemcpyAsync(hctrl, ctrl, sizeof(Ctrl) * C, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&fault, lb_fault, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (fault) return ctx->fail(SPHX_EHIP, "cell-count scan: look-back wait exceeded its bound");
         bool fold = false;
         for (int c = 0; c < C; ++c)
             if (hctrl[c].err_pending) {  // raised outside a sub-step queue (rates, profiling)
@@ -796,12 +821,18 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
-    int enqueue_scan(int32_t* out)
+    // Exclusive scan of the cell counts into out[0..ncell]; with q >= 0 the
+    // same launch closes the queue's last sub-step q of every case.
+    int enqueue_scan(int32_t* out, int q = -1)
     {
-        int nb = nblk_scan();
-        k_scan_tiles<<<nb, BLOCK, 0, s>>>(cnt, out, bsum, ncell);
-        k_scan_top<<<1, BLOCK, 0, s>>>(bsum, nb);
-        k_scan_add<<<nb, BLOCK, 0, s>>>(out, bsum, ncell, nb);
+        if (nblk_lb() <= LB_MAX_BLOCKS) {
+            k_scan_lb<real><<<nblk_lb(), BLOCK, 0, s>>>(cnt, out, ncell, lb_status, lb_ticket, lb_epoch, lb_fault,
+                                                         dP, ctrl, vslot, q, C);
+        } else {
+            const int nb = nblk_scan();
+            k_scan_tiles<<<nb, BLOCK, 0, s>>>(cnt, out, bsum, ncell);
+            k_scan_fin<real><<<nb, BLOCK, 0, s>>>(out, bsum, ncell, dP, ctrl, vslot, q, C);
+        }
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -818,15 +849,17 @@ struct Engine final : EngineBase {
                                                                 wgeo, nbr, ncnt, wnb, wcnt);
     }
 
-    int enqueue_rebuild(int force, int a)
+    // `q` >= 0: at the end of a queue whose last sub-step is q (the scan
+    // closes it, the binning decides the full updates from the same state).
+    int enqueue_rebuild(int force, int a, int q = -1)
     {
         ++conf_gen;
         int b = 1 - a;
         const int nb = nblk(ntot);
-        if (any_move()) RETCHK(enqueue_wall_sort());  // walls in their pose at each case's clock
         k_bin<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, x[a][0], x[a][1], x[a][2], cell[a], key,
-                                            rank, cnt);
-        RETCHK(enqueue_scan(fstart));
+                                            rank, cnt, vslot, q);
+        RETCHK(enqueue_scan(fstart, q));
+        if (any_move()) RETCHK(enqueue_wall_sort());  // walls in their pose at each case's (closed) clock
         k_scatter<real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ntot, key, rank, fstart, perm);
         k_place_fluid<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, ntot, perm, key, fstart, x[a][0],
                                                      x[a][1], x[a][2], st[a], dr3[a], id[a], geo[a], x[b][0], x[b][1],
@@ -896,9 +929,7 @@ struct Engine final : EngineBase {
         RETCHK(enqueue_reinit(1, a));
         RETCHK(enqueue_adv_forces(1, a));
         for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr));
-        k_step_end<real><<<C, 64, 0, s>>>(dP, ctrl, vslot, nsub_q - 1);
-        HIPCHK(hipGetLastError());
-        RETCHK(enqueue_rebuild(0, a));
+        RETCHK(enqueue_rebuild(0, a, nsub_q - 1));
         return SPHX_OK;
     }
 
