@@ -375,6 +375,21 @@ __device__ __forceinline__ void wall_velocity(const R4<real>& k, const real V[3]
     v[2] = k.z * V[2];
 }
 
+// Density re-initialisation of one particle from its kernel sum sigma (self
+// included): rho = max(rho*, rho0 sigma / sigma0) for free-surface flow,
+// rho0 sigma / sigma0 without free surface; st holds rho - rho0.
+template <int D, typename real>
+__device__ __forceinline__ void reinit_density(const KP<real>& P, double sigma, R4<real>* __restrict__ sp)
+{
+    const real dev_sum = (real)(P.rho0d * (sigma / P.sigma0 - 1.0));
+    R4<real> s = *sp;
+    if (D == 2) {
+        if (P.reinit_mode || dev_sum > s.z) { s.z = dev_sum; *sp = s; }
+    } else {
+        if (P.reinit_mode || dev_sum > s.w) { s.w = dev_sum; *sp = s; }
+    }
+}
+
 template <typename real>
 __device__ __forceinline__ real kernel_W(const KP<real>& P, real r)
 {
@@ -743,6 +758,13 @@ template <int B> struct BodyTag { static constexpr int value = B; };
 // margin 8e-6 L^2 only candidates in a thin shell around 2h need the FP64
 // test, and the list is bit-exact. Cases without a full update keep their
 // lists (their order did not change).
+//
+// In 2D, with `reinit` (the update at the end of a queue), a case whose
+// next advection step has been prepared also gets that step's density
+// re-initialisation (Eq. eqrhosum / eqrhosumnosurface) here, saving a
+// launch: the kernel sum over the accepted neighbours is taken while they
+// are found, from the frozen offsets. (In 3D the extra registers cost the
+// candidate scan more than the separate pass over the lists.)
 template <int D, typename real, int T, int TB>
 __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int force,
@@ -751,7 +773,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const typename GeoSel<D, real>::T* __restrict__ geo, const double* __restrict__ wx0,
     const double* __restrict__ wx1, const double* __restrict__ wx2, const int32_t* __restrict__ wstart,
     const typename GeoSel<D, real>::T* __restrict__ wgeo, uint32_t* __restrict__ nbr, int32_t* __restrict__ ncnt,
-    uint32_t* __restrict__ wnb, int32_t* __restrict__ wcnt)
+    uint32_t* __restrict__ wnb, int32_t* __restrict__ wcnt, int reinit, R4<real>* __restrict__ st)
 {
     static_assert(64 % TB == 0, "lane groups must tile a wavefront");
     using G = typename GeoSel<D, real>::T;
@@ -760,6 +782,8 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const KP<real> P = Pt[tcase[b]];  // a copy: the fields stay in registers through the loops
     Ctrl* ctrl = ctrl_all + P.case_id;
     if (!full_update(ctrl, force) || ctrl->err) return;
+    const bool do_reinit = D == 2 && reinit && ctrl->ss[0].active && !ctrl->midstep;
+    double sigma = 0.0;
     const int i = b * TILE + (int)threadIdx.x / TB;
     const int l = threadIdx.x % TB;
     const int fend = P.fbase + P.nf, wend = P.wbase + P.nw;
@@ -782,7 +806,8 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     // compile-time constant so that every choice below is static); cell
     // offset in x from the range boundaries b1, b2 (first candidate of the
     // 2nd and 3rd cell).
-    auto scan = [&](auto bodyc, int j0, int j1, int b1, int b2, int dcx0, uint32_t tag_yz) {
+    auto scan = [&](auto bodyc, int j0, int j1, int b1, int b2, int dcx0, uint32_t tag_yz)
+                    __attribute__((always_inline)) {
         constexpr int BODY = decltype(bodyc)::value;
         const G* csrc = BODY ? wgeo : geo;
         const double* bx0 = BODY ? wx0 : x0;
@@ -815,6 +840,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
                 const int j = jb + u * TB + l;
                 const int dcx = dcx0 + (j >= b1) + (j >= b2);
                 bool in = false;
+                float r2w = 0.f;  // FP32 squared distance from the frozen offsets (prefilter)
                 if (j < j1 && (BODY || j != i)) {
                     if constexpr (PREFILTER) {
                         float dx = (float)((oi.x - oj[u].x) - (real)dcx * P.L[0]);
@@ -824,6 +850,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
                             float dz = (float)((oi.z - zc(oj[u])) - (real)((int)((tag_yz >> 4) & 3u) - 1) * P.L[2]);
                             r2 += dz * dz;
                         }
+                        r2w = r2;
                         if (r2 < rc2f - margin) {
                             in = true;
                         } else if (r2 > rc2f + margin) {
@@ -842,6 +869,14 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
                     uint32_t code = (uint32_t)(dcx + 1) | tag_yz;
                     if (slot < mx) out[ell_at<T>(i, slot, mx)] = (uint32_t)j | (code << NBR_SHIFT);
                     else over = 1;
+                    if (do_reinit) {
+                        if constexpr (PREFILTER) {
+                            sigma += (double)kernel_W(P, (real)(r2w * rsqrt_r(r2w)));
+                        } else {
+                            const G ojv = csrc[j];
+                            sigma += (double)kernel_W(P, pair_geo<D, real>(P, oi, ojv, code).r);
+                        }
+                    }
                 }
                 nn += __popcll(m);
             }
@@ -849,7 +884,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     };
 
     // One stencil row (three x-adjacent cells) of one body.
-    auto row = [&](auto bodyc, int rowc, uint32_t tag_yz) {
+    auto row = [&](auto bodyc, int rowc, uint32_t tag_yz) __attribute__((always_inline)) {
         constexpr int BODY = decltype(bodyc)::value;
         const int32_t* st_ = BODY ? wstart : fstart;
         const int lim = BODY ? wend : fend;
@@ -891,6 +926,10 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
         wcnt[i] = cnt_w < P.maxw ? cnt_w : P.maxw;
     }
     if (over) atomicOr(&ctrl->err, ERR_NBR_OVERFLOW);
+    if (do_reinit) {
+        sigma = group_sum<TB>(sigma) + (double)P.Wc;  // + W(0), the particle itself
+        if (l == 0) reinit_density<D>(P, sigma, st + i);
+    }
 }
 
 // ---------------------------------------------------------------------
@@ -1064,13 +1103,7 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
     for_pairs<T, BATCH>(wnb, i, wcnt[i], P.maxw, l, [&](uint32_t e) { return wgeo[e & NBR_MASK]; }, add_w);
     sigma = group_sum<T>(sigma) + (double)P.Wc;  // + W(0), the particle itself
     if (l != 0) return;
-    real dev_sum = (real)(P.rho0d * (sigma / P.sigma0 - 1.0));
-    R4<real> s = st[i];
-    if (D == 2) {
-        if (P.reinit_mode || dev_sum > s.z) { s.z = dev_sum; st[i] = s; }
-    } else {
-        if (P.reinit_mode || dev_sum > s.w) { s.w = dev_sum; st[i] = s; }
-    }
+    reinit_density<D>(P, sigma, st + i);
 }
 
 // Shear force, Eq. (eqviscous), and transport-velocity acceleration,

@@ -842,11 +842,11 @@ struct Engine final : EngineBase {
     // zero on entry (zeroed at allocation and by every scan that consumes
     // them).
     template <int T>
-    void launch_neighbors(int force, int b)
+    void launch_neighbors(int force, int b, int reinit = 0)
     {
         k_neighbors<D, real, T, LB><<<ntiles, TILE * LB, 0, s>>>(dP, tcase, ctrl, force, x[b][0], x[b][1], x[b][2],
                                                                 cell[b], fstart, geo[b], wx[0], wx[1], wx[2], wstart,
-                                                                wgeo, nbr, ncnt, wnb, wcnt);
+                                                                wgeo, nbr, ncnt, wnb, wcnt, reinit, st[b]);
     }
 
     // `q` >= 0: at the end of a queue whose last sub-step is q (the scan
@@ -864,7 +864,8 @@ struct Engine final : EngineBase {
         k_place_fluid<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, ntot, perm, key, fstart, x[a][0],
                                                      x[a][1], x[a][2], st[a], dr3[a], id[a], geo[a], x[b][0], x[b][1],
                                                      x[b][2], st[b], dr3[b], id[b], cell[b], geo[b]);
-        by_lanes([&](auto t) { launch_neighbors<decltype(t)::value>(force, b); });
+        // at the end of a queue the next step's density re-initialisation rides along
+        by_lanes([&](auto t) { launch_neighbors<decltype(t)::value>(force, b, q >= 0 ? 1 : 0); });
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -924,9 +925,13 @@ struct Engine final : EngineBase {
     // One queue on set a (graph body): re-initialisation for the cases
     // starting a step, the queued sub-steps, the step end (which prepares the
     // next step or marks a continuation), the configuration update.
+    // One queue: the density re-initialisation (in 2D it came with the
+    // configuration update that ended the previous queue, or with advance's
+    // prologue) and the advection-step forces of the cases starting a step,
+    // the sub-steps, the configuration update.
     int enqueue_step(int a)
     {
-        RETCHK(enqueue_reinit(1, a));
+        if (D == 3) RETCHK(enqueue_reinit(1, a));
         RETCHK(enqueue_adv_forces(1, a));
         for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr));
         RETCHK(enqueue_rebuild(0, a, nsub_q - 1));
@@ -1156,6 +1161,15 @@ struct Engine final : EngineBase {
         RETCHK(push_ctrl());
         k_adv_begin<real><<<(C + 63) / 64, 64, 0, s>>>(dP, ctrl, C);
         HIPCHK(hipGetLastError());
+        // 2D: the first step's density re-initialisation, by the same kernel
+        // (and so the same arithmetic) that re-initialises the later steps at
+        // the end of each queue: the lists are rebuilt unchanged from the
+        // current configuration, so how a run is split into calls changes no
+        // bit (3D re-initialises at the head of every queue)
+        if (D == 2) {
+            by_lanes([&](auto t) { launch_neighbors<decltype(t)::value>(1, cur, 1); });
+            HIPCHK(hipGetLastError());
+        }
         RETCHK(sync_ctrl());
         // queues in batches of at most 64, one host synchronisation per batch
         for (long long need = queues_needed(); need > 0; need = queues_needed()) {
