@@ -47,7 +47,7 @@ MUTATIONS = [
      "double acc[3] = {s->av[3 * i], s->av[3 * i + 1], s->av[3 * i + 2]};", None),
     ("viscous_sign", "av[k] += cv * (vi[k] - vj[k]);", "av[k] += cv * (vj[k] - vi[k]);", None),
     ("viscous_factor_two", "double cv = 2.0 * m * eta", "double cv = m * eta", None),
-    ("viscous_wall_dropped", "av[k] += cv * vi[k];", "av[k] += 0.0 * cv * vi[k];", None),
+    ("viscous_wall_dropped", "av[k] += cv * (vi[k] - vw[k]);", "av[k] += 0.0 * cv * (vi[k] - vw[k]);", None),
     ("viscous_not_applied", "s->p.g[0] + s->av[3 * i],", "s->p.g[0],", None),
     ("viscous_time_step_missing", "if (s->p.eta > 0.0) *dt_ad", "if (0) *dt_ad", None),
     ("transport_sign", "s->x[3 * i + k] += dt * dt * s->atv[3 * i + k];", "s->x[3 * i + k] -= dt * dt * s->atv[3 * i + k];", None),
