@@ -244,6 +244,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick the pair-kernel lanes per particle first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads for cpu_baseline (0: all)")
     ap.add_argument("--profile-reps", type=int, default=50)
     ap.add_argument("--no-torch", action="store_true", help="let the library create its own stream")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -394,6 +395,9 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
+        if args.cpu_threads > 0:
+            import oracle as O
+            O.set_num_threads(args.cpu_threads)
         out["cpu_baseline"] = (cpu_baseline(case, args.cpu_budget) if cases is None
                                else cpu_baseline_ensemble(cases, args.cpu_budget))
     sim.close()

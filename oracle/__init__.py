@@ -97,6 +97,8 @@ def lib():
         L.orc_diagnostics.argtypes = [vp, vp]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -134,6 +136,10 @@ def riemann(rhoL, UL, PL, rhoR, UR, PR, c):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 def params_from_case(case, sigma0=0.0):

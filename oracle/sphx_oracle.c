@@ -1022,3 +1022,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the parallel-for loops (results do not depend on it). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
