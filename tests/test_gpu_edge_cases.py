@@ -1,0 +1,159 @@
+"""Edge cases of the hot path on the GPU against the FP64 oracle, through
+the C ABI: particle counts around the 64-slot tile (1, 63, 64, 65, 129),
+a tight cluster in one cell, the neighbour-list capacity reached exactly and
+exceeded by one, positions on the domain boundary, and empty inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2010_12375_amd import sphx
+from paper_2010_12375_amd import workloads as wl
+from parity import developed_state, make_pair, rate_errors
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = sphx.SPHX_FP64, sphx.SPHX_FP32
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def case_from(pos, dp=0.1, lo=(-1.0, -1.0, 0.0), hi=(1.0, 1.0, 0.0), walls=None, periodic=(0, 0, 0)):
+    dim = pos.shape[1]
+    if walls is None:
+        wpos, wn = np.zeros((0, dim)), np.zeros((0, dim))
+    else:
+        wpos, wn = walls
+    return wl.Case(name="edge", dim=dim, dp=dp, h=1.3 * dp, rho0=1.0, c0=10.0, u_ref=1.0, cfl_ad=0.25, cfl_ac=0.6,
+                   gravity=(0.0, -1.0, 0.0), lo=lo, hi=hi, periodic=periodic, fluid_pos=pos, wall_pos=wpos,
+                   wall_normal=wn, column=(1.0, 1.0))
+
+
+def lists_equal(g, o):
+    for kind in (sphx.SPHX_INNER, sphx.SPHX_CONTACT):
+        og, ig = g.get_neighbors(kind)
+        oo, io = o.neighbors(kind)
+        if not (np.array_equal(og, oo) and np.array_equal(ig, io)):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 129])
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-9), (FP32, 1e-4)])
+def test_ragged_particle_counts(n, precision, tol):
+    """Counts below, at and above the 64-slot tile (the last tile of a case
+    partly filled, its unused slots in the padding cell)."""
+    rng = np.random.Generator(np.random.PCG64(100 + n))
+    lat = wl._lattice((12, 11), 0.1) + np.array([-0.6, -0.4])  # first n sites of a jittered block
+    pos = lat[:n] + rng.uniform(-0.001, 0.001, size=(n, 2))
+    wpos = np.column_stack([np.linspace(-0.8, 0.8, 17), np.full(17, -0.45)])
+    wn = np.tile([0.0, 1.0], (17, 1))
+    case = case_from(pos, walls=(wpos, wn))
+    st = developed_state(case, seed=n, speed=0.2)
+    g, o = make_pair(case, precision, st)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o)
+    dt = o.time_steps()[1]
+    ag, dg = g.compute_rates(dt)
+    ao, do = o.compute_rates(dt)
+    ea, ed = rate_errors(ag, ao, dg, do, gmag=1.0)
+    assert ea.max() <= tol and ed.max() <= tol
+    # a few whole steps: the clock and the sub-step count agree
+    ng = g.advance(3)
+    no = sum(o.advance(1e9) for _ in range(3))
+    if precision == FP64:
+        assert ng == no and g.t == pytest.approx(o.t, abs=1e-12)
+    else:  # dt from an FP32 |v|max
+        assert g.t == pytest.approx(o.t, rel=1e-5)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_tight_cluster_in_one_cell(precision):
+    """40 particles within a disc of radius 0.6h (one cell, every pair a
+    neighbour), next to a lattice block."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    dp = 0.1
+    r = 0.6 * 1.3 * dp * np.sqrt(rng.uniform(0, 1, 40))
+    a = rng.uniform(0, 2 * np.pi, 40)
+    cluster = np.column_stack([0.05 + r * np.cos(a), 0.05 + r * np.sin(a)])
+    block = wl._lattice((6, 6), dp) + np.array([0.3, -0.3])
+    pos = np.concatenate([cluster, block])
+    case = case_from(pos)
+    g, o = make_pair(case, precision)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o)
+    off, _ = o.neighbors(0)
+    assert (np.diff(off)[:40] >= 39).all()
+    dt = o.time_steps()[1]
+    ag, dg = g.compute_rates(dt)
+    ao, do = o.compute_rates(dt)
+    ea, ed = rate_errors(ag, ao, dg, do, gmag=1.0)
+    assert ea.max() <= (1e-9 if precision == FP64 else 1e-4) and ed.max() <= (1e-9 if precision == FP64 else 1e-4)
+
+
+def _ring(m):
+    """A particle at the centre of a ring of m particles at radius 1.5h: the
+    centre has exactly m neighbours, every ring particle fewer."""
+    dp = 0.1
+    h = 1.3 * dp
+    a = 2 * np.pi * (np.arange(m) + 0.25) / m
+    ring = np.column_stack([1.5 * h * np.cos(a), 1.5 * h * np.sin(a)])
+    return case_from(np.concatenate([[[0.0, 0.0]], ring]), dp=dp)
+
+
+def test_list_capacity_reached_exactly_then_exceeded():
+    """The 2D inner-list capacity is 48 entries: 48 neighbours build exact
+    lists, 49 report an overflow."""
+    case = _ring(48)
+    g, o = make_pair(case, FP64)
+    g.build_neighbors()
+    o.build_config()
+    off, _ = o.neighbors(0)
+    assert off[1] - off[0] == 48 and np.diff(off).max() == 48
+    assert lists_equal(g, o)
+    case = _ring(49)
+    g2 = sphx.Simulation.from_case(case, FP64)
+    with pytest.raises(sphx.SphxError) as e:
+        g2.build_neighbors()
+    assert e.value.code == sphx.SPHX_EOVERFLOW
+
+
+def test_positions_on_the_domain_boundary():
+    """A particle exactly on the lower box face is inside (the box is
+    half-open); one exactly on the upper face has escaped."""
+    pos = np.array([[-1.0, 0.0], [0.0, -1.0], [0.1, 0.1]])
+    g, o = make_pair(case_from(pos), FP64)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o)
+    pos2 = np.array([[1.0, 0.0], [0.1, 0.1]])
+    g2 = sphx.Simulation.from_case(case_from(pos2), FP64)
+    with pytest.raises(sphx.SphxError) as e:
+        g2.build_neighbors()
+    assert e.value.code == sphx.SPHX_EESCAPE
+
+
+def test_empty_fluid_and_empty_walls():
+    case = case_from(np.zeros((0, 2)))
+    g = sphx.Simulation(sphx.params_from_case(case, FP64))
+    g.set_fluid(np.zeros((0, 2)))
+    with pytest.raises(sphx.SphxError) as e:
+        g.build_neighbors()
+    assert e.value.code == sphx.SPHX_ESTATE
+    with pytest.raises(sphx.SphxError) as e:
+        g.advance(1)
+    assert e.value.code == sphx.SPHX_ESTATE
+    # no walls at all: the contact lists are empty
+    g.set_fluid(np.array([[0.0, 0.0], [0.05, 0.0]]))
+    g.set_walls(np.zeros((0, 2)), np.zeros((0, 2)))
+    g.build_neighbors()
+    off, idx = g.get_neighbors(sphx.SPHX_CONTACT)
+    assert off.tolist() == [0, 0, 0] and idx.size == 0
+    off, idx = g.get_neighbors(sphx.SPHX_INNER)
+    assert off.tolist() == [0, 1, 2] and idx.tolist() == [1, 0]
