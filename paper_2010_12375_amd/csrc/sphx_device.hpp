@@ -1574,8 +1574,11 @@ __device__ __forceinline__ void density_body(
     }
 }
 
+// (2D static: at most 64 VGPRs, eight wavefronts per SIMD; the kernel is
+// latency-bound and the extra wavefront per SIMD pays)
 template <int D, typename real, int T, bool MOVE>
-__global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR void k_density(
+__global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR
+__attribute__((amdgpu_waves_per_eu((D == 2 && !MOVE) ? 8 : 1))) void k_density(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int finalize,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
