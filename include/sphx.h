@@ -184,6 +184,32 @@ int sphx_set_wall_motion(sphx_ctx* ctx, const sphx_wall_motion* motion, const in
 /* The same for case c. */
 int sphx_set_wall_motion_case(sphx_ctx* ctx, int32_t c, const sphx_wall_motion* motion, const int32_t* moving);
 
+/* Fluid particles from device memory of the context's device (for example
+ * the storage of framework tensors; the caller keeps ownership and may free
+ * the buffers when the call returns): the same arrays and meaning as
+ * sphx_set_fluid_case, FP64, in original particle order. Before the batch's
+ * first device layout the arrays are staged through the host. */
+int sphx_set_fluid_device(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* vel,
+                          const double* rho, const double* drho);
+
+/* Field `field` of case c, as sphx_get_field_case, written to device memory
+ * `out` of the context's device (FP64, original particle order, n*dim or n
+ * values). Returns when the copy is complete. */
+int sphx_get_field_device(sphx_ctx* ctx, int32_t c, int field, double* out);
+
+/* Checkpoint (the survey's save and load of a run): sphx_save writes the
+ * parameters of every case, its walls and wall motion, its clock and time
+ * step state, and its particle state in the library's current slot order
+ * to `path`; sphx_load restores such a file into a context created with the
+ * same parameters (same number of cases, dimension, precision and every
+ * sphx_params field except nsub_queue; SPHX_EINVAL otherwise or for a
+ * truncated or foreign file). The neighbour configuration is rebuilt on the
+ * next call that needs it; from the restored state the run continues bit for
+ * bit as the saved context would have. The surrogate's parameters are not
+ * part of a checkpoint. */
+int sphx_save(sphx_ctx* ctx, const char* path);
+int sphx_load(sphx_ctx* ctx, const char* path);
+
 /* Configuration update (Section 2.4: at the advection frequency): wrap
  * periodic coordinates, bin particles into cells of size >= 2h, rebuild the
  * inner and contact neighbour lists with the FP64 predicate r^2 < (2h)^2

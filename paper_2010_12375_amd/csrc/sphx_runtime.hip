@@ -58,6 +58,11 @@ struct EngineBase {
                           const double* drho) = 0;
     virtual int set_walls(int c, int64_t n, const double* pos, const double* nrm) = 0;
     virtual int set_wall_motion(int c, const sphx_wall_motion* m, const int32_t* moving) = 0;
+    virtual int save(const char* path) = 0;
+    virtual int load(const char* path) = 0;
+    virtual int set_fluid_device(int c, int64_t n, const double* pos, const double* vel, const double* rho,
+                                 const double* drho) = 0;
+    virtual int get_field_device(int c, int which, double* out) = 0;
     virtual int build_neighbors() = 0;
     virtual int get_neighbors(int c, int kind, int64_t* off, int64_t* idx, int64_t cap, int64_t* n_out) = 0;
     virtual int density_reinit() = 0;
@@ -602,8 +607,37 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
+    // Fluid from device memory (the context's device): staged on the host
+    // before the first device layout, copied device to device afterwards.
+    int set_fluid_device(int c, int64_t n, const double* pos, const double* vel, const double* rho,
+                         const double* drho) override
+    {
+        RETCHK(check_case(c));
+        if (n < 0 || (n > 0 && !pos)) return ctx->fail(SPHX_EINVAL, "bad fluid particle count or positions");
+        if (!laid_out || round_tile(n) > hP[c].fcap) {
+            const size_t nn = (size_t)n;
+            std::vector<double> hp(nn * D), hv(vel ? nn * D : 0), hr(rho ? nn : 0), hd(drho ? nn : 0);
+            HIPCHK(hipStreamSynchronize(s));
+            if (n > 0) {
+                HIPCHK(hipMemcpy(hp.data(), pos, nn * D * sizeof(double), hipMemcpyDeviceToHost));
+                if (vel) HIPCHK(hipMemcpy(hv.data(), vel, nn * D * sizeof(double), hipMemcpyDeviceToHost));
+                if (rho) HIPCHK(hipMemcpy(hr.data(), rho, nn * sizeof(double), hipMemcpyDeviceToHost));
+                if (drho) HIPCHK(hipMemcpy(hd.data(), drho, nn * sizeof(double), hipMemcpyDeviceToHost));
+            }
+            return set_fluid(c, n, hp.data(), vel ? hv.data() : nullptr, rho ? hr.data() : nullptr,
+                             drho ? hd.data() : nullptr);
+        }
+        return set_fluid_impl(c, n, pos, vel, rho, drho, true);
+    }
+
     int set_fluid(int c, int64_t n, const double* pos, const double* vel, const double* rho,
                   const double* drho) override
+    {
+        return set_fluid_impl(c, n, pos, vel, rho, drho, false);
+    }
+
+    int set_fluid_impl(int c, int64_t n, const double* pos, const double* vel, const double* rho,
+                       const double* drho, bool device)
     {
         RETCHK(check_case(c));
         if (n < 0 || (n > 0 && !pos) || n > (int64_t)NBR_MASK / 2)
@@ -638,12 +672,13 @@ struct Engine final : EngineBase {
             RETCHK(upload_params());
             configured = false;
         }
-        return load_case(c, n, pos, vel, rho, drho);
+        return load_case(c, n, pos, vel, rho, drho, device);
     }
 
     // Load case c's fluid (n particles, original order) into its slots of the
     // current set; reset its clock and counters and take its |v|max.
-    int load_case(int c, int64_t n, const double* pos, const double* vel, const double* rho, const double* drho)
+    int load_case(int c, int64_t n, const double* pos, const double* vel, const double* rho, const double* drho,
+                  bool device = false)
     {
         size_t nn = (size_t)n;
         RETCHK(ensure_stage(nn * (2 * D + 2)));
@@ -651,11 +686,12 @@ struct Engine final : EngineBase {
         double* dvel = stage + nn * D;
         double* drh = stage + nn * 2 * D;
         double* ddr = drh + nn;
+        const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         if (n > 0) {
-            HIPCHK(hipMemcpyAsync(dpos, pos, nn * D * sizeof(double), hipMemcpyHostToDevice, s));
-            if (vel) HIPCHK(hipMemcpyAsync(dvel, vel, nn * D * sizeof(double), hipMemcpyHostToDevice, s));
-            if (rho) HIPCHK(hipMemcpyAsync(drh, rho, nn * sizeof(double), hipMemcpyHostToDevice, s));
-            if (drho) HIPCHK(hipMemcpyAsync(ddr, drho, nn * sizeof(double), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(dpos, pos, nn * D * sizeof(double), kind, s));
+            if (vel) HIPCHK(hipMemcpyAsync(dvel, vel, nn * D * sizeof(double), kind, s));
+            if (rho) HIPCHK(hipMemcpyAsync(drh, rho, nn * sizeof(double), kind, s));
+            if (drho) HIPCHK(hipMemcpyAsync(ddr, drho, nn * sizeof(double), kind, s));
             k_load_fluid<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, c, dpos, vel ? dvel : nullptr, rho ? drh : nullptr,
                                                              drho ? ddr : nullptr, x[cur][0], x[cur][1], x[cur][2],
                                                              st[cur], dr3[cur], id[cur], cell[cur]);
@@ -1199,7 +1235,10 @@ struct Engine final : EngineBase {
         return err_code(c, hctrl[c].err);
     }
 
-    int get_field(int c, int which, double* out) override
+    int get_field(int c, int which, double* out) override { return get_field_impl(c, which, out, false); }
+    int get_field_device(int c, int which, double* out) override { return get_field_impl(c, which, out, true); }
+
+    int get_field_impl(int c, int which, double* out, bool device)
     {
         RETCHK(check_case(c));
         if (which < 0 || which > 4 || !out) return ctx->fail(SPHX_EINVAL, "bad field");
@@ -1210,10 +1249,172 @@ struct Engine final : EngineBase {
                                                               st[cur], dr3[cur], outbuf);
         HIPCHK(hipGetLastError());
         size_t cnt_out = (which <= 1 ? (size_t)D : 1) * P.nf;
-        HIPCHK(hipMemcpyAsync(out, outbuf, sizeof(double) * cnt_out, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(out, outbuf, sizeof(double) * cnt_out,
+                              device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         return SPHX_OK;
     }
+
+    // ------------------------------------------------------------------
+    // Checkpoint: parameters, walls and their motion, clocks and control
+    // blocks, and every case's particle state in the current (cell-sorted)
+    // slot order. A context created with the same parameters continues from
+    // a loaded checkpoint exactly as the saved one would (the configuration
+    // is rebuilt from the sorted state, which the stable sort leaves as is).
+    static constexpr char CKPT_MAGIC[9] = "SPHXCK01";
+
+    int save(const char* path) override
+    {
+        if (!path) return ctx->fail(SPHX_EINVAL, "no checkpoint path");
+        RETCHK(ensure_layout());
+        RETCHK(sync_ctrl());
+        FILE* f = std::fopen(path, "wb");
+        if (!f) return ctx->fail(SPHX_EINVAL, std::string("cannot write ") + path);
+        bool ok = true;
+        auto put = [&](const void* p, size_t bytes) { ok = ok && (bytes == 0 || std::fwrite(p, 1, bytes, f) == bytes); };
+        const int32_t hdr[4] = {D, (int32_t)sizeof(real), C, ntot};
+        put(CKPT_MAGIC, 8);
+        put(hdr, sizeof(hdr));
+        for (int c = 0; c < C; ++c) {
+            const KP<real>& P = hP[c];
+            put(&ctx->prm[c], sizeof(sphx_params));
+            const int32_t lay[4] = {P.nf, P.fcap, P.fbase, P.nw};
+            put(lay, sizeof(lay));
+            put(&hctrl[c], sizeof(Ctrl));
+            put(wpos_h[c].data(), wpos_h[c].size() * sizeof(double));
+            put(wnrm_h[c].data(), wnrm_h[c].size() * sizeof(double));
+            const int32_t nfl = (int32_t)wflag_h[c].size();
+            put(&nfl, sizeof(nfl));
+            put(wflag_h[c].data(), wflag_h[c].size() * sizeof(int32_t));
+            const double mo[8] = {P.wamp[0], P.wamp[1], P.wamp[2], P.womega, P.wroll, P.wpivot[0], P.wpivot[1],
+                                  P.wpivot[2]};
+            put(&P.wmove, sizeof(int32_t));
+            put(mo, sizeof(mo));
+        }
+        const size_t n = (size_t)ntot;
+        std::vector<double> hx(n);
+        for (int k = 0; k < D; ++k) {
+            HIPCHK(hipMemcpy(hx.data(), x[cur][k], n * sizeof(double), hipMemcpyDeviceToHost));
+            put(hx.data(), n * sizeof(double));
+        }
+        std::vector<R4<real>> hs(n);
+        HIPCHK(hipMemcpy(hs.data(), st[cur], n * sizeof(R4<real>), hipMemcpyDeviceToHost));
+        put(hs.data(), n * sizeof(R4<real>));
+        if (D == 3) {
+            std::vector<real> hd(n);
+            HIPCHK(hipMemcpy(hd.data(), dr3[cur], n * sizeof(real), hipMemcpyDeviceToHost));
+            put(hd.data(), n * sizeof(real));
+        }
+        std::vector<int32_t> hi(n);
+        HIPCHK(hipMemcpy(hi.data(), id[cur], n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        put(hi.data(), n * sizeof(int32_t));
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok) return ctx->fail(SPHX_EINVAL, std::string("write failed: ") + path);
+        return SPHX_OK;
+    }
+
+    int load(const char* path) override
+    {
+        if (!path) return ctx->fail(SPHX_EINVAL, "no checkpoint path");
+        FILE* f = std::fopen(path, "rb");
+        if (!f) return ctx->fail(SPHX_EINVAL, std::string("cannot read ") + path);
+        std::unique_ptr<FILE, int (*)(FILE*)> guard(f, &std::fclose);
+        bool ok = true;
+        auto get = [&](void* p, size_t bytes) { ok = ok && (bytes == 0 || std::fread(p, 1, bytes, f) == bytes); };
+        char magic[8];
+        int32_t hdr[4];
+        get(magic, 8);
+        get(hdr, sizeof(hdr));
+        if (!ok || std::memcmp(magic, CKPT_MAGIC, 8) != 0) return ctx->fail(SPHX_EINVAL, "not a checkpoint");
+        if (hdr[0] != D || hdr[1] != (int32_t)sizeof(real) || hdr[2] != C || hdr[3] < 0 || hdr[3] % TILE)
+            return ctx->fail(SPHX_EINVAL, "checkpoint of another dimension, precision or case count");
+        struct CaseRec {
+            sphx_params q;
+            int32_t lay[4];
+            Ctrl k;
+            std::vector<double> wp, wn;
+            std::vector<int32_t> fl;
+            int32_t wmove;
+            double mo[8];
+        };
+        std::vector<CaseRec> rec(C);
+        int32_t ntot_f = 0;
+        for (int c = 0; c < C && ok; ++c) {
+            CaseRec& r = rec[c];
+            get(&r.q, sizeof(sphx_params));
+            get(r.lay, sizeof(r.lay));
+            get(&r.k, sizeof(Ctrl));
+            if (!ok) break;
+            sphx_params a = r.q, b = ctx->prm[c];
+            a.nsub_queue = b.nsub_queue = 0;
+            if (std::memcmp(&a, &b, sizeof(sphx_params)) != 0)
+                return ctx->fail(SPHX_EINVAL, case_tag(c) + "checkpoint parameters differ from the context's");
+            if (r.lay[0] < 0 || r.lay[1] != round_tile(r.lay[0]) || r.lay[2] != ntot_f || r.lay[3] < 0 ||
+                r.lay[3] > (int32_t)NBR_MASK)
+                return ctx->fail(SPHX_EINVAL, "corrupt checkpoint layout");
+            ntot_f += r.lay[1];
+            r.wp.resize((size_t)r.lay[3] * D);
+            r.wn.resize((size_t)r.lay[3] * D);
+            get(r.wp.data(), r.wp.size() * sizeof(double));
+            get(r.wn.data(), r.wn.size() * sizeof(double));
+            int32_t nfl = 0;
+            get(&nfl, sizeof(nfl));
+            if (!ok || (nfl != 0 && nfl != r.lay[3])) return ctx->fail(SPHX_EINVAL, "corrupt checkpoint walls");
+            r.fl.resize(nfl);
+            get(r.fl.data(), r.fl.size() * sizeof(int32_t));
+            get(&r.wmove, sizeof(int32_t));
+            get(r.mo, sizeof(r.mo));
+        }
+        if (!ok || ntot_f != hdr[3]) return ctx->fail(SPHX_EINVAL, "truncated or corrupt checkpoint");
+        const size_t n = (size_t)hdr[3];
+        std::vector<std::vector<double>> hx(D, std::vector<double>(n));
+        for (int k = 0; k < D; ++k) get(hx[k].data(), n * sizeof(double));
+        std::vector<R4<real>> hs(n);
+        get(hs.data(), n * sizeof(R4<real>));
+        std::vector<real> hd(D == 3 ? n : 0);
+        if (D == 3) get(hd.data(), n * sizeof(real));
+        std::vector<int32_t> hi(n);
+        get(hi.data(), n * sizeof(int32_t));
+        if (!ok) return ctx->fail(SPHX_EINVAL, "truncated checkpoint");
+        // layout exactly as saved, state into set 0
+        HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < C; ++c) {
+            hP[c].nf = rec[c].lay[0];
+            hP[c].fcap = rec[c].lay[1];
+            pend[c] = Pending{};
+        }
+        laid_out = false;
+        RETCHK(layout(false, -1));
+        for (int k = 0; k < D; ++k)
+            HIPCHK(hipMemcpy(x[0][k], hx[k].data(), n * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(st[0], hs.data(), n * sizeof(R4<real>), hipMemcpyHostToDevice));
+        if (D == 3) HIPCHK(hipMemcpy(dr3[0], hd.data(), n * sizeof(real), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(id[0], hi.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+        for (int c = 0; c < C; ++c) hctrl[c] = rec[c].k;
+        RETCHK(push_ctrl());
+        HIPCHK(hipStreamSynchronize(s));
+        // walls and motions, posed at the restored clocks
+        for (int c = 0; c < C; ++c) {
+            CaseRec& r = rec[c];
+            wpos_h[c] = r.wp;
+            wnrm_h[c] = r.wn;
+            hP[c].nw = r.lay[3];
+            hP[c].wmove = r.wmove ? 1 : 0;
+            hP[c].wamp[0] = r.mo[0];
+            hP[c].wamp[1] = r.mo[1];
+            hP[c].wamp[2] = r.mo[2];
+            hP[c].womega = r.mo[3];
+            hP[c].wroll = r.mo[4];
+            hP[c].wpivot[0] = r.mo[5];
+            hP[c].wpivot[1] = r.mo[6];
+            hP[c].wpivot[2] = r.mo[7];
+            wflag_h[c] = r.fl;
+        }
+        RETCHK(upload_walls());
+        configured = false;
+        return SPHX_OK;
+    }
+
 
     // c >= 0: one case into out[0]; c < 0: every case into out[0..C).
     int diagnostics(int c, sphx_diag* out) override
@@ -2033,6 +2234,18 @@ int sphx_set_wall_motion_case(sphx_ctx* ctx, int32_t c, const sphx_wall_motion* 
 {
     ENG_CALL(set_wall_motion(c, motion, moving));
 }
+
+int sphx_save(sphx_ctx* ctx, const char* path) { ENG_CALL(save(path)); }
+
+int sphx_load(sphx_ctx* ctx, const char* path) { ENG_CALL(load(path)); }
+
+int sphx_set_fluid_device(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos, const double* vel,
+                          const double* rho, const double* drho)
+{
+    ENG_CALL(set_fluid_device(c, n, pos, vel, rho, drho));
+}
+
+int sphx_get_field_device(sphx_ctx* ctx, int32_t c, int field, double* out) { ENG_CALL(get_field_device(c, field, out)); }
 
 int sphx_build_neighbors(sphx_ctx* ctx) { ENG_CALL(build_neighbors()); }
 

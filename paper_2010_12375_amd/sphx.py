@@ -26,7 +26,8 @@ ERROR_NAMES = {SPHX_EINVAL: "EINVAL", SPHX_ENOMEM: "ENOMEM", SPHX_EHIP: "EHIP", 
 
 EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_set_params_case", "sphx_destroy", "sphx_last_error",
             "sphx_set_fluid", "sphx_set_fluid_case", "sphx_set_walls", "sphx_set_walls_case",
-            "sphx_set_wall_motion", "sphx_set_wall_motion_case",
+            "sphx_set_wall_motion", "sphx_set_wall_motion_case", "sphx_set_fluid_device", "sphx_get_field_device",
+            "sphx_save", "sphx_load",
             "sphx_build_neighbors", "sphx_get_neighbors", "sphx_get_neighbors_case", "sphx_density_reinit",
             "sphx_time_steps", "sphx_time_steps_case", "sphx_compute_rates", "sphx_compute_rates_case",
             "sphx_advance", "sphx_case_status", "sphx_get_field", "sphx_get_field_case", "sphx_diagnostics",
@@ -88,6 +89,10 @@ def load(path=None):
         "sphx_set_walls_case": [vp, i32, i64, vp, vp],
         "sphx_set_wall_motion": [vp, C.POINTER(sphx_wall_motion), vp],
         "sphx_set_wall_motion_case": [vp, i32, C.POINTER(sphx_wall_motion), vp],
+        "sphx_set_fluid_device": [vp, i32, i64, vp, vp, vp, vp],
+        "sphx_get_field_device": [vp, i32, C.c_int, vp],
+        "sphx_save": [vp, C.c_char_p],
+        "sphx_load": [vp, C.c_char_p],
         "sphx_build_neighbors": [vp],
         "sphx_get_neighbors": [vp, C.c_int, vp, vp, i64, pi64],
         "sphx_get_neighbors_case": [vp, i32, C.c_int, vp, vp, i64, pi64],
@@ -235,6 +240,32 @@ class Simulation:
         pos, normal = _f64(pos), _f64(normal)
         self._check(self._L.sphx_set_walls_case(self._h, case, pos.shape[0], _ptr(pos), _ptr(normal)),
                     "sphx_set_walls_case")
+
+    def save(self, path):
+        """Checkpoint the whole batch to `path`."""
+        self._check(self._L.sphx_save(self._h, str(path).encode()), "sphx_save")
+
+    def load(self, path):
+        """Restore a checkpoint written by a context with the same parameters."""
+        self._check(self._L.sphx_load(self._h, str(path).encode()), "sphx_load")
+        self.nf = [int(self.counts(case=k)["fluid"]) for k in range(self.n_cases)]
+
+    @staticmethod
+    def _dptr(t):
+        """Device address of a tensor-like object (data_ptr()) or an int."""
+        if t is None:
+            return None
+        return C.c_void_p(t.data_ptr() if hasattr(t, "data_ptr") else int(t))
+
+    def set_fluid_device(self, n, pos, vel=None, rho=None, drho=None, case=0):
+        """Fluid from device buffers (FP64, original order), e.g. tensors."""
+        self._check(self._L.sphx_set_fluid_device(self._h, case, int(n), self._dptr(pos), self._dptr(vel),
+                                                  self._dptr(rho), self._dptr(drho)), "sphx_set_fluid_device")
+        self.nf[case] = int(n)
+
+    def get_field_device(self, which, out, case=0):
+        """Write a field (FP64, original order) into a device buffer."""
+        self._check(self._L.sphx_get_field_device(self._h, case, which, self._dptr(out)), "sphx_get_field_device")
 
     def set_wall_motion(self, amp=(0.0, 0.0, 0.0), omega=0.0, roll=0.0, pivot=(0.0, 0.0, 0.0), moving=None,
                         case=0, static=False):

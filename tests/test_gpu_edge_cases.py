@@ -157,3 +157,122 @@ def test_empty_fluid_and_empty_walls():
     assert off.tolist() == [0, 0, 0] and idx.size == 0
     off, idx = g.get_neighbors(sphx.SPHX_INNER)
     assert off.tolist() == [0, 1, 2] and idx.tolist() == [1, 0]
+
+
+# ---------------------------------------------------------------------------
+# checkpoints and device-memory input/output
+
+def _state(g, case=0):
+    return [g.get_field(f, case).tobytes() for f in (sphx.SPHX_FIELD_POS, sphx.SPHX_FIELD_VEL, sphx.SPHX_FIELD_RHO,
+                                                      sphx.SPHX_FIELD_DRHO)]
+
+
+@pytest.mark.parametrize("which", ["dambreak2d_fp32", "sloshing2d_fp64", "batch_fp32", "dambreak3d_fp32"])
+def test_checkpoint_restart_is_bit_identical(which, tmp_path):
+    """Run, save, run on; a fresh context that loads the file and runs on
+    ends bit-identical (all cases, clocks and sub-step counts)."""
+    if which == "dambreak2d_fp32":
+        cases = [wl.config_small(2)]
+        prec = FP32
+    elif which == "sloshing2d_fp64":
+        cases = [wl.sloshing_2d(0.05, roll=0.05)]
+        prec = FP64
+    elif which == "batch_fp32":
+        cases = [wl.dam_break_2d(0.05, seed=1, L=1.5, H=1.2), wl.dam_break_2d(0.025, seed=2),
+                 wl.sloshing_2d(0.05, roll=0.1)]
+        prec = FP32
+    else:
+        cases = [wl.dam_break_3d(0.05, seed=3, W=0.4, DL=2.4, DH=1.3)]
+        prec = FP32
+    a = sphx.Simulation.from_cases(cases, prec, nsub_queue=3)
+    a.advance(7)
+    path = tmp_path / "run.ckpt"
+    a.save(path)
+    a.advance(9)
+    b = sphx.Simulation([sphx.params_from_case(c, prec, 3) for c in cases])
+    b.load(path)
+    b.advance(9)
+    for k in range(len(cases)):
+        assert _state(a, k) == _state(b, k), (which, k)
+        da, db = a.diagnostics(k), b.diagnostics(k)
+        assert da["t"] == db["t"] and da["n_substeps"] == db["n_substeps"] and da["n_steps"] == db["n_steps"]
+
+
+def test_checkpoint_refused_for_other_parameters(tmp_path):
+    case = wl.config_small(0)
+    a = sphx.Simulation.from_case(case, FP32)
+    a.advance(2)
+    path = tmp_path / "run.ckpt"
+    a.save(path)
+    p = sphx.params_from_case(case, FP32)
+    p.c0 = p.c0 * 1.01
+    b = sphx.Simulation(p)
+    with pytest.raises(sphx.SphxError) as e:
+        b.load(path)
+    assert e.value.code == sphx.SPHX_EINVAL
+    c = sphx.Simulation(sphx.params_from_case(case, FP64))
+    with pytest.raises(sphx.SphxError):
+        c.load(path)
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(path.read_bytes()[:100])
+    d = sphx.Simulation(sphx.params_from_case(case, FP32))
+    with pytest.raises(sphx.SphxError):
+        d.load(bad)
+
+
+class _DeviceBuffer:
+    """Device memory from the HIP runtime (standing in for a framework
+    tensor): a data_ptr() and host copies in and out."""
+
+    def __init__(self, hip, arr):
+        import ctypes as C
+        self._hip, self.shape = hip, arr.shape
+        self.nbytes = arr.nbytes
+        self.ptr = C.c_void_p()
+        assert hip.hipMalloc(C.byref(self.ptr), C.c_size_t(max(self.nbytes, 8))) == 0
+        assert hip.hipMemcpy(self.ptr, arr.ctypes.data_as(C.c_void_p), C.c_size_t(self.nbytes), 1) == 0
+
+    def data_ptr(self):
+        return self.ptr.value
+
+    def to_host(self):
+        import ctypes as C
+        out = np.zeros(self.shape)
+        assert self._hip.hipMemcpy(out.ctypes.data_as(C.c_void_p), self.ptr, C.c_size_t(self.nbytes), 2) == 0
+        return out
+
+    def free(self):
+        self._hip.hipFree(self.ptr)
+
+
+def test_device_memory_input_and_output():
+    """Fluid from device buffers and fields into device buffers give the same
+    state and fields as the host calls."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    hip.hipFree.argtypes = [C.c_void_p]
+    case = wl.config_small(3)
+    vel, rho, drho = developed_state(case, seed=3)
+    h = sphx.Simulation(sphx.params_from_case(case, FP64))
+    h.set_fluid(case.fluid_pos, vel, rho, drho)
+    h.set_walls(case.wall_pos, case.wall_normal)
+    d = sphx.Simulation(sphx.params_from_case(case, FP64))
+    bufs = [_DeviceBuffer(hip, np.ascontiguousarray(a, dtype=np.float64)) for a in (case.fluid_pos, vel, rho, drho)]
+    d.set_fluid_device(case.n_fluid, *bufs)
+    d.set_walls(case.wall_pos, case.wall_normal)
+    for g in (h, d):
+        g.advance(4)
+    assert _state(h) == _state(d)
+    out = _DeviceBuffer(hip, np.zeros((case.n_fluid, 2)))
+    d.get_field_device(sphx.SPHX_FIELD_VEL, out)
+    assert np.array_equal(out.to_host(), d.get_field(sphx.SPHX_FIELD_VEL))
+    # refill in place from device memory, now on the device layout
+    d.set_fluid_device(case.n_fluid, *bufs)
+    h.set_fluid(case.fluid_pos, vel, rho, drho)
+    for g in (h, d):
+        g.advance(2)
+    assert _state(h) == _state(d)
+    for b in bufs + [out]:
+        b.free()
