@@ -75,6 +75,8 @@ def lib():
         L.orc_set_walls.argtypes = [vp, i64, vp, vp]
         L.orc_set_wall_motion.restype = C.c_int
         L.orc_set_wall_motion.argtypes = [vp, C.POINTER(orc_wall_motion), vp]
+        L.orc_set_wall_velocity.restype = C.c_int
+        L.orc_set_wall_velocity.argtypes = [vp, vp]
         L.orc_wall_kinematics.restype = C.c_int
         L.orc_wall_kinematics.argtypes = [vp, d, vp, vp, vp]
         L.orc_build_config.restype = C.c_int
@@ -237,6 +239,12 @@ class Oracle:
         flags = None if moving is None else np.ascontiguousarray(moving, dtype=np.int32)
         self._flags = flags
         self._check(self._L.orc_set_wall_motion(self._h, C.byref(m), _ptr(flags)), "set_wall_motion")
+
+    def set_wall_velocity(self, vel):
+        """Given velocity of every wall particle (None: none)."""
+        v = None if vel is None else _f64(vel)
+        self._wv = v
+        self._check(self._L.orc_set_wall_velocity(self._h, _ptr(v)), "set_wall_velocity")
 
     def wall_kinematics(self, t, n_wall):
         """(positions, normals, velocities) of the wall particles at time t."""

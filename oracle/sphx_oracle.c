@@ -95,6 +95,9 @@ typedef struct {
     int32_t *wmov;
     orc_wall_motion mo;
     double wc[3];
+    /* given velocity of each wall particle (stride 3; NULL: none), e.g. a
+     * lid sliding along itself; added to the velocity of the motion */
+    double *vw0;
     /* configuration: positions frozen at the last update and neighbour lists */
     double *xs;
     int64_t *in_off, *ct_off; /* CSR offsets, nf + 1 each */
@@ -228,7 +231,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     free_config(s);
     free(s->x); free(s->v); free(s->rho); free(s->drho);
-    free(s->xw); free(s->nrm); free(s->xw0); free(s->nrm0); free(s->wmov);
+    free(s->xw); free(s->nrm); free(s->xw0); free(s->nrm0); free(s->wmov); free(s->vw0);
     free(s->av); free(s->atv);
     free(s);
 }
@@ -299,8 +302,9 @@ int orc_set_walls(orc_sim *s, int64_t n, const double *pos, const double *normal
             double xk = pos[s->d * i + k];
             if (!(xk >= s->p.lo[k] && xk < s->p.hi[k])) return ORC_EINVAL;
         }
-    free(s->xw); free(s->nrm); free(s->xw0); free(s->nrm0); free(s->wmov);
+    free(s->xw); free(s->nrm); free(s->xw0); free(s->nrm0); free(s->wmov); free(s->vw0);
     s->wmov = NULL;
+    s->vw0 = NULL;
     s->moving = 0;
     free_config(s);
     s->nw = n;
@@ -344,6 +348,23 @@ int orc_set_wall_motion(orc_sim *s, const orc_wall_motion *m, const int32_t *fla
         s->mo.pivot[2] = 0.0;
     }
     s->moving = 1;
+    return ORC_OK;
+}
+
+/* Given wall velocities: vel n*dim in the order given to orc_set_walls
+ * (NULL: none). The walls do not move with them: they are the velocity of
+ * the wall surface (e.g. a lid sliding along itself), used in the wall
+ * states and the no-slip shear like the velocity of a motion. */
+int orc_set_wall_velocity(orc_sim *s, const double *vel)
+{
+    if (!s) return ORC_EINVAL;
+    free(s->vw0);
+    s->vw0 = NULL;
+    if (!vel) return ORC_OK;
+    s->vw0 = (double *)calloc(3 * (size_t)(s->nw > 0 ? s->nw : 1), sizeof(double));
+    if (!s->vw0) return ORC_ENOMEM;
+    for (int64_t w = 0; w < s->nw; ++w)
+        for (int k = 0; k < s->d; ++k) s->vw0[3 * w + k] = vel[s->d * w + k];
     return ORC_OK;
 }
 
@@ -403,6 +424,8 @@ int orc_wall_kinematics(const orc_sim *s, double t, double *pos, double *nrm, do
         double x[3], n[3], v[3] = {0.0, 0.0, 0.0};
         wall_pose(s, w, t, x, n);
         if (s->moving && s->wmov[w]) wall_velocity(s, x, c, t, v);
+        if (s->vw0)
+            for (int k = 0; k < 3; ++k) v[k] += s->vw0[3 * w + k];
         for (int k = 0; k < s->d; ++k) {
             if (pos) pos[s->d * w + k] = x[k];
             if (nrm) nrm[s->d * w + k] = n[k];
@@ -668,14 +691,17 @@ void orc_kernel_sums(const orc_sim *s, double *sigma)
 }
 
 /* ------------------------------------------------------------------ */
-/* Velocity at time t of wall particle w of the current configuration (zero
- * for a static wall). Reading: the pose (position, normal and lever arm
+/* Velocity at time t of wall particle w of the current configuration: its
+ * given velocity plus the velocity of its motion (zero for a static wall
+ * without one). Reading: the pose (position, normal and lever arm
  * about the rotation centre) is the one frozen at the configuration update;
  * only the rates d'(t), theta'(t) are taken at time t. */
 static void config_wall_velocity(const orc_sim *s, int64_t w, double t, double *v)
 {
     v[0] = v[1] = v[2] = 0.0;
     if (s->moving && s->wmov[w]) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);
+    if (s->vw0)
+        for (int k = 0; k < 3; ++k) v[k] += s->vw0[3 * w + k];
 }
 
 /* One-sided wall Riemann states, Eqs. (eqriepartial), (eqrienoslip),

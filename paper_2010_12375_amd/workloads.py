@@ -81,6 +81,7 @@ class Case:
     reinit_mode: int = 0           # 0: free-surface density re-init, 1: no free surface
     wall_motion: Optional[WallMotion] = None   # None: static walls
     wall_moving: Optional[np.ndarray] = None   # per wall particle 0/1 (None: all follow the motion)
+    wall_velocity: Optional[np.ndarray] = None  # (n_w, dim) given wall velocities (None: none)
 
     @property
     def n_fluid(self) -> int:
@@ -379,3 +380,41 @@ def piston_2d(dp, V=0.2, L=2.0, W=0.4, omega=0.5, precision=FP64, layers=4, name
                 lo=(-pad - V / omega, 0.0, 0.0), hi=(L + V / omega + pad + 1.0, W, 0.0), periodic=(0, 1, 0),
                 fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision, column=(L, W),
                 wall_motion=mo, **prm)
+
+
+def couette_2d(dp=0.02, H=0.2, L=0.2, U=0.1, nu=0.05, precision=FP64):
+    """Plane Couette flow: fluid between a fixed bottom wall and a top wall
+    sliding along itself with velocity U (a given wall velocity, the walls do
+    not move), periodic along x, no gravity, viscosity nu; the steady profile
+    is linear."""
+    nx, ny = int(round(L / dp)), int(round(H / dp))
+    pos = _lattice((nx, ny), dp)
+    wb = _lattice((nx, 4), dp) - np.array([0.0, 4 * dp])
+    wt = _lattice((nx, 4), dp) + np.array([0.0, H])
+    wpos = np.concatenate([wb, wt])
+    wn = np.concatenate([np.tile([0.0, 1.0], (len(wb), 1)), np.tile([0.0, -1.0], (len(wt), 1))])
+    wv = np.concatenate([np.zeros((len(wb), 2)), np.tile([U, 0.0], (len(wt), 1))])
+    c0 = 10.0 * U
+    return Case(name=f"couette2d_dp{dp:g}", dim=2, dp=dp, h=1.3 * dp, rho0=1.0, c0=c0, u_ref=U, cfl_ad=0.25,
+                cfl_ac=0.6, gravity=(0.0, 0.0, 0.0), lo=(0.0, -0.2 * H - 4 * dp, 0.0), hi=(L, 1.2 * H + 4 * dp, 0.0),
+                periodic=(1, 0, 0), fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision, column=(L, H),
+                eta=nu, reinit_mode=1, wall_velocity=wv)
+
+
+def lid_cavity_2d(dp=0.02, Re=100.0, U=1.0, L=1.0, seed=0, jitter=0.0, precision=FP64, layers=4):
+    """Lid-driven cavity: fluid filling a closed L x L box whose top wall
+    slides along itself with velocity U (a given wall velocity), no gravity,
+    viscosity rho0 U L / Re, c0 = 10 U, density re-initialisation without
+    free surface (a flow without free surface)."""
+    n = int(round(L / dp))
+    pos = _lattice((n, n), dp)
+    if jitter:
+        pos = _jitter(pos, dp, seed, jitter)
+    wpos, wn = tank_walls_2d(L, L, dp, layers)
+    wv = np.where((wpos[:, 1] > L)[:, None], np.array([U, 0.0]), 0.0)
+    c0 = 10.0 * U
+    pad = layers * dp + 2.6 * dp
+    return Case(name=f"lidcavity2d_dp{dp:g}_Re{Re:g}", dim=2, dp=dp, h=1.3 * dp, rho0=1.0, c0=c0, u_ref=U,
+                cfl_ad=0.25, cfl_ac=0.6, gravity=(0.0, 0.0, 0.0), lo=(-pad, -pad, 0.0), hi=(L + pad, L + pad, 0.0),
+                periodic=(0, 0, 0), fluid_pos=pos, wall_pos=wpos, wall_normal=wn, precision=precision, column=(L, L),
+                tank=(L, L), seed=seed, eta=U * L / Re, reinit_mode=1, wall_velocity=wv)

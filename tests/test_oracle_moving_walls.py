@@ -158,3 +158,48 @@ def test_walls_flagged_static_give_the_static_rates():
     a0, d0 = _rates(case, vel, rho, drho, t=0.8)
     a1, d1 = _rates(case, vel, rho, drho, motion=mo, t=0.8)
     assert np.array_equal(a0, a1) and np.array_equal(d0, d1)
+
+
+def test_given_wall_velocity_is_galilean_invariant_too():
+    """Walls at rest carrying a given velocity U, fluid moving with U: the
+    rates of the same state at rest, with and without viscosity."""
+    case = wl.dam_break_2d(0.05, seed=4)
+    _, rho, drho = developed_state(case, seed=6)
+    U = np.array([0.3, 0.5])
+    n = case.n_fluid
+    for eta in (0.0, 0.02):
+        p = O.params_from_case(case)
+        p.eta = eta
+        rest = O.Oracle(params=p)
+        rest.set_fluid(case.fluid_pos, vel=np.zeros((n, 2)), rho=rho, drho=drho)
+        rest.set_walls(case.wall_pos, case.wall_normal)
+        rest.build_config()
+        a0, d0 = rest.compute_rates(0.0)
+        mov = O.Oracle(params=p)
+        mov.set_fluid(case.fluid_pos, vel=np.tile(U, (n, 1)), rho=rho, drho=drho)
+        mov.set_walls(case.wall_pos, case.wall_normal)
+        mov.set_wall_velocity(np.tile(U, (case.n_wall, 1)))
+        mov.build_config()
+        a1, d1 = mov.compute_rates(0.0)
+        assert np.abs(a1 - a0).max() <= 1e-10 * (np.abs(a0).max() + 1.0)
+        assert np.abs(d1 - d0).max() <= 1e-10 * (np.abs(d0).max() + np.sqrt((d0 ** 2).mean()))
+
+
+def test_couette_flow_between_a_sliding_and_a_fixed_wall():
+    """Plane Couette flow (viscous, no gravity): the steady velocity profile
+    is linear, U (y + dp/2) / (H + dp), the no-slip condition holding at the
+    first layer of wall particles on either side, within 1 % of U. Pins the
+    given wall velocity in the no-slip shear (sign and size)."""
+    case = wl.couette_2d()
+    o = O.Oracle(case)
+    o.set_wall_velocity(case.wall_velocity)
+    o.build_config()
+    while o.t < 1.0 - 1e-12:
+        o.advance(1.0)
+    x = o.field(O.FIELD_POS)
+    v = o.field(O.FIELD_VEL)
+    H, dp, U = case.column[1], case.dp, float(case.wall_velocity[:, 0].max())
+    for y in np.unique(np.round(case.fluid_pos[:, 1], 9)):
+        sel = np.abs(x[:, 1] - y) < dp / 2
+        assert v[sel, 0].mean() == pytest.approx(U * (y + dp / 2) / (H + dp), abs=0.01 * U)
+    assert np.abs(v[:, 1]).max() < 1e-3 * U

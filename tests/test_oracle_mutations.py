@@ -66,6 +66,10 @@ MUTATIONS = [
     ("normal_not_rotated", "n[0] = ct * n0[0] - st * n0[1];", "n[0] = n0[0];", None),
     ("static_flag_ignored", "if (s->moving && s->wmov[w]) wall_velocity(s, x, c, t, v);",
      "if (s->moving) wall_velocity(s, x, c, t, v);", None),
+    ("given_wall_velocity_dropped", "for (int k = 0; k < 3; ++k) v[k] += s->vw0[3 * w + k];\n}",
+     "for (int k = 0; k < 3; ++k) v[k] += 0.0 * s->vw0[3 * w + k];\n}", None),
+    ("given_wall_velocity_sign", "for (int k = 0; k < 3; ++k) v[k] += s->vw0[3 * w + k];\n}",
+     "for (int k = 0; k < 3; ++k) v[k] -= s->vw0[3 * w + k];\n}", None),
     ("static_flag_ignored_in_states", "if (s->moving && s->wmov[w]) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);",
      "if (s->moving) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);", None),
 ]
