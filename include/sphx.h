@@ -184,6 +184,21 @@ int sphx_set_wall_motion(sphx_ctx* ctx, const sphx_wall_motion* motion, const in
 /* The same for case c. */
 int sphx_set_wall_motion_case(sphx_ctx* ctx, int32_t c, const sphx_wall_motion* motion, const int32_t* moving);
 
+/* Given velocities of case 0's wall particles (Section 2.3: the wall
+ * velocity v_w of Eqs. eqrienoslip and eqviscous for walls that do not move,
+ * e.g. a lid or belt sliding along itself). `vel`: dim values per wall
+ * particle, in the order of sphx_set_walls, host memory, copied; NULL clears
+ * them. They add to the velocity of a motion where both are given, are
+ * taken in the fixed x-y-z frame (not turned with a roll), and leave the
+ * walls where they are. All zero is the same as none (the static code
+ * path). sphx_set_walls clears them. SPHX_EINVAL for a non-finite value.
+ * Invalidates the neighbour configuration; the surrogate calls refuse
+ * batches with wall velocities. */
+int sphx_set_wall_velocity(sphx_ctx* ctx, const double* vel);
+
+/* The same for case c. */
+int sphx_set_wall_velocity_case(sphx_ctx* ctx, int32_t c, const double* vel);
+
 /* Fluid particles from device memory of the context's device (for example
  * the storage of framework tensors; the caller keeps ownership and may free
  * the buffers when the call returns): the same arrays and meaning as

@@ -126,6 +126,7 @@ template <typename real> struct KP {
     int reinit_mode;                          // 0: free surface (max), 1: no free surface
     int adv_forces;                           // eta > 0 or p0 != 0
     int wmove;                                // the walls follow the prescribed motion below
+    int wvel;                                 // the walls carry given velocities (surface sliding)
     double wamp[3], womega, wroll, wpivot[3]; // sway amp sin(w t), roll sin(w t) about pivot + sway
     int case_id;
     int fbase, nf, fcap;                      // fluid slots [fbase, fbase + fcap), the first nf used
@@ -373,6 +374,25 @@ __device__ __forceinline__ void wall_velocity(const R4<real>& k, const real V[3]
     v[0] = k.z * V[0] - om * k.y;
     v[1] = k.z * V[1] + om * k.x;
     v[2] = k.z * V[2];
+}
+
+// Add a wall particle's given velocity g = {v_x, v_y, v_z, 0}.
+template <typename real>
+__device__ __forceinline__ void add_given(const R4<real>& g, real v[3])
+{
+    v[0] += g.x;
+    v[1] += g.y;
+    v[2] += g.z;
+}
+
+// Whether the case of the tile holding slot i0 has walls with a velocity
+// (a motion or given velocities).
+template <typename real>
+__device__ __forceinline__ bool wall_velocity_case(const KP<real>* __restrict__ Pt,
+                                                   const int32_t* __restrict__ tcase, int i0)
+{
+    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    return P.wmove || P.wvel;
 }
 
 // Density re-initialisation of one particle from its kernel sum sigma (self
@@ -684,7 +704,8 @@ __global__ __launch_bounds__(BLOCK) void k_cell_order(int ncell, const int32_t* 
 // Walls: move into cell order in their pose at the case's clock, freeze
 // offsets and normals, keep ids relative to the case's first wall particle;
 // with `bmot`, also the motion record {m r_x, m r_y, m, 0} (m: follows the
-// motion, r: lever arm from the rotation centre).
+// motion, r: lever arm from the rotation centre); with `bvg`, the given
+// velocity (vin: 3 per wall particle, input order).
 template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_gather_wall(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ wcase, const Ctrl* __restrict__ ctrl_all,
@@ -693,7 +714,8 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
     const double* __restrict__ an0, const double* __restrict__ an1, const double* __restrict__ an2,
     double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
     typename GeoSel<D, real>::T* __restrict__ bgeo, typename GeoSel<D, real>::T* __restrict__ bnrm,
-    int32_t* __restrict__ bid, R4<real>* __restrict__ bmot)
+    int32_t* __restrict__ bid, R4<real>* __restrict__ bmot, const double* __restrict__ vin,
+    R4<real>* __restrict__ bvg)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -716,6 +738,8 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
         }
         bmot[s] = k;
     }
+    if (bvg) bvg[s] = R4<real>{(real)vin[3 * (size_t)i], (real)vin[3 * (size_t)i + 1], (real)vin[3 * (size_t)i + 2],
+                               (real)0};
     bx0[s] = x[0];
     bx1[s] = x[1];
     if (D == 3) bx2[s] = x[2];
@@ -1119,7 +1143,7 @@ __device__ __forceinline__ void adv_forces_body(
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
     const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, R4<real>* __restrict__ avt,
-    const R4<real>* __restrict__ wmot)
+    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
     const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
     const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
@@ -1136,12 +1160,13 @@ __device__ __forceinline__ void adv_forces_body(
     const real rho_i = P.rho0 + (D == 2 ? si.z : si.w);
     const real inv_rho_i = (real)1 / rho_i;
     real av[3] = {0, 0, 0}, at[3] = {0, 0, 0};
-    // moving walls: velocity at the start of the advection step (no slip)
-    const bool mv = MOVE && P.wmove;
+    // moving walls: velocity at the start of the advection step (no slip),
+    // plus the given velocities
+    const bool mv = MOVE && P.wmove, gv = MOVE && P.wvel;
     real Vw[3] = {0, 0, 0}, omw = 0;
     if (mv) wall_rates(P, ctrl->t, Vw, omw);
     struct FluidJ { G o; R4<real> s; };
-    struct WallJ { G o; R4<real> k; };
+    struct WallJ { G o; R4<real> k, g; };
     for_pairs<T, BATCH>(
         nbr, i, ncnt[i], P.maxn, l,
         [&](uint32_t e) {
@@ -1172,6 +1197,7 @@ __device__ __forceinline__ void adv_forces_body(
             WallJ r;
             r.o = wgeo[w];
             if (mv) r.k = wmot[w];
+            if (gv) r.g = wvg[w];
             return r;
         },
         [&](uint32_t e, const WallJ& r) {
@@ -1181,6 +1207,7 @@ __device__ __forceinline__ void adv_forces_body(
             const real ct = (real)2 * P.p0 * w;
             real vw[3] = {0, 0, 0};
             if (mv) wall_velocity(r.k, Vw, omw, vw);
+            if (gv) add_given(r.g, vw);
             av[0] += cv * (vi[0] - vw[0]);
             av[1] += cv * (vi[1] - vw[1]);
             if (D == 3) av[2] += cv * (vi[2] - vw[2]);
@@ -1204,18 +1231,18 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
     const int32_t* __restrict__ wcnt, const R4<real>* __restrict__ st, R4<real>* __restrict__ avt,
-    const R4<real>* __restrict__ wmot)
+    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
     if constexpr (MOVE) {
         // cases with static walls run the static instantiation's code
-        if (!Pt[tcase[pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)) / TILE]].wmove) {
+        if (!wall_velocity_case(Pt, tcase, pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)))) {
             adv_forces_body<D, real, T, false>(
-                Pt, tcase, ctrl_all, gate, geo, wgeo, nbr, ncnt, wnb, wcnt, st, avt, wmot);
+                Pt, tcase, ctrl_all, gate, geo, wgeo, nbr, ncnt, wnb, wcnt, st, avt, wmot, wvg);
             return;
         }
     }
     adv_forces_body<D, real, T, MOVE>(
-        Pt, tcase, ctrl_all, gate, geo, wgeo, nbr, ncnt, wnb, wcnt, st, avt, wmot);
+        Pt, tcase, ctrl_all, gate, geo, wgeo, nbr, ncnt, wnb, wcnt, st, avt, wmot, wvg);
 }
 
 // The pair kernels below take MOVE = true only for batches with moving
@@ -1234,7 +1261,7 @@ __device__ __forceinline__ void pressure_body(
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
     real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all,
-    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot)
+    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
     const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
     const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
@@ -1273,8 +1300,9 @@ __device__ __forceinline__ void pressure_body(
     using G = typename GeoSel<D, real>::T;
     const real dt = (real)S.dt;
     const real half = (real)0.5 * dt;
-    // moving walls: velocity rates at the sub-step's start (the level of v^n)
-    const bool mv = MOVE && P.wmove;
+    // moving walls: velocity rates at the sub-step's start (the level of v^n),
+    // plus the given velocities
+    const bool mv = MOVE && P.wmove, gv = MOVE && P.wvel;
     real Vw[3] = {0, 0, 0}, omw = 0;
     if (mv) wall_rates(P, ctrl->t + S.tau, Vw, omw);
     const R4<real> si = st[i];
@@ -1292,7 +1320,7 @@ __device__ __forceinline__ void pressure_body(
     const G oi = geo[i];
     real acc[3] = {0, 0, 0};
     struct FluidJ { G o; R4<real> s; real dr; };
-    struct WallJ { G o; G n; R4<real> k; };
+    struct WallJ { G o; G n; R4<real> k, g; };
     for_pairs<T, BATCH>(
         nbr, i, ncnt[i], P.maxn, l,
         [&](uint32_t e) {
@@ -1327,6 +1355,7 @@ __device__ __forceinline__ void pressure_body(
             r.o = wgeo[w];
             r.n = wnrm[w];
             if (mv) r.k = wmot[w];
+            if (gv) r.g = wvg[w];
             return r;
         },
         [&](uint32_t e, const WallJ& r) {
@@ -1334,9 +1363,10 @@ __device__ __forceinline__ void pressure_body(
             const G& nw = r.n;
             real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
             real uw = 0;  // u_w = -n_w . v_w, zero for a static wall
-            if (mv) {
-                real vw[3];
-                wall_velocity(r.k, Vw, omw, vw);
+            if (mv || gv) {
+                real vw[3] = {0, 0, 0};
+                if (mv) wall_velocity(r.k, Vw, omw, vw);
+                if (gv) add_given(r.g, vw);
                 uw = -(nw.x * vw[0] + nw.y * vw[1] + (D == 3 ? zc(nw) * vw[2] : (real)0));
             }
             real du = (real)2 * (UL - uw);  // U_L - U_R with U_R = -U_L + 2 u_w
@@ -1389,20 +1419,20 @@ __global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR void k_pressure(
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
     real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all,
-    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot)
+    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
     if constexpr (MOVE) {
         // cases with static walls run the static instantiation's code
-        if (!Pt[tcase[pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)) / TILE]].wmove) {
+        if (!wall_velocity_case(Pt, tcase, pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)))) {
             pressure_body<D, real, T, false>(
                 Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all,
-                avt, wmot);
+                avt, wmot, wvg);
             return;
         }
     }
     pressure_body<D, real, T, MOVE>(
         Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all, avt,
-        wmot);
+        wmot, wvg);
 }
 
 // ---------------------------------------------------------------------
@@ -1420,7 +1450,7 @@ __device__ __forceinline__ void density_body(
     const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
     double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
     unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt,
-    const R4<real>* __restrict__ wmot)
+    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i0 = pair_block_first<T>(b);
@@ -1435,8 +1465,9 @@ __device__ __forceinline__ void density_body(
     const real half = (real)0.5 * dt;
     const int i = i0 + (int)threadIdx.x / T;
     const int l = threadIdx.x % T;
-    // moving walls: velocity rates at the sub-step's end (the level of v^{n+1})
-    const bool mv = MOVE && P.wmove;
+    // moving walls: velocity rates at the sub-step's end (the level of v^{n+1}),
+    // plus the given velocities
+    const bool mv = MOVE && P.wmove, gv = MOVE && P.wvel;
     real Vw[3] = {0, 0, 0}, omw = 0;
     if (mv) wall_rates(P, ctrl->t + (S.tau + S.dt), Vw, omw);
     real speed = 0;
@@ -1463,7 +1494,7 @@ __device__ __forceinline__ void density_body(
         }
         real sum = 0;
         struct HalfJ { G o; R4<real> h; };
-        struct WallJ { G o; G n; R4<real> k; };
+        struct WallJ { G o; G n; R4<real> k, g; };
         for_pairs<T, BATCH>(
             nbr, i, ncnt[i], P.maxn, l,
             [&](uint32_t e) {
@@ -1494,6 +1525,7 @@ __device__ __forceinline__ void density_body(
                 r.o = wgeo[w];
                 r.n = wnrm[w];
                 if (mv) r.k = wmot[w];
+                if (gv) r.g = wvg[w];
                 return r;
             },
             [&](uint32_t e, const WallJ& r) {
@@ -1505,9 +1537,10 @@ __device__ __forceinline__ void density_body(
                 real rhoR = P.rho0 + pR * P.inv_c2;
                 real rho_bar = (real)0.5 * (rho_i + rhoR);
                 real us = div_r((p_i - pR) * P.half_inv_c, rho_bar);  // + (U_L + U_R)/2 = u_w below
-                if (mv) {
-                    real vw[3];
-                    wall_velocity(r.k, Vw, omw, vw);
+                if (mv || gv) {
+                    real vw[3] = {0, 0, 0};
+                    if (mv) wall_velocity(r.k, Vw, omw, vw);
+                    if (gv) add_given(r.g, vw);
                     us += -(nw.x * vw[0] + nw.y * vw[1] + (D == 3 ? zc(nw) * vw[2] : (real)0));
                 }
                 sum += P.vw * (us - UL) * pq.dW;
@@ -1586,20 +1619,20 @@ __attribute__((amdgpu_waves_per_eu((D == 2 && !MOVE) ? 8 : 1))) void k_density(
     const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
     double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
     unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt,
-    const R4<real>* __restrict__ wmot)
+    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
     if constexpr (MOVE) {
         // cases with static walls run the static instantiation's code
-        if (!Pt[tcase[pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)) / TILE]].wmove) {
+        if (!wall_velocity_case(Pt, tcase, pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)))) {
             density_body<D, real, T, false>(
                 Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2,
-                drho_out, vslot_all, q, avt, wmot);
+                drho_out, vslot_all, q, avt, wmot, wvg);
             return;
         }
     }
     density_body<D, real, T, MOVE>(
         Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2, drho_out,
-        vslot_all, q, avt, wmot);
+        vslot_all, q, avt, wmot, wvg);
 }
 
 // S5 after the last queued density relaxation, for case c, by one

@@ -58,6 +58,7 @@ struct EngineBase {
                           const double* drho) = 0;
     virtual int set_walls(int c, int64_t n, const double* pos, const double* nrm) = 0;
     virtual int set_wall_motion(int c, const sphx_wall_motion* m, const int32_t* moving) = 0;
+    virtual int set_wall_velocity(int c, const double* vel) = 0;
     virtual int save(const char* path) = 0;
     virtual int load(const char* path) = 0;
     virtual int set_fluid_device(int c, int64_t n, const double* pos, const double* vel, const double* rho,
@@ -172,12 +173,15 @@ struct Engine final : EngineBase {
     int nw_tot = 0;
     std::vector<std::vector<double>> wpos_h, wnrm_h;  // per case, as given
     std::vector<std::vector<int32_t>> wflag_h;         // per case: follows the motion (empty: all)
+    std::vector<std::vector<double>> wvel_h;           // per case: given velocities, n*D (empty: none)
     double* wref[6] = {};                              // reference positions and normals, input order
     int32_t *wflag = nullptr, *wcase = nullptr, *wkey = nullptr, *wrank = nullptr, *wperm = nullptr;
     double* wx[3] = {};
     G* wgeo = nullptr;
     G* wnrm = nullptr;
     R4<real>* wmot = nullptr;  // motion records (only while some case has moving walls)
+    double* wvin = nullptr;    // given velocities, 3 per wall particle, input order (only while some case has them)
+    R4<real>* wvg = nullptr;   // the same in the sorted order
     int32_t* wid = nullptr;
     int32_t* wstart = nullptr;
     // control
@@ -345,6 +349,7 @@ struct Engine final : EngineBase {
         wpos_h.assign(C, {});
         wnrm_h.assign(C, {});
         wflag_h.assign(C, {});
+        wvel_h.assign(C, {});
         int cbase = 0;
         for (int c = 0; c < C; ++c) {
             RETCHK(init_case(c, cbase));
@@ -406,12 +411,22 @@ struct Engine final : EngineBase {
     }
     R4<real>* wmot_arg() const { return any_move() ? wmot : nullptr; }
 
-    // Call f with whether the pair kernels need the moving-wall terms as a
-    // constant (the static instantiation carries none of their code).
+    // Whether any case has walls with given velocities.
+    bool any_wvel() const
+    {
+        for (int c = 0; c < C; ++c)
+            if (hP[c].wvel) return true;
+        return false;
+    }
+    R4<real>* wvg_arg() const { return any_wvel() ? wvg : nullptr; }
+
+    // Call f with whether the pair kernels need the wall-velocity terms (a
+    // motion or given velocities) as a constant (the static instantiation
+    // carries none of their code).
     template <typename F>
     void by_motion(F&& f)
     {
-        if (wmot_arg()) f(std::true_type{});
+        if (any_move() || any_wvel()) f(std::true_type{});
         else f(std::false_type{});
     }
 
@@ -727,7 +742,33 @@ struct Engine final : EngineBase {
         wnrm_h[c].assign(nrm, nrm + n * D);
         hP[c].nw = (int)n;
         hP[c].wmove = 0;  // new walls are static until a motion is given
+        hP[c].wvel = 0;   // and carry no velocity until one is given
         wflag_h[c].clear();
+        wvel_h[c].clear();
+        return upload_walls();
+    }
+
+    // Given velocities of case c's wall particles (n*D in the order the
+    // walls were given; NULL: none). They do not move the walls.
+    int set_wall_velocity(int c, const double* vel) override
+    {
+        RETCHK(check_case(c));
+        KP<real>& P = hP[c];
+        if (!vel) {
+            P.wvel = 0;
+            wvel_h[c].clear();
+            return upload_walls();
+        }
+        const size_t m = (size_t)P.nw * D;
+        bool any = false;
+        for (size_t k = 0; k < m; ++k) {
+            if (!std::isfinite(vel[k])) return ctx->fail(SPHX_EINVAL, case_tag(c) + "bad wall velocity");
+            any = any || vel[k] != 0.0;
+        }
+        // all zero: the walls stay at rest (the static code path)
+        P.wvel = any ? 1 : 0;
+        wvel_h[c].assign(vel, vel + m);
+        if (!any) wvel_h[c].clear();
         return upload_walls();
     }
 
@@ -789,6 +830,8 @@ struct Engine final : EngineBase {
         configured = false;
         free_list(wall_allocs);
         wmot = nullptr;
+        wvin = nullptr;
+        wvg = nullptr;
         int base = 0;
         for (int c = 0; c < C; ++c) {
             hP[c].wbase = base;
@@ -815,6 +858,10 @@ struct Engine final : EngineBase {
         RETCHK(dalloc(L, wrank, wcap));
         RETCHK(dalloc(L, wperm, wcap));
         if (any_move()) RETCHK(dalloc(L, wmot, wcap));
+        if (any_wvel()) {
+            RETCHK(dalloc(L, wvin, (size_t)3 * wcap));
+            RETCHK(dalloc(L, wvg, wcap));
+        }
         size_t nn = (size_t)nw_tot;
         std::vector<double> soa(nn * 6, 0.0);
         std::vector<int32_t> wc(nn), wf(nn);
@@ -832,6 +879,16 @@ struct Engine final : EngineBase {
             HIPCHK(hipMemcpyAsync(wref[k], soa.data() + k * nn, nn * sizeof(double), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(wcase, wc.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(wflag, wf.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        std::vector<double> wv;
+        if (wvin) {
+            wv.assign(3 * nn, 0.0);
+            for (int c = 0; c < C; ++c)
+                if (hP[c].wvel)
+                    for (int i = 0; i < hP[c].nw; ++i)
+                        for (int k = 0; k < D; ++k)
+                            wv[3 * ((size_t)hP[c].wbase + i) + k] = wvel_h[c][(size_t)i * D + k];
+            HIPCHK(hipMemcpyAsync(wvin, wv.data(), wv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        }
         RETCHK(enqueue_wall_sort());
         HIPCHK(hipStreamSynchronize(s));
         return SPHX_OK;
@@ -852,7 +909,7 @@ struct Engine final : EngineBase {
         k_cell_order<<<nblk(ncell), BLOCK, 0, s>>>(ncell, wstart, wperm);
         k_gather_wall<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, ctrl, wflag, n, wperm, wkey, wref[0], wref[1],
                                                           wref[D3], wref[3], wref[4], wref[3 + D3], wx[0], wx[1],
-                                                          wx[2], wgeo, wnrm, wid, wmot_arg());
+                                                          wx[2], wgeo, wnrm, wid, wmot_arg(), wvin, wvg_arg());
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -912,13 +969,14 @@ struct Engine final : EngineBase {
         const int nb = pair_blocks();
         R4<real>* av = avt_arg();
         R4<real>* wm = wmot_arg();
+        R4<real>* wg = wvg_arg();
         by_motion([&](auto mc) {
             constexpr bool MV = decltype(mc)::value;
             k_pressure<D, real, T, MV><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                            st[a], dr3[a], hf, acc, q, adv, vslot, av, wm);
+                                                            st[a], dr3[a], hf, acc, q, adv, vslot, av, wm, wg);
             k_density<D, real, T, MV><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt,
                                                            wnb, wcnt, hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2],
-                                                           dro, vslot, q, av, wm);
+                                                           dro, vslot, q, av, wm, wg);
         });
     }
 
@@ -951,7 +1009,7 @@ struct Engine final : EngineBase {
         by_lanes([&](auto t) {
             by_motion([&](auto mc) {
                 k_adv_forces<D, real, decltype(t)::value, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
-                    dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a], avt, wmot_arg());
+                    dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a], avt, wmot_arg(), wvg_arg());
             });
         });
         HIPCHK(hipGetLastError());
@@ -1261,7 +1319,7 @@ struct Engine final : EngineBase {
     // slot order. A context created with the same parameters continues from
     // a loaded checkpoint exactly as the saved one would (the configuration
     // is rebuilt from the sorted state, which the stable sort leaves as is).
-    static constexpr char CKPT_MAGIC[9] = "SPHXCK01";
+    static constexpr char CKPT_MAGIC[9] = "SPHXCK02";
 
     int save(const char* path) override
     {
@@ -1290,6 +1348,9 @@ struct Engine final : EngineBase {
                                   P.wpivot[2]};
             put(&P.wmove, sizeof(int32_t));
             put(mo, sizeof(mo));
+            const int32_t nwv = (int32_t)wvel_h[c].size();
+            put(&nwv, sizeof(nwv));
+            put(wvel_h[c].data(), wvel_h[c].size() * sizeof(double));
         }
         const size_t n = (size_t)ntot;
         std::vector<double> hx(n);
@@ -1336,6 +1397,7 @@ struct Engine final : EngineBase {
             std::vector<int32_t> fl;
             int32_t wmove;
             double mo[8];
+            std::vector<double> wv;
         };
         std::vector<CaseRec> rec(C);
         int32_t ntot_f = 0;
@@ -1364,6 +1426,11 @@ struct Engine final : EngineBase {
             get(r.fl.data(), r.fl.size() * sizeof(int32_t));
             get(&r.wmove, sizeof(int32_t));
             get(r.mo, sizeof(r.mo));
+            int32_t nwv = 0;
+            get(&nwv, sizeof(nwv));
+            if (!ok || (nwv != 0 && nwv != r.lay[3] * D)) return ctx->fail(SPHX_EINVAL, "corrupt checkpoint walls");
+            r.wv.resize(nwv);
+            get(r.wv.data(), r.wv.size() * sizeof(double));
         }
         if (!ok || ntot_f != hdr[3]) return ctx->fail(SPHX_EINVAL, "truncated or corrupt checkpoint");
         const size_t n = (size_t)hdr[3];
@@ -1409,6 +1476,8 @@ struct Engine final : EngineBase {
             hP[c].wpivot[1] = r.mo[6];
             hP[c].wpivot[2] = r.mo[7];
             wflag_h[c] = r.fl;
+            wvel_h[c] = r.wv;
+            hP[c].wvel = r.wv.empty() ? 0 : 1;
         }
         RETCHK(upload_walls());
         configured = false;
@@ -1479,14 +1548,14 @@ struct Engine final : EngineBase {
             by_motion([&](auto mc) {
                 k_pressure<D, real, T, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
                     dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, nullptr, 0, 0,
-                    vslot, avt_arg(), wmot_arg());
+                    vslot, avt_arg(), wmot_arg(), wvg_arg());
             });
         }));
         RETCHK(time_launches(reps, &ms[1], [&] {
             by_motion([&](auto mc) {
                 k_density<D, real, T, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
                     dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
-                    x[a][1], x[a][2], nullptr, vslot, 0, avt_arg(), wmot_arg());
+                    x[a][1], x[a][2], nullptr, vslot, 0, avt_arg(), wmot_arg(), wvg_arg());
             });
         }));
         // the list build is idempotent on the current set
@@ -1616,6 +1685,7 @@ struct Engine final : EngineBase {
         hP[c].wbase = old.wbase;
         hP[c].nw = old.nw;
         hP[c].wmove = old.wmove;
+        hP[c].wvel = old.wvel;
         for (int k = 0; k < 3; ++k) {
             hP[c].wamp[k] = old.wamp[k];
             hP[c].wpivot[k] = old.wpivot[k];
@@ -1747,7 +1817,7 @@ struct Engine final : EngineBase {
     int gnn_check_ready()
     {
         if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
-        if (any_move()) return ctx->fail(SPHX_EINVAL, "the surrogate models static walls only");
+        if (any_move() || any_wvel()) return ctx->fail(SPHX_EINVAL, "the surrogate models static walls only");
         if (!gn.ready) return ctx->fail(SPHX_ESTATE, "surrogate parameters not set");
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
         return SPHX_OK;
@@ -2057,7 +2127,7 @@ struct Engine final : EngineBase {
                           int64_t* n_surrogate) override
     {
         if (D != 2) return ctx->fail(SPHX_EINVAL, "the surrogate is two-dimensional");
-        if (any_move()) return ctx->fail(SPHX_EINVAL, "the surrogate models static walls only");
+        if (any_move() || any_wvel()) return ctx->fail(SPHX_EINVAL, "the surrogate models static walls only");
         if (!gn.ready) return ctx->fail(SPHX_ESTATE, "surrogate parameters not set");
         if (windows < 0) return ctx->fail(SPHX_EINVAL, "negative window count");
         RETCHK(all_have_fluid());
@@ -2233,6 +2303,13 @@ int sphx_set_wall_motion(sphx_ctx* ctx, const sphx_wall_motion* motion, const in
 int sphx_set_wall_motion_case(sphx_ctx* ctx, int32_t c, const sphx_wall_motion* motion, const int32_t* moving)
 {
     ENG_CALL(set_wall_motion(c, motion, moving));
+}
+
+int sphx_set_wall_velocity(sphx_ctx* ctx, const double* vel) { ENG_CALL(set_wall_velocity(0, vel)); }
+
+int sphx_set_wall_velocity_case(sphx_ctx* ctx, int32_t c, const double* vel)
+{
+    ENG_CALL(set_wall_velocity(c, vel));
 }
 
 int sphx_save(sphx_ctx* ctx, const char* path) { ENG_CALL(save(path)); }

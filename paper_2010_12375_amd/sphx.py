@@ -26,7 +26,8 @@ ERROR_NAMES = {SPHX_EINVAL: "EINVAL", SPHX_ENOMEM: "ENOMEM", SPHX_EHIP: "EHIP", 
 
 EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_set_params_case", "sphx_destroy", "sphx_last_error",
             "sphx_set_fluid", "sphx_set_fluid_case", "sphx_set_walls", "sphx_set_walls_case",
-            "sphx_set_wall_motion", "sphx_set_wall_motion_case", "sphx_set_fluid_device", "sphx_get_field_device",
+            "sphx_set_wall_motion", "sphx_set_wall_motion_case", "sphx_set_wall_velocity", "sphx_set_wall_velocity_case",
+            "sphx_set_fluid_device", "sphx_get_field_device",
             "sphx_save", "sphx_load",
             "sphx_build_neighbors", "sphx_get_neighbors", "sphx_get_neighbors_case", "sphx_density_reinit",
             "sphx_time_steps", "sphx_time_steps_case", "sphx_compute_rates", "sphx_compute_rates_case",
@@ -89,6 +90,8 @@ def load(path=None):
         "sphx_set_walls_case": [vp, i32, i64, vp, vp],
         "sphx_set_wall_motion": [vp, C.POINTER(sphx_wall_motion), vp],
         "sphx_set_wall_motion_case": [vp, i32, C.POINTER(sphx_wall_motion), vp],
+        "sphx_set_wall_velocity": [vp, vp],
+        "sphx_set_wall_velocity_case": [vp, i32, vp],
         "sphx_set_fluid_device": [vp, i32, i64, vp, vp, vp, vp],
         "sphx_get_field_device": [vp, i32, C.c_int, vp],
         "sphx_save": [vp, C.c_char_p],
@@ -283,11 +286,21 @@ class Simulation:
         self._check(self._L.sphx_set_wall_motion_case(self._h, case, C.byref(m), _ptr(flags)),
                     "sphx_set_wall_motion_case")
 
+    def set_wall_velocity(self, vel, case=0):
+        """Given velocities of case `case`'s wall particles (n_wall x dim; None
+        clears them); the walls do not move with them."""
+        v = _f64(vel)
+        self._check(self._L.sphx_set_wall_velocity_case(self._h, case, _ptr(v)), "sphx_set_wall_velocity_case")
+
     def set_case_motion(self, c, case=0):
-        """Apply a workload case's wall motion, if it has one."""
+        """Apply a workload case's wall motion and given wall velocities, if
+        it has them."""
         m = getattr(c, "wall_motion", None)
         if m is not None:
             self.set_wall_motion(m.amp, m.omega, m.roll, m.pivot, getattr(c, "wall_moving", None), case=case)
+        v = getattr(c, "wall_velocity", None)
+        if v is not None:
+            self.set_wall_velocity(v, case=case)
 
     def build_neighbors(self):
         self._check(self._L.sphx_build_neighbors(self._h), "sphx_build_neighbors")

@@ -49,6 +49,10 @@ def make_pair(case, precision, state=None, nsub_queue=0, walls=True):
             mv = getattr(case, "wall_moving", None)
             g.set_wall_motion(m.amp, m.omega, m.roll, m.pivot, mv)
             o.set_wall_motion(amp=m.amp, omega=m.omega, roll=m.roll, pivot=m.pivot, moving=mv)
+        v = getattr(case, "wall_velocity", None)
+        if v is not None:
+            g.set_wall_velocity(v)
+            o.set_wall_velocity(v)
     return g, o
 
 

@@ -167,7 +167,8 @@ def _state(g, case=0):
                                                       sphx.SPHX_FIELD_DRHO)]
 
 
-@pytest.mark.parametrize("which", ["dambreak2d_fp32", "sloshing2d_fp64", "batch_fp32", "dambreak3d_fp32"])
+@pytest.mark.parametrize("which", ["dambreak2d_fp32", "sloshing2d_fp64", "batch_fp32", "dambreak3d_fp32",
+                                   "lidcavity2d_fp64"])
 def test_checkpoint_restart_is_bit_identical(which, tmp_path):
     """Run, save, run on; a fresh context that loads the file and runs on
     ends bit-identical (all cases, clocks and sub-step counts)."""
@@ -176,6 +177,9 @@ def test_checkpoint_restart_is_bit_identical(which, tmp_path):
         prec = FP32
     elif which == "sloshing2d_fp64":
         cases = [wl.sloshing_2d(0.05, roll=0.05)]
+        prec = FP64
+    elif which == "lidcavity2d_fp64":
+        cases = [wl.lid_cavity_2d(0.05, Re=50.0, U=0.5)]
         prec = FP64
     elif which == "batch_fp32":
         cases = [wl.dam_break_2d(0.05, seed=1, L=1.5, H=1.2), wl.dam_break_2d(0.025, seed=2),

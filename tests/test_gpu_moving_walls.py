@@ -225,3 +225,115 @@ def test_surrogate_refuses_moving_walls():
     with pytest.raises(sphx.SphxError):
         g.gnn_set_params(gi.init_params(0, 0.3))
         g.gnn_forward()
+
+
+def lid(dp=0.05, precision=FP64, jitter=0.2):
+    return wl.lid_cavity_2d(dp, Re=50.0, U=0.5, seed=3, jitter=jitter, precision=precision)
+
+
+def sliding_slosh(precision=FP64):
+    """Sway and roll plus a given velocity on the floor (a belt): both wall
+    velocities add."""
+    case = slosh(0.05, roll=0.08, precision=precision)
+    case.eta = 0.01
+    v = np.zeros((case.n_wall, 2))
+    v[case.wall_pos[:, 1] < 0.0, 0] = 0.3
+    case.wall_velocity = v
+    return case
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-9), (FP32, 1e-4)])
+@pytest.mark.parametrize("which", ["couette", "lid_cavity", "belt_in_sloshing_tank"])
+def test_rates_parity_with_given_wall_velocities(which, precision, tol):
+    """Rates with walls carrying given velocities (a sliding lid or belt, no
+    slip): the velocity in the wall Riemann states and in the shear."""
+    if which == "couette":
+        case = wl.couette_2d(precision=precision)
+    elif which == "lid_cavity":
+        case = lid(0.025, precision)
+    else:
+        case = sliding_slosh(precision)
+    st = developed_state(case, seed=7, speed=0.1)
+    g, o = make_pair(case, precision, st)
+    g.build_neighbors()
+    o.build_config()
+    dt_ad, dt_ac = o.time_steps()
+    ag, dg = g.compute_rates(dt_ac)
+    ao, do = o.compute_rates(dt_ac)
+    ea, ed = rate_errors(ag, ao, dg, do, gmag=1.0)
+    say(which, precision, "max err a", ea.max(), "drho", ed.max())
+    assert ea.max() <= tol and ed.max() <= tol
+    # the velocities matter: without them the rates differ
+    g.set_wall_velocity(None)
+    g.build_neighbors()
+    a0, _ = g.compute_rates(dt_ac)
+    assert np.abs(a0 - ag).max() > 100 * tol * (np.abs(ao).max() + 1.0)
+
+
+@pytest.mark.parametrize("which", ["couette", "lid_cavity", "belt_in_sloshing_tank"])
+def test_fp64_runs_with_given_wall_velocities_track_the_oracle(which):
+    if which == "couette":
+        case, stops = wl.couette_2d(), [0.1, 0.3]
+    elif which == "lid_cavity":
+        case, stops = lid(), [0.1, 0.25]
+    else:
+        case, stops = sliding_slosh(), [0.2, 0.4]
+    g, o = make_pair(case, FP64)
+    for dg, do in run_to(g, o, stops):
+        assert dg["t"] == pytest.approx(do["t"], abs=1e-12)
+        assert dg["e_kin"] == pytest.approx(do["e_kin"], rel=1e-9, abs=1e-14)
+    d = np.abs(g.get_field(sphx.SPHX_FIELD_POS) - o.field(O.FIELD_POS))
+    if case.periodic[0]:
+        per = case.hi[0] - case.lo[0]
+        d[:, 0] = np.minimum(d[:, 0], per - d[:, 0])
+    say(which, "max position difference", d.max())
+    assert d.max() < 1e-8
+
+
+def test_fp32_lid_cavity_within_one_percent():
+    case = lid(0.025, FP32, jitter=0.0)
+    g, o = make_pair(case, FP32)
+    o.build_config()
+    for dg, do in run_to(g, o, [0.2, 0.4]):
+        say("t", do["t"], "E_kin", dg["e_kin"], do["e_kin"])
+        assert abs(dg["e_kin"] - do["e_kin"]) <= 0.01 * abs(do["e_kin"])
+
+
+def test_given_wall_velocities_in_a_batch_and_all_zero():
+    """A batch of a lid cavity, a dam break and a belt-driven sloshing tank
+    is bit-identical to the single runs; all-zero given velocities are the
+    static walls bit for bit; set_walls clears them."""
+    cases = [lid(), wl.dam_break_2d(0.05, seed=4), sliding_slosh()]
+    batch = sphx.Simulation.from_cases(cases, FP64, nsub_queue=2)
+    batch.advance(20)
+    for k, c in enumerate(cases):
+        one = sphx.Simulation.from_case(c, FP64, nsub_queue=2)
+        one.advance(20)
+        for a, b in zip(_fields(batch, k), _fields(one)):
+            assert np.array_equal(a, b), c.name
+        one.close()
+    case = lid()
+    zero = sphx.Simulation.from_case(case, FP64)
+    zero.set_wall_velocity(np.zeros_like(case.wall_velocity))
+    case.wall_velocity = None
+    static = sphx.Simulation.from_case(case, FP64)
+    reset = sphx.Simulation.from_case(lid(), FP64)
+    reset.set_walls(case.wall_pos, case.wall_normal)
+    for s in (zero, static, reset):
+        s.advance(15)
+    for a, b, c in zip(_fields(zero), _fields(static), _fields(reset)):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+    with pytest.raises(sphx.SphxError) as e:
+        v = np.zeros((case.n_wall, 2))
+        v[3, 1] = float("inf")
+        static.set_wall_velocity(v)
+    assert e.value.code == sphx.SPHX_EINVAL
+
+
+def test_surrogate_refuses_given_wall_velocities():
+    from paper_2010_12375_amd import gnn_inputs as gi
+    g = sphx.Simulation.from_case(lid(), FP32)
+    g.build_neighbors()
+    with pytest.raises(sphx.SphxError):
+        g.gnn_set_params(gi.init_params(0, 0.3))
+        g.gnn_forward()
