@@ -241,7 +241,9 @@ def main():
     ap.add_argument("--test-cases", type=int, default=32, help="surrogate: held-out trajectories")
     ap.add_argument("--train-iters", type=int, default=2000, help="surrogate: Adam steps (16 snapshots each)")
     ap.add_argument("--windows", type=int, default=250, help="surrogate: evaluation windows (2 advection steps)")
-    ap.add_argument("--autotune", action="store_true", help="pick the pair-kernel lanes per particle first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the pair-kernel lanes per particle first (always for the ensemble)")
+    ap.add_argument("--lanes", type=int, default=0, help="pair-kernel lanes per particle (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads for cpu_baseline (0: all)")
@@ -313,7 +315,12 @@ def main():
         n_wall = sum(c.n_wall for c in cases)
         name = f"ensemble64_dambreak2d ({n_fluid} fluid particles in 64 cases)"
     sim.build_neighbors()
-    lanes = sim.autotune(10) if args.autotune else None
+    lanes = None
+    if args.lanes:
+        sim.set_lanes(args.lanes)
+        lanes = args.lanes
+    if args.autotune or (cases is not None and not args.lanes):
+        lanes = sim.autotune(10)
     sim.advance(args.warmup)
     if torch is not None:
         torch.cuda.synchronize()

@@ -307,14 +307,22 @@ int sphx_profile(sphx_ctx* ctx, int32_t reps, double* ms);
 int sphx_counts(sphx_ctx* ctx, int64_t* out);
 int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out);
 
-/* Choose the lanes per particle of the pair kernels (4, 8 or 16) by timing
- * `reps` launches of the pressure and density relaxation of the batch with
- * each, and rebuild the configuration for the fastest one (*lanes, may be
- * NULL; times, may be NULL: 3 entries, ms per relaxation pair for 4, 8, 16
- * lanes). The lists are the same; the per-particle sums are combined in a
+/* Choose the lanes per particle of the pair kernels (2, 4 or 8 in 2D; 4, 8
+ * or 16 in 3D) by timing `reps` launches of the pressure and density
+ * relaxation of the batch with each, and rebuild the configuration for the
+ * fastest one (*lanes, may be NULL; times, may be NULL: 3 entries, ms per
+ * relaxation pair for the three candidates in that order). The lists are the same; the per-particle sums are combined in a
  * different order, so later results can differ from the default's at
  * rounding level. Requires a configuration. */
 int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes, double* times);
+
+/* Set the lanes per particle of the pair kernels (2, 4 or 8 in 2D, default
+ * 4; 4, 8 or 16 in 3D, default 8), e.g. a value sphx_autotune picked
+ * before. An existing configuration is rebuilt from the current state in
+ * the new list layout, as by sphx_build_neighbors (the same lists; sums are
+ * then combined in another order). Call between advances. SPHX_EINVAL for
+ * another value. */
+int sphx_set_lanes(sphx_ctx* ctx, int32_t lanes);
 
 /* ---------------------------------------------------------------------
  * Message-passing surrogate (2D contexts only; SPHX_EINVAL in 3D).

@@ -1089,13 +1089,20 @@ __device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int
     }
 }
 
-// Pair kernels: BLOCK threads, T lanes per particle, BLOCK / T <= TILE
-// particles per block, so a block lies inside one tile (one case).
+// Pair kernels: T lanes per particle and pair_threads<T>() threads per
+// block (BLOCK, or the T * TILE lanes of one tile where that is fewer), so a
+// block lies inside one tile (one case).
+template <int T>
+__host__ __device__ constexpr int pair_threads()
+{
+    return T * TILE < BLOCK ? T * TILE : BLOCK;
+}
+
 template <int T>
 __device__ __forceinline__ int pair_block_first(int b)
 {
-    static_assert(T >= BLOCK / TILE && T <= 64, "a pair-kernel block must lie inside one tile");
-    return b * (BLOCK / T);
+    static_assert(T >= 1 && T <= 64 && 64 % T == 0, "lane groups must tile a wavefront");
+    return b * (pair_threads<T>() / T);
 }
 
 // S4: density re-initialisation rho = max(rho*, rho0 sum W / sum W0) with
@@ -1600,7 +1607,7 @@ __device__ __forceinline__ void density_body(
     __syncthreads();
     if (threadIdx.x == 0) {
         double bm = smax[0];
-        for (int w = 1; w < BLOCK / 64; ++w) bm = fmax(bm, smax[w]);
+        for (int w = 1; w < pair_threads<T>() / 64; ++w) bm = fmax(bm, smax[w]);
         // relaxed, result unused: no wait, no fence; read after the kernel ends
         unsigned long long* vslot = vslot_all + (size_t)P.case_id * 2 * VSLOTS;
         atomicMax(&vslot[(q & 1) * VSLOTS + (b & (VSLOTS - 1))], speed_bits((real)bm));

@@ -76,6 +76,7 @@ struct EngineBase {
     virtual int profile(int32_t reps, double* ms) = 0;
     virtual int counts(int c, int64_t* out) = 0;
     virtual int autotune(int32_t reps, int32_t* lanes, double* times) = 0;
+    virtual int set_lanes(int32_t lanes) = 0;
     virtual int set_params_case(int c, const sphx_params* q) = 0;
     virtual int gnn_set_params(const float* p, int64_t n) = 0;
     virtual int gnn_get(int which, float* p, int64_t n) = 0;
@@ -121,7 +122,7 @@ struct Engine final : EngineBase {
     sphx_ctx* ctx;
     hipStream_t s;
     static constexpr int LB = 4;  // lanes per particle in the neighbour build (one tile per block)
-    int ln = D == 2 ? 4 : 8;      // lanes per particle in the pair kernels (4 or 8)
+    int ln = D == 2 ? 4 : 8;      // lanes per particle in the pair kernels (2, 4, 8 or 16)
     int C = 0;                    // cases
     std::vector<KP<real>> hP;     // parameter table (host copy)
     KP<real>* dP = nullptr;
@@ -391,7 +392,7 @@ struct Engine final : EngineBase {
 
     int nblk_scan() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
     int nblk_lb() const { return (ncell + LB_TILE - 1) / LB_TILE; }
-    int pair_blocks() const { return (int)((long long)ntot * ln / BLOCK); }
+    int pair_blocks() const { return (int)((long long)ntot * ln / (ln * TILE < BLOCK ? ln * TILE : BLOCK)); }
 
     // Whether any case has a shear force or a transport-velocity correction.
     bool any_adv() const
@@ -434,6 +435,12 @@ struct Engine final : EngineBase {
     template <typename F>
     void by_lanes(F&& f)
     {
+        if constexpr (D == 2) {
+            if (ln == 2) {
+                f(std::integral_constant<int, 2>{});
+                return;
+            }
+        }
         if (ln == 4) f(std::integral_constant<int, 4>{});
         else if (ln == 8) f(std::integral_constant<int, 8>{});
         else f(std::integral_constant<int, 16>{});
@@ -972,9 +979,9 @@ struct Engine final : EngineBase {
         R4<real>* wg = wvg_arg();
         by_motion([&](auto mc) {
             constexpr bool MV = decltype(mc)::value;
-            k_pressure<D, real, T, MV><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+            k_pressure<D, real, T, MV><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
                                                             st[a], dr3[a], hf, acc, q, adv, vslot, av, wm, wg);
-            k_density<D, real, T, MV><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt,
+            k_density<D, real, T, MV><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt,
                                                            wnb, wcnt, hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2],
                                                            dro, vslot, q, av, wm, wg);
         });
@@ -993,7 +1000,7 @@ struct Engine final : EngineBase {
     {
         const int nb = pair_blocks();
         by_lanes([&](auto t) {
-            k_reinit<D, real, decltype(t)::value><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt,
+            k_reinit<D, real, decltype(t)::value><<<nb, pair_threads<decltype(t)::value>(), 0, s>>>(dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt,
                                                                       wnb, wcnt, st[a]);
         });
         HIPCHK(hipGetLastError());
@@ -1008,7 +1015,7 @@ struct Engine final : EngineBase {
         const int nb = pair_blocks();
         by_lanes([&](auto t) {
             by_motion([&](auto mc) {
-                k_adv_forces<D, real, decltype(t)::value, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
+                k_adv_forces<D, real, decltype(t)::value, decltype(mc)::value><<<nb, pair_threads<decltype(t)::value>(), 0, s>>>(
                     dP, tcase, ctrl, gate, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a], avt, wmot_arg(), wvg_arg());
             });
         });
@@ -1087,7 +1094,8 @@ struct Engine final : EngineBase {
 
     size_t ell_index(int i, int k, int mx) const
     {
-        return ln == 4 ? ell_at<4>(i, k, mx) : ln == 8 ? ell_at<8>(i, k, mx) : ell_at<16>(i, k, mx);
+        return ln == 2 ? ell_at<2>(i, k, mx)
+               : ln == 4 ? ell_at<4>(i, k, mx) : ln == 8 ? ell_at<8>(i, k, mx) : ell_at<16>(i, k, mx);
     }
 
     int get_neighbors(int c, int kind, int64_t* off, int64_t* idx, int64_t cap_idx, int64_t* n_out) override
@@ -1546,14 +1554,14 @@ struct Engine final : EngineBase {
         const int a = cur;
         RETCHK(time_launches(reps, &ms[0], [&] {
             by_motion([&](auto mc) {
-                k_pressure<D, real, T, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
+                k_pressure<D, real, T, decltype(mc)::value><<<nb, pair_threads<T>(), 0, s>>>(
                     dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, nullptr, 0, 0,
                     vslot, avt_arg(), wmot_arg(), wvg_arg());
             });
         }));
         RETCHK(time_launches(reps, &ms[1], [&] {
             by_motion([&](auto mc) {
-                k_density<D, real, T, decltype(mc)::value><<<nb, BLOCK, 0, s>>>(
+                k_density<D, real, T, decltype(mc)::value><<<nb, pair_threads<T>(), 0, s>>>(
                     dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
                     x[a][1], x[a][2], nullptr, vslot, 0, avt_arg(), wmot_arg(), wvg_arg());
             });
@@ -1561,7 +1569,7 @@ struct Engine final : EngineBase {
         // the list build is idempotent on the current set
         RETCHK(time_launches(reps, &ms[2], [&] { launch_neighbors<T>(1, a); }));
         RETCHK(time_launches(reps, &ms[3], [&] {
-            k_reinit<D, real, T><<<nb, BLOCK, 0, s>>>(dP, tcase, ctrl, 0, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
+            k_reinit<D, real, T><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, 0, geo[a], wgeo, nbr, ncnt, wnb, wcnt, st[a]);
         }));
         return SPHX_OK;
     }
@@ -1621,7 +1629,8 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
-    // Pick the lanes per particle of the pair kernels (4, 8 or 16) by timing
+    // Pick the lanes per particle of the pair kernels (2, 4 or 8 in 2D; 4, 8
+    // or 16 in 3D) by timing
     // the pressure and density relaxations of every case with each; the lists
     // are rebuilt in the chosen layout (the same lists; sums are combined in
     // a different order, so results change at rounding level).
@@ -1629,7 +1638,7 @@ struct Engine final : EngineBase {
     {
         if (!configured) return ctx->fail(SPHX_ESTATE, "no neighbour configuration");
         if (reps < 1) return ctx->fail(SPHX_EINVAL, "bad repetition count");
-        const int cand[3] = {4, 8, 16};
+        const int cand[3] = {D == 2 ? 2 : 4, D == 2 ? 4 : 8, D == 2 ? 8 : 16};
         double tk[3] = {1e300, 1e300, 1e300};
         // each candidate timed twice, in forward then in reverse order (the
         // first launches after a rebuild run on a cold GPU); its best counts
@@ -1656,6 +1665,20 @@ struct Engine final : EngineBase {
         drop_graphs();
         RETCHK(build_neighbors());
         if (lanes) *lanes = ln;
+        return SPHX_OK;
+    }
+
+    // Set the lanes per particle of the pair kernels; an existing
+    // configuration is rebuilt in the new list layout (the same lists).
+    int set_lanes(int32_t lanes) override
+    {
+        const bool ok = D == 2 ? (lanes == 2 || lanes == 4 || lanes == 8) : (lanes == 4 || lanes == 8 || lanes == 16);
+        if (!ok) return ctx->fail(SPHX_EINVAL, "lanes per particle: 2, 4 or 8 in 2D; 4, 8 or 16 in 3D");
+        if (lanes == ln) return SPHX_OK;
+        HIPCHK(hipStreamSynchronize(s));
+        ln = lanes;
+        drop_graphs();
+        if (configured) RETCHK(build_neighbors());
         return SPHX_OK;
     }
 
@@ -2378,6 +2401,8 @@ int sphx_profile(sphx_ctx* ctx, int32_t reps, double* ms) { ENG_CALL(profile(rep
 int sphx_counts(sphx_ctx* ctx, int64_t* out) { ENG_CALL(counts(-1, out)); }
 
 int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out) { ENG_CALL(counts(c, out)); }
+
+int sphx_set_lanes(sphx_ctx* ctx, int32_t lanes) { ENG_CALL(set_lanes(lanes)); }
 
 int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes, double* times)
 {
