@@ -944,7 +944,10 @@ struct Engine final : EngineBase {
     template <int T>
     void launch_neighbors(int force, int b, int reinit = 0)
     {
-        k_neighbors<D, real, T, LB><<<ntiles, TILE * LB, 0, s>>>(dP, tcase, ctrl, force, x[b][0], x[b][1], x[b][2],
+        // with two lanes per particle in the pair kernels (large 2D batches,
+        // issue-bound) the build packs two lanes per particle as well
+        constexpr int TB = T < LB ? T : LB;
+        k_neighbors<D, real, T, TB><<<ntiles, TILE * TB, 0, s>>>(dP, tcase, ctrl, force, x[b][0], x[b][1], x[b][2],
                                                                 cell[b], fstart, geo[b], wx[0], wx[1], wx[2], wstart,
                                                                 wgeo, nbr, ncnt, wnb, wcnt, reinit, st[b]);
     }
