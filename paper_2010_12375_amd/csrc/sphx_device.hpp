@@ -113,6 +113,8 @@ template <typename real> struct KP {
     real two_m, m, two_vw, vw;                // particle mass and wall volume
     double md;                                // particle mass in FP64 (diagnostics)
     real inv_h, Wc, dWc;                      // Wendland: Wc = a/h^d, dWc = -5a/h^(d+1)
+    real s_r, dWr;                            // -1/(2h), dWc/h: dW/dr = dWr r (1 + s_r r)^3
+    real quarter_c;                           // c/4 (bound of the limiter beta/4)
     real g[3];
     real L[3];                                // cell size per axis
     double Ld[3], lo[3], hi[3], period[3], half_period[3];
@@ -173,6 +175,9 @@ __device__ __forceinline__ int wave_tile()
 
 template <typename T> __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
 template <typename T> __device__ __forceinline__ T dmin(T a, T b) { return a < b ? a : b; }
+// x clamped to [0, hi] for hi >= 0 (FP32: one median-of-three instruction)
+__device__ __forceinline__ float clamp0(float x, float hi) { return __builtin_amdgcn_fmed3f(x, 0.0f, hi); }
+__device__ __forceinline__ double clamp0(double x, double hi) { return dmin(dmax(x, 0.0), hi); }
 
 // hardware reciprocal square root (about 1 ulp), far inside the FP32 budget
 __device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -292,19 +297,26 @@ __device__ __forceinline__ double pair_r2(const KP<real>& P, const double* xi, c
     return r2;
 }
 
-// Frozen pair geometry from cell offsets: returns e_ij (from i to j),
-// r_ij and dW/dr of the Wendland C2 kernel with support 2h.
+// Frozen pair geometry from cell offsets: d = x_i - x_j, 1/r_ij, r_ij,
+// e_ij = -d/r (from i to j) and dW/dr of the Wendland C2 kernel with
+// support 2h. The pair loops use d and 1/r where that saves the products of
+// e (e.g. (v_i - v_j) . e_ij = -(v_i - v_j) . d / r); the compiler drops
+// what a caller does not use. A neighbour's cell code c in {0, 1, 2} per
+// axis enters as d = (o_i - o_j) - (c - 1) L.
 template <int D, typename real> struct Pair {
+    real d[3];
+    real rinv;
     real e[3];
     real r;
     real dW;
+    real dW_r;  // dW/dr / r
 };
 
 template <int D, typename real, typename G>
 __device__ __forceinline__ Pair<D, real> pair_geo(const KP<real>& P, const G& oi, const G& oj, uint32_t code)
 {
     Pair<D, real> q;
-    real dx[3];
+    real* dx = q.d;
     dx[0] = (oi.x - oj.x) - (real)((int)(code & 3u) - 1) * P.L[0];
     dx[1] = (oi.y - oj.y) - (real)((int)((code >> 2) & 3u) - 1) * P.L[1];
     if constexpr (D == 3) dx[2] = (oi.z - oj.z) - (real)((int)((code >> 4) & 3u) - 1) * P.L[2];
@@ -312,10 +324,12 @@ __device__ __forceinline__ Pair<D, real> pair_geo(const KP<real>& P, const G& oi
     real r2 = dx[0] * dx[0] + dx[1] * dx[1] + (D == 3 ? dx[2] * dx[2] : (real)0);
     real rinv = rsqrt_r(r2);
     real r = r2 * rinv;
-    real qh = r * P.inv_h;
-    real s = dmax((real)1 - (real)0.5 * qh, (real)0);
-    q.dW = P.dWc * qh * s * s * s;
+    // listed pairs have r < 2h (up to the rounding of r), so 1 - r/(2h) >= 0
+    real s = (real)1 + P.s_r * r;
+    q.dW_r = P.dWr * s * s * s;
+    q.dW = q.dW_r * r;
     q.r = r;
+    q.rinv = rinv;
     q.e[0] = -dx[0] * rinv;
     q.e[1] = -dx[1] * rinv;
     q.e[2] = -dx[2] * rinv;
@@ -1324,6 +1338,8 @@ __device__ __forceinline__ void pressure_body(
     const real rho_i = P.rho0 + dev_i;
     const real p_i = P.c2 * dev_i;
     const real inv_rho_i = (real)1 / rho_i;
+    const real mi = P.two_m * inv_rho_i;   // 2 m / rho_i
+    const real wi = P.two_vw * inv_rho_i;  // 2 V_w / rho_i
     const G oi = geo[i];
     real acc[3] = {0, 0, 0};
     struct FluidJ { G o; R4<real> s; real dr; };
@@ -1342,17 +1358,19 @@ __device__ __forceinline__ void pressure_body(
             Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const R4<real>& sj = r.s;
             real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * r.dr;
-            real UL = vi[0] * pq.e[0] + vi[1] * pq.e[1] + (D == 3 ? vi[2] * pq.e[2] : (real)0);
-            real UR = sj.x * pq.e[0] + sj.y * pq.e[1] + (D == 3 ? sj.z * pq.e[2] : (real)0);
+            // U_L - U_R = (v_i - v_j) . e_ij = -(v_i - v_j) . d / r
+            real dvd = (vi[0] - sj.x) * pq.d[0] + (vi[1] - sj.y) * pq.d[1] +
+                       (D == 3 ? (vi[2] - sj.z) * pq.d[2] : (real)0);
+            real du = -dvd * pq.rinv;
             real rho_j = P.rho0 + dev_j;
             real p_j = P.c2 * dev_j;
-            real du = UL - UR;
-            real beta = dmin((real)3 * dmax(du, (real)0), P.c);
-            real ps = (real)0.5 * (p_i + p_j) + (real)0.25 * beta * (rho_i + rho_j) * du;
-            real coef = div_r(P.two_m * ps * inv_rho_i, rho_j) * pq.dW;
-            acc[0] += coef * pq.e[0];
-            acc[1] += coef * pq.e[1];
-            if (D == 3) acc[2] += coef * pq.e[2];
+            real qbeta = clamp0((real)0.75 * du, P.quarter_c);  // beta / 4 = min(3 max(du, 0), c) / 4
+            real ps = (real)0.5 * (p_i + p_j) + qbeta * (rho_i + rho_j) * du;
+            // coef e_ij with coef = 2 m ps W' / (rho_i rho_j), e_ij = -d / r
+            real cd = div_r(mi * ps, rho_j) * pq.dW_r;
+            acc[0] -= cd * pq.d[0];
+            acc[1] -= cd * pq.d[1];
+            if (D == 3) acc[2] -= cd * pq.d[2];
         });
     for_pairs<T, BATCH>(
         wnb, i, wcnt[i], P.maxw, l,
@@ -1377,15 +1395,16 @@ __device__ __forceinline__ void pressure_body(
                 uw = -(nw.x * vw[0] + nw.y * vw[1] + (D == 3 ? zc(nw) * vw[2] : (real)0));
             }
             real du = (real)2 * (UL - uw);  // U_L - U_R with U_R = -U_L + 2 u_w
-            real gr = pq.r * (P.g[0] * pq.e[0] + P.g[1] * pq.e[1] + (D == 3 ? P.g[2] * pq.e[2] : (real)0));
+            // g . r_fw with r_fw = x_w - x_i = -d
+            real gr = -(P.g[0] * pq.d[0] + P.g[1] * pq.d[1] + (D == 3 ? P.g[2] * pq.d[2] : (real)0));
             real pR = p_i + rho_i * gr;
             real rhoR = P.rho0 + pR * P.inv_c2;
-            real beta = dmin((real)3 * dmax(du, (real)0), P.c);
-            real ps = (real)0.5 * (p_i + pR) + (real)0.25 * beta * (rho_i + rhoR) * du;
-            real coef = P.two_vw * ps * inv_rho_i * pq.dW;
-            acc[0] += coef * pq.e[0];
-            acc[1] += coef * pq.e[1];
-            if (D == 3) acc[2] += coef * pq.e[2];
+            real qbeta = clamp0((real)0.75 * du, P.quarter_c);  // beta / 4
+            real ps = (real)0.5 * (p_i + pR) + qbeta * (rho_i + rhoR) * du;
+            real cd = wi * ps * pq.dW_r;
+            acc[0] -= cd * pq.d[0];
+            acc[1] -= cd * pq.d[1];
+            if (D == 3) acc[2] -= cd * pq.d[2];
         });
     acc[0] = group_sum<T>(acc[0]);
     acc[1] = group_sum<T>(acc[1]);
@@ -1487,6 +1506,7 @@ __device__ __forceinline__ void density_body(
         const real dev_i = D == 2 ? hi_.z : hi_.w;
         const real rho_i = P.rho0 + dev_i;
         const real p_i = P.c2 * dev_i;
+        const real two_c = (real)2 * P.c, half_m = (real)0.5 * P.m;
         const G oi = geo[i];
         // the particle's own state for the final half-steps, loaded ahead of
         // the pair loop so that its latency hides behind it
@@ -1515,14 +1535,16 @@ __device__ __forceinline__ void density_body(
                 Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
                 const R4<real>& hj = r.h;
                 real dev_j = D == 2 ? hj.z : hj.w;
-                real UL = vi[0] * pq.e[0] + vi[1] * pq.e[1] + (D == 3 ? vi[2] * pq.e[2] : (real)0);
-                real UR = hj.x * pq.e[0] + hj.y * pq.e[1] + (D == 3 ? hj.z * pq.e[2] : (real)0);
+                // U_R - U_L = (v_j - v_i) . e_ij = (v_i - v_j) . d / r
+                real dvd = (vi[0] - hj.x) * pq.d[0] + (vi[1] - hj.y) * pq.d[1] +
+                           (D == 3 ? (vi[2] - hj.z) * pq.d[2] : (real)0);
                 real rho_j = P.rho0 + dev_j;
-                real p_j = P.c2 * dev_j;
                 real inv_rho_j = div_r((real)1, rho_j);
-                real rho_bar = (real)0.5 * (rho_i + rho_j);
-                real us = (real)0.5 * (UL + UR) + div_r((p_i - p_j) * P.half_inv_c, rho_bar);
-                sum += P.m * inv_rho_j * (us - UL) * pq.dW;
+                // U* - U_L = (U_R - U_L) / 2 + (p_i - p_j) / (2 rho_bar c) with
+                // rho_bar = (rho_i + rho_j) / 2 and p = c^2 (rho - rho0):
+                // 2 (U* - U_L) = (v_i - v_j) . d / r + 2 c (dev_i - dev_j) / (rho_i + rho_j)
+                real dus2 = dvd * pq.rinv + div_r(two_c * (dev_i - dev_j), rho_i + rho_j);
+                sum += half_m * inv_rho_j * dus2 * pq.dW;
             });
         for_pairs<T, BATCH>(
             wnb, i, wcnt[i], P.maxw, l,
@@ -1539,7 +1561,8 @@ __device__ __forceinline__ void density_body(
                 Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
                 const G& nw = r.n;
                 real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
-                real gr = pq.r * (P.g[0] * pq.e[0] + P.g[1] * pq.e[1] + (D == 3 ? P.g[2] * pq.e[2] : (real)0));
+                // g . r_fw with r_fw = x_w - x_i = -d
+                real gr = -(P.g[0] * pq.d[0] + P.g[1] * pq.d[1] + (D == 3 ? P.g[2] * pq.d[2] : (real)0));
                 real pR = p_i + rho_i * gr;
                 real rhoR = P.rho0 + pR * P.inv_c2;
                 real rho_bar = (real)0.5 * (rho_i + rhoR);

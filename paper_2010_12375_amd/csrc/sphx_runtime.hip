@@ -267,6 +267,9 @@ struct Engine final : EngineBase {
         P.inv_h = (real)(1.0 / h);
         P.Wc = (real)(alpha / std::pow(h, D));
         P.dWc = (real)(-5.0 * alpha / std::pow(h, D + 1));
+        P.s_r = (real)(-0.5 / h);
+        P.dWr = (real)(-5.0 * alpha / std::pow(h, D + 2));
+        P.quarter_c = (real)(0.25 * q.c0);
         for (int k = 0; k < 3; ++k) P.g[k] = (real)(k < D ? q.gravity[k] : 0.0);
         double rc = 2.0 * h;
         long long nc = 1;
