@@ -447,26 +447,21 @@ __device__ __forceinline__ bool full_update(const Ctrl* ctrl, int force) { retur
 // queue (q >= 0) each wavefront decides itself whether its case takes a full
 // update (update_due); escape and NaN bits go to err_pending, which the
 // scan's step_end folds in.
-template <typename real> __device__ __forceinline__ bool update_due(const KP<real>&, const Ctrl* __restrict__,
-                                                                    const unsigned long long* __restrict__, int, int);
+template <typename real> __device__ __forceinline__ bool update_due(const KP<real>&, const Ctrl* __restrict__, int,
+                                                                    int);
+
+// Bin the slots [i0, i0 + n) of one case (n <= 64), one per lane of the
+// calling wavefront: full update from the positions, else the kept cell.
 template <int D, typename real>
-__global__ __launch_bounds__(BLOCK) void k_bin(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
-                                               int ntiles, Ctrl* __restrict__ ctrl_all, int force,
-                                               double* __restrict__ x0, double* __restrict__ x1,
-                                               double* __restrict__ x2, const int32_t* __restrict__ cell,
-                                               int32_t* __restrict__ key, int32_t* __restrict__ rank,
-                                               int32_t* __restrict__ cnt,
-                                               const unsigned long long* __restrict__ vslot_all, int q)
+__device__ __forceinline__ void bin_slots(const KP<real>& P, Ctrl* __restrict__ ctrl, bool full, int i0, int n,
+                                          double* __restrict__ x0, double* __restrict__ x1, double* __restrict__ x2,
+                                          const int32_t* __restrict__ cell, int32_t* __restrict__ key,
+                                          int32_t* __restrict__ rank, int32_t* __restrict__ cnt)
 {
-    const int tile = wave_tile();
-    if (tile >= ntiles) return;
-    const KP<real>& P = Pt[tcase[tile]];
-    Ctrl* ctrl = ctrl_all + P.case_id;
     const int lane = threadIdx.x & 63;
-    const int i = tile * TILE + lane;
-    const bool full = update_due(P, ctrl, vslot_all + (size_t)P.case_id * 2 * VSLOTS, force, q);
-    if (lane == 0 && i + TILE == P.fbase + P.fcap) cnt[P.cbase + P.ncell] = P.fcap - P.nf;
-    const bool act = i < P.fbase + P.nf;  // the active lanes are a prefix of the wavefront
+    const int i = i0 + lane;
+    if (lane == 0 && i0 % TILE == 0 && i0 + TILE == P.fbase + P.fcap) cnt[P.cbase + P.ncell] = P.fcap - P.nf;
+    const bool act = lane < n && i < P.fbase + P.nf;  // the active lanes are a prefix of the wavefront
     int kc = -1;
     if (!act) {
     } else if (!full) {
@@ -512,6 +507,21 @@ __global__ __launch_bounds__(BLOCK) void k_bin(const KP<real>* __restrict__ Pt, 
     if (!act) return;
     key[i] = kc;
     rank[i] = base + (lane - h);
+}
+
+template <int D, typename real>
+__global__ __launch_bounds__(BLOCK) void k_bin(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
+                                               int ntiles, Ctrl* __restrict__ ctrl_all, int force,
+                                               double* __restrict__ x0, double* __restrict__ x1,
+                                               double* __restrict__ x2, const int32_t* __restrict__ cell,
+                                               int32_t* __restrict__ key, int32_t* __restrict__ rank,
+                                               int32_t* __restrict__ cnt, int q)
+{
+    const int tile = wave_tile();
+    if (tile >= ntiles) return;
+    const KP<real>& P = Pt[tcase[tile]];
+    Ctrl* ctrl = ctrl_all + P.case_id;
+    bin_slots<D>(P, ctrl, update_due(P, ctrl, force, q), tile * TILE, TILE, x0, x1, x2, cell, key, rank, cnt);
 }
 
 // Exclusive scan of cell counts in three passes (block sums, scan of block
@@ -1649,20 +1659,33 @@ __attribute__((amdgpu_waves_per_eu((D == 2 && !MOVE) ? 8 : 1))) void k_density(
     const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
     double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
     unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt,
-    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
+    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg, int bin,
+    const int32_t* __restrict__ cell, int32_t* __restrict__ key, int32_t* __restrict__ rank,
+    int32_t* __restrict__ cnt)
 {
-    if constexpr (MOVE) {
-        // cases with static walls run the static instantiation's code
-        if (!wall_velocity_case(Pt, tcase, pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)))) {
-            density_body<D, real, T, false>(
-                Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2,
-                drho_out, vslot_all, q, avt, wmot, wvg);
-            return;
-        }
+    const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
+    bool static_code = !MOVE;
+    if constexpr (MOVE) static_code = !wall_velocity_case(Pt, tcase, i0);
+    // cases with static walls run the static instantiation's code
+    if (static_code) {
+        density_body<D, real, T, false>(
+            Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2,
+            drho_out, vslot_all, q, avt, wmot, wvg);
+    } else {
+        density_body<D, real, T, MOVE>(
+            Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2,
+            drho_out, vslot_all, q, avt, wmot, wvg);
     }
-    density_body<D, real, T, MOVE>(
-        Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2, drho_out,
-        vslot_all, q, avt, wmot, wvg);
+    if (!bin) return;
+    // Last sub-step of a queue: the cell binning of the configuration update
+    // (S1) for this block's slots, from the positions the block has just
+    // written (every case, also one whose sub-steps are over), one
+    // launch less per queue.
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const KP<real>& P = Pt[tcase[i0 / TILE]];
+    Ctrl* ctrl = ctrl_all + P.case_id;
+    bin_slots<D>(P, ctrl, update_due(P, ctrl, 0, q), i0, pair_threads<T>() / T, x0, x1, x2, cell, key, rank, cnt);
 }
 
 // S5 after the last queued density relaxation, for case c, by one
@@ -1704,20 +1727,18 @@ __device__ void step_end(const KP<real>& P, Ctrl* __restrict__ ctrl, unsigned lo
 
 // Whether the configuration update at the end of a queue is a full one for
 // this case: requested, an advection step ended earlier in the queue, or the
-// last queued sub-step q (q >= 0) ends it. The same decision as step_end's,
-// taken from the same state by every wavefront (all 64 lanes active).
+// last queued sub-step q (q >= 0) ends it. The same decision as step_end's
+// (next_substep's `finished`, which does not depend on |v|max), taken from
+// the same state by every wavefront, also inside the density relaxation of
+// sub-step q itself (nothing it writes enters the decision).
 template <typename real>
-__device__ __forceinline__ bool update_due(const KP<real>& P, const Ctrl* __restrict__ ctrl,
-                                           const unsigned long long* __restrict__ vslot, int force, int q)
+__device__ __forceinline__ bool update_due(const KP<real>& P, const Ctrl* __restrict__ ctrl, int force, int q)
 {
     if (force || ctrl->rebuild) return true;
     if (q < 0) return false;
     const SubState Sp = ctrl->ss[q & 1];
     if (!Sp.active || ctrl->err) return false;
-    const double vmax = slot_max<real>(vslot + (q & 1) * VSLOTS);
-    bool finished;
-    (void)next_substep(P, ctrl->dt_ad, Sp, vmax, finished);
-    return finished;
+    return Sp.last || !(ctrl->dt_ad - (Sp.tau + Sp.dt) > 0.0);
 }
 
 // Single-pass exclusive scan of the cell counts (decoupled look-back), for

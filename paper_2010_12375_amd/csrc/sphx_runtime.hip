@@ -957,13 +957,15 @@ struct Engine final : EngineBase {
 
     // `q` >= 0: at the end of a queue whose last sub-step is q (the scan
     // closes it, the binning decides the full updates from the same state).
-    int enqueue_rebuild(int force, int a, int q = -1)
+    // `binned`: the last density relaxation of the queue has done the binning.
+    int enqueue_rebuild(int force, int a, int q = -1, bool binned = false)
     {
         ++conf_gen;
         int b = 1 - a;
         const int nb = nblk(ntot);
-        k_bin<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, x[a][0], x[a][1], x[a][2], cell[a], key,
-                                            rank, cnt, vslot, q);
+        if (!binned)
+            k_bin<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, x[a][0], x[a][1], x[a][2], cell[a],
+                                                key, rank, cnt, q);
         RETCHK(enqueue_scan(fstart, q));
         if (any_move()) RETCHK(enqueue_wall_sort());  // walls in their pose at each case's (closed) clock
         k_scatter<real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ntot, key, rank, fstart, perm);
@@ -977,7 +979,7 @@ struct Engine final : EngineBase {
     }
 
     template <int T>
-    void launch_substep(int a, int q, int adv, int finalize, real* acc, real* dro)
+    void launch_substep(int a, int q, int adv, int finalize, real* acc, real* dro, int bin)
     {
         const int nb = pair_blocks();
         R4<real>* av = avt_arg();
@@ -989,15 +991,15 @@ struct Engine final : EngineBase {
                                                             st[a], dr3[a], hf, acc, q, adv, vslot, av, wm, wg);
             k_density<D, real, T, MV><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt,
                                                            wnb, wcnt, hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2],
-                                                           dro, vslot, q, av, wm, wg);
+                                                           dro, vslot, q, av, wm, wg, bin, cell[a], key, rank, cnt);
         });
     }
 
     // Pressure and density relaxation of sub-step q on set a; `adv`: close
     // sub-step q - 1 first (inside the pressure relaxation).
-    int enqueue_substep(int a, int q, int adv, int finalize, real* acc, real* dro)
+    int enqueue_substep(int a, int q, int adv, int finalize, real* acc, real* dro, int bin = 0)
     {
-        by_lanes([&](auto t) { launch_substep<decltype(t)::value>(a, q, adv, finalize, acc, dro); });
+        by_lanes([&](auto t) { launch_substep<decltype(t)::value>(a, q, adv, finalize, acc, dro, bin); });
         HIPCHK(hipGetLastError());
         return SPHX_OK;
     }
@@ -1040,8 +1042,8 @@ struct Engine final : EngineBase {
     {
         if (D == 3) RETCHK(enqueue_reinit(1, a));
         RETCHK(enqueue_adv_forces(1, a));
-        for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr));
-        RETCHK(enqueue_rebuild(0, a, nsub_q - 1));
+        for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr, q == nsub_q - 1));
+        RETCHK(enqueue_rebuild(0, a, nsub_q - 1, true));
         return SPHX_OK;
     }
 
@@ -1569,7 +1571,8 @@ struct Engine final : EngineBase {
             by_motion([&](auto mc) {
                 k_density<D, real, T, decltype(mc)::value><<<nb, pair_threads<T>(), 0, s>>>(
                     dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
-                    x[a][1], x[a][2], nullptr, vslot, 0, avt_arg(), wmot_arg(), wvg_arg());
+                    x[a][1], x[a][2], nullptr, vslot, 0, avt_arg(), wmot_arg(), wvg_arg(), 0, nullptr, nullptr, nullptr,
+                    nullptr);
             });
         }));
         // the list build is idempotent on the current set
