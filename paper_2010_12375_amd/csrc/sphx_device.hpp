@@ -104,6 +104,8 @@ template <typename real> struct alignas(4 * sizeof(real)) R4 { real x, y, z, w; 
 template <typename real> struct alignas(2 * sizeof(real)) R2 { real x, y; };
 template <typename real> __device__ __forceinline__ real zc(const R2<real>&) { return (real)0; }
 template <typename real> __device__ __forceinline__ real zc(const R4<real>& v) { return v.z; }
+template <typename real> __device__ __forceinline__ real geo_w(const R2<real>&) { return (real)0; }
+template <typename real> __device__ __forceinline__ real geo_w(const R4<real>& v) { return v.w; }
 template <int D, typename real> struct GeoSel { using T = R2<real>; };
 template <typename real> struct GeoSel<3, real> { using T = R4<real>; };
 
@@ -664,7 +666,7 @@ __global__ __launch_bounds__(BLOCK) void k_place_fluid(
     g.y = (real)(x[1] - (P.lo[1] + (double)c1 * P.Ld[1]));
     if constexpr (D == 3) {
         g.z = (real)(x[2] - (P.lo[2] + (double)c2 * P.Ld[2]));
-        g.w = (real)0;
+        g.w = adr[i];  // the density rate rides along (read by the pressure relaxation's gathers)
     }
     bgeo[s] = g;
 }
@@ -1343,7 +1345,7 @@ __device__ __forceinline__ void pressure_body(
         dev_i = si.z + half * si.w;
     } else {
         vi[0] = si.x; vi[1] = si.y; vi[2] = si.z;
-        dev_i = si.w + half * dr3[i];
+        dev_i = si.w + half * dr3[i];  // (= geo[i].w)
     }
     const real rho_i = P.rho0 + dev_i;
     const real p_i = P.c2 * dev_i;
@@ -1352,7 +1354,7 @@ __device__ __forceinline__ void pressure_body(
     const real wi = P.two_vw * inv_rho_i;  // 2 V_w / rho_i
     const G oi = geo[i];
     real acc[3] = {0, 0, 0};
-    struct FluidJ { G o; R4<real> s; real dr; };
+    struct FluidJ { G o; R4<real> s; };
     struct WallJ { G o; G n; R4<real> k, g; };
     for_pairs<T, BATCH>(
         nbr, i, ncnt[i], P.maxn, l,
@@ -1361,13 +1363,13 @@ __device__ __forceinline__ void pressure_body(
             FluidJ r;
             r.o = geo[j];
             r.s = st[j];
-            r.dr = D == 3 ? dr3[j] : (real)0;
             return r;
         },
         [&](uint32_t e, const FluidJ& r) {
             Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const R4<real>& sj = r.s;
-            real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * r.dr;
+            // 3D: the neighbour's density rate is the w of its frozen offsets
+            real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * geo_w(r.o);
             // U_L - U_R = (v_i - v_j) . e_ij = -(v_i - v_j) . d / r
             real dvd = (vi[0] - sj.x) * pq.d[0] + (vi[1] - sj.y) * pq.d[1] +
                        (D == 3 ? (vi[2] - sj.z) * pq.d[2] : (real)0);
@@ -1622,6 +1624,9 @@ __device__ __forceinline__ void density_body(
                 sn.z = vi[2];
                 sn.w = dev_i + half * drho;
                 dr3[i] = drho;
+                // and in w of the frozen offsets, where the pressure relaxation
+                // gathers it with them (the pair loops here read x, y, z only)
+                reinterpret_cast<real*>(const_cast<G*>(geo))[4 * (size_t)i + 3] = drho;
             }
             st[i] = sn;
             if (drho_out) drho_out[i] = drho;

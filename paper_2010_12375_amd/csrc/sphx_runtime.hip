@@ -162,6 +162,7 @@ struct Engine final : EngineBase {
     // state backup for calls that must leave the state unchanged
     R4<real>* bk_st = nullptr;
     real* bk_dr = nullptr;
+    G* bk_geo = nullptr;  // 3D: the frozen geometry carries the density rate in w
     double* bk_x[3] = {};
     // fluid given before the first device layout, per case (uploaded together)
     struct Pending {
@@ -613,6 +614,7 @@ struct Engine final : EngineBase {
         RETCHK(dalloc(L, diag_part, (size_t)(n / TILE) * NDIAG));
         RETCHK(dalloc(L, bk_st, n));
         if (D == 3) RETCHK(dalloc(L, bk_dr, n));
+        if (D == 3) RETCHK(dalloc(L, bk_geo, n));
         for (int k = 0; k < D; ++k) RETCHK(dalloc(L, bk_x[k], n));
         if (D == 2) bk_x[2] = bk_x[1];
         return SPHX_OK;
@@ -1179,6 +1181,7 @@ struct Engine final : EngineBase {
     {
         HIPCHK(hipMemcpyAsync(bk_st, st[cur], sizeof(R4<real>) * ntot, hipMemcpyDeviceToDevice, s));
         if (D == 3) HIPCHK(hipMemcpyAsync(bk_dr, dr3[cur], sizeof(real) * ntot, hipMemcpyDeviceToDevice, s));
+        if (D == 3) HIPCHK(hipMemcpyAsync(bk_geo, geo[cur], sizeof(G) * ntot, hipMemcpyDeviceToDevice, s));
         for (int k = 0; k < D; ++k)
             HIPCHK(hipMemcpyAsync(bk_x[k], x[cur][k], sizeof(double) * ntot, hipMemcpyDeviceToDevice, s));
         return SPHX_OK;
@@ -1188,6 +1191,7 @@ struct Engine final : EngineBase {
     {
         HIPCHK(hipMemcpyAsync(st[cur], bk_st, sizeof(R4<real>) * ntot, hipMemcpyDeviceToDevice, s));
         if (D == 3) HIPCHK(hipMemcpyAsync(dr3[cur], bk_dr, sizeof(real) * ntot, hipMemcpyDeviceToDevice, s));
+        if (D == 3) HIPCHK(hipMemcpyAsync(geo[cur], bk_geo, sizeof(G) * ntot, hipMemcpyDeviceToDevice, s));
         for (int k = 0; k < D; ++k)
             HIPCHK(hipMemcpyAsync(x[cur][k], bk_x[k], sizeof(double) * ntot, hipMemcpyDeviceToDevice, s));
         std::memcpy(hctrl, saved.data(), sizeof(Ctrl) * C);
