@@ -871,17 +871,18 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
         for (int jb = j0; jb < j1; jb += TB * BATCH) {
             G oj[BATCH];
             double xq[BATCH][3];
+            // unconditional loads (past the end: the range's last candidate,
+            // loaded and not tested), so that the BATCH loads issue back to
+            // back without a wait between them
 #pragma unroll
             for (int u = 0; u < BATCH; ++u) {
-                const int j = jb + u * TB + l;
-                if (j < j1) {
-                    if constexpr (PREFILTER) {
-                        oj[u] = csrc[j];
-                    } else {
-                        xq[u][0] = bx0[j];
-                        xq[u][1] = bx1[j];
-                        xq[u][2] = D == 3 ? bx2[j] : 0.0;
-                    }
+                const int j = min(jb + u * TB + l, j1 - 1);
+                if constexpr (PREFILTER) {
+                    oj[u] = csrc[j];
+                } else {
+                    xq[u][0] = bx0[j];
+                    xq[u][1] = bx1[j];
+                    xq[u][2] = D == 3 ? bx2[j] : 0.0;
                 }
             }
 #pragma unroll
