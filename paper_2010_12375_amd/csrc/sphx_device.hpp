@@ -47,7 +47,11 @@ constexpr int BLOCK = 256;  // threads per block of every particle kernel
 #ifndef SPHX_PAIR_BATCH
 #define SPHX_PAIR_BATCH 4
 #endif
-constexpr int BATCH = SPHX_PAIR_BATCH;  // list entries / candidate rounds loaded ahead per lane
+constexpr int BATCH = SPHX_PAIR_BATCH;  // list entries loaded ahead per lane (pair kernels)
+#ifndef SPHX_BUILD_BATCH
+#define SPHX_BUILD_BATCH 4
+#endif
+constexpr int NBATCH = SPHX_BUILD_BATCH;  // candidate rounds loaded ahead per lane (neighbour build)
 constexpr uint32_t NO_ENTRY = 0xffffffffu;  // stencil code 63 never occurs
 constexpr int VSLOTS = 64;  // slots the density relaxation folds its block maxima into
 #ifndef SPHX_PAIR_WAVES
@@ -866,16 +870,16 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
         uint32_t* out = BODY ? wnb : nbr;
         const int mx = BODY ? P.maxw : P.maxn;
         int& nn = BODY ? cnt_w : cnt_f;
-        // BATCH rounds per iteration: all candidate loads first, then the
+        // NBATCH rounds per iteration: all candidate loads first, then the
         // tests and ballots in candidate order
-        for (int jb = j0; jb < j1; jb += TB * BATCH) {
-            G oj[BATCH];
-            double xq[BATCH][3];
+        for (int jb = j0; jb < j1; jb += TB * NBATCH) {
+            G oj[NBATCH];
+            double xq[NBATCH][3];
             // unconditional loads (past the end: the range's last candidate,
-            // loaded and not tested), so that the BATCH loads issue back to
+            // loaded and not tested), so that the NBATCH loads issue back to
             // back without a wait between them
 #pragma unroll
-            for (int u = 0; u < BATCH; ++u) {
+            for (int u = 0; u < NBATCH; ++u) {
                 const int j = min(jb + u * TB + l, j1 - 1);
                 if constexpr (PREFILTER) {
                     oj[u] = csrc[j];
@@ -886,7 +890,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
                 }
             }
 #pragma unroll
-            for (int u = 0; u < BATCH; ++u) {
+            for (int u = 0; u < NBATCH; ++u) {
                 if (jb + u * TB >= j1) break;  // uniform over the lane group
                 const int j = jb + u * TB + l;
                 const int dcx = dcx0 + (j >= b1) + (j >= b2);
