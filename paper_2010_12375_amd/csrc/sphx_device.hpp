@@ -813,12 +813,11 @@ template <int B> struct BodyTag { static constexpr int value = B; };
 // test, and the list is bit-exact. Cases without a full update keep their
 // lists (their order did not change).
 //
-// In 2D, with `reinit` (the update at the end of a queue), a case whose
-// next advection step has been prepared also gets that step's density
+// With `reinit` (the update at the end of a queue), a case whose next
+// advection step has been prepared also gets that step's density
 // re-initialisation (Eq. eqrhosum / eqrhosumnosurface) here, saving a
 // launch: the kernel sum over the accepted neighbours is taken while they
-// are found, from the frozen offsets. (In 3D the extra registers cost the
-// candidate scan more than the separate pass over the lists.)
+// are found, from the frozen offsets.
 template <int D, typename real, int T, int TB>
 __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int force,
@@ -836,7 +835,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const KP<real> P = Pt[tcase[b]];  // a copy: the fields stay in registers through the loops
     Ctrl* ctrl = ctrl_all + P.case_id;
     if (!full_update(ctrl, force) || ctrl->err) return;
-    const bool do_reinit = D == 2 && reinit && ctrl->ss[0].active && !ctrl->midstep;
+    const bool do_reinit = reinit && ctrl->ss[0].active && !ctrl->midstep;
     double sigma = 0.0;
     const int i = b * TILE + (int)threadIdx.x / TB;
     const int l = threadIdx.x % TB;

@@ -435,19 +435,20 @@ struct Engine final : EngineBase {
         else f(std::false_type{});
     }
 
-    // Call f with the lanes per particle of the pair kernels as a constant.
+    // Call f with the lanes per particle of the pair kernels as a constant
+    // (2, 4 or 8 in 2D; 4, 8 or 16 in 3D: only these are instantiated).
     template <typename F>
     void by_lanes(F&& f)
     {
         if constexpr (D == 2) {
-            if (ln == 2) {
-                f(std::integral_constant<int, 2>{});
-                return;
-            }
+            if (ln == 2) f(std::integral_constant<int, 2>{});
+            else if (ln == 4) f(std::integral_constant<int, 4>{});
+            else f(std::integral_constant<int, 8>{});
+        } else {
+            if (ln == 4) f(std::integral_constant<int, 4>{});
+            else if (ln == 8) f(std::integral_constant<int, 8>{});
+            else f(std::integral_constant<int, 16>{});
         }
-        if (ln == 4) f(std::integral_constant<int, 4>{});
-        else if (ln == 8) f(std::integral_constant<int, 8>{});
-        else f(std::integral_constant<int, 16>{});
     }
 
     int upload_params()
@@ -1042,7 +1043,6 @@ struct Engine final : EngineBase {
     // the sub-steps, the configuration update.
     int enqueue_step(int a)
     {
-        if (D == 3) RETCHK(enqueue_reinit(1, a));
         RETCHK(enqueue_adv_forces(1, a));
         for (int q = 0; q < nsub_q; ++q) RETCHK(enqueue_substep(a, q, q > 0, 1, nullptr, nullptr, q == nsub_q - 1));
         RETCHK(enqueue_rebuild(0, a, nsub_q - 1, true));
@@ -1275,15 +1275,12 @@ struct Engine final : EngineBase {
         RETCHK(push_ctrl());
         k_adv_begin<real><<<(C + 63) / 64, 64, 0, s>>>(dP, ctrl, C);
         HIPCHK(hipGetLastError());
-        // 2D: the first step's density re-initialisation, by the same kernel
-        // (and so the same arithmetic) that re-initialises the later steps at
-        // the end of each queue: the lists are rebuilt unchanged from the
-        // current configuration, so how a run is split into calls changes no
-        // bit (3D re-initialises at the head of every queue)
-        if (D == 2) {
-            by_lanes([&](auto t) { launch_neighbors<decltype(t)::value>(1, cur, 1); });
-            HIPCHK(hipGetLastError());
-        }
+        // the first step's density re-initialisation, by the same kernel (and
+        // so the same arithmetic) that re-initialises the later steps at the
+        // end of each queue: the lists are rebuilt unchanged from the current
+        // configuration, so how a run is split into calls changes no bit
+        by_lanes([&](auto t) { launch_neighbors<decltype(t)::value>(1, cur, 1); });
+        HIPCHK(hipGetLastError());
         RETCHK(sync_ctrl());
         // queues in batches of at most 64, one host synchronisation per batch
         for (long long need = queues_needed(); need > 0; need = queues_needed()) {
