@@ -212,10 +212,10 @@ int sphx_set_fluid_device(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos
  * values). Returns when the copy is complete. */
 int sphx_get_field_device(sphx_ctx* ctx, int32_t c, int field, double* out);
 
-/* Checkpoint (the survey's save and load of a run): sphx_save writes the
- * parameters of every case, its walls and wall motion, its clock and time
- * step state, and its particle state in the library's current slot order
- * to `path`; sphx_load restores such a file into a context created with the
+/* Checkpoint (save and load of a run): sphx_save writes the parameters of
+ * every case, its walls, wall motion and given wall velocities, its clock
+ * and time step state, and its particle state in the library's current slot
+ * order to `path`; sphx_load restores such a file into a context created with the
  * same parameters (same number of cases, dimension, precision and every
  * sphx_params field except nsub_queue; SPHX_EINVAL otherwise or for a
  * truncated or foreign file). The neighbour configuration is rebuilt on the

@@ -75,7 +75,7 @@ def load(path=None):
         return _lib
     p = path or LIB_PATH
     if not os.path.exists(p):
-        raise ImportError(f"HIP library not built: {p} (run __graft_entry__.build())")
+        raise ImportError(f"HIP library not built: {p} (build it with: python -m paper_2010_12375_amd.build)")
     L = C.CDLL(p)
     vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     pd, pi64 = C.POINTER(C.c_double), C.POINTER(C.c_int64)
