@@ -713,26 +713,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter_walls(int n, const int32_t* _
     if (p < n) perm[p] = i;
 }
 
-// Order each cell's wall particles by input index (deterministic order).
-__global__ __launch_bounds__(BLOCK) void k_cell_order(int ncell, const int32_t* __restrict__ start,
-                                                      int32_t* __restrict__ perm)
-{
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    int s = start[c], e = start[c + 1];
-    for (int a = s + 1; a < e; ++a) {
-        int v = perm[a];
-        int b = a - 1;
-        while (b >= s && perm[b] > v) {
-            perm[b + 1] = perm[b];
-            --b;
-        }
-        perm[b + 1] = v;
-    }
-}
-
 // Walls: move into cell order in their pose at the case's clock, freeze
-// offsets and normals, keep ids relative to the case's first wall particle;
+// offsets and normals, keep ids relative to the case's first wall particle.
+// One thread per wall particle i (input order): its slot in its cell is the
+// number of the cell's wall particles with a smaller input index (counted
+// over the cell's arrival list from k_scatter_walls), the order of a stable
+// sort, so walls sit in each cell in input order;
 // with `bmot`, also the motion record {m r_x, m r_y, m, 0} (m: follows the
 // motion, r: lever arm from the rotation centre); with `bvg`, the given
 // velocity (vin: 3 per wall particle, input order).
@@ -740,16 +726,20 @@ template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_gather_wall(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ wcase, const Ctrl* __restrict__ ctrl_all,
     const int32_t* __restrict__ wflag, int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ key,
-    const double* __restrict__ ax0, const double* __restrict__ ax1, const double* __restrict__ ax2,
+    const int32_t* __restrict__ start, const double* __restrict__ ax0, const double* __restrict__ ax1,
+    const double* __restrict__ ax2,
     const double* __restrict__ an0, const double* __restrict__ an1, const double* __restrict__ an2,
     double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2,
     typename GeoSel<D, real>::T* __restrict__ bgeo, typename GeoSel<D, real>::T* __restrict__ bnrm,
     int32_t* __restrict__ bid, R4<real>* __restrict__ bmot, const double* __restrict__ vin,
     R4<real>* __restrict__ bvg)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    int i = perm[s];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s0 = start[key[i]], s1 = min(start[key[i] + 1], n);
+    int s = s0;
+    for (int q = s0; q < s1; ++q) s += perm[q] < i;
+    if (s >= n) return;  // never for consistent counts
     const KP<real>& P = Pt[wcase[i]];
     int kc = key[i] - P.cbase;
     const double t = ctrl_all[P.case_id].t;

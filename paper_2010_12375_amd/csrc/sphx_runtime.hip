@@ -919,8 +919,7 @@ struct Engine final : EngineBase {
                                                         wrank, cnt);
         RETCHK(enqueue_scan(wstart));
         k_scatter_walls<<<nblk(n), BLOCK, 0, s>>>(n, wkey, wrank, wstart, wperm);
-        k_cell_order<<<nblk(ncell), BLOCK, 0, s>>>(ncell, wstart, wperm);
-        k_gather_wall<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, ctrl, wflag, n, wperm, wkey, wref[0], wref[1],
+        k_gather_wall<D, real><<<nblk(n), BLOCK, 0, s>>>(dP, wcase, ctrl, wflag, n, wperm, wkey, wstart, wref[0], wref[1],
                                                           wref[D3], wref[3], wref[4], wref[3 + D3], wx[0], wx[1],
                                                           wx[2], wgeo, wnrm, wid, wmot_arg(), wvin, wvg_arg());
         HIPCHK(hipGetLastError());
