@@ -220,7 +220,8 @@ int sphx_get_field_device(sphx_ctx* ctx, int32_t c, int field, double* out);
  * sphx_params field except nsub_queue; SPHX_EINVAL otherwise or for a
  * truncated or foreign file). The neighbour configuration is rebuilt on the
  * next call that needs it; from the restored state the run continues bit for
- * bit as the saved context would have. The surrogate's parameters are not
+ * bit as the saved context would have, given the same lanes per particle
+ * (sphx_set_lanes; not part of the file). The surrogate's parameters are not
  * part of a checkpoint. */
 int sphx_save(sphx_ctx* ctx, const char* path);
 int sphx_load(sphx_ctx* ctx, const char* path);
