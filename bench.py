@@ -264,8 +264,8 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
-              "described in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path (slabs along x "
+              "with halo exchanges over RCCL) is designed, not built.", file=sys.stderr)
         sys.exit(2)
 
     from paper_2010_12375_amd import sphx
