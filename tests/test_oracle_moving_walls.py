@@ -160,18 +160,23 @@ def test_walls_flagged_static_give_the_static_rates():
     assert np.array_equal(a0, a1) and np.array_equal(d0, d1)
 
 
-def test_given_wall_velocity_is_galilean_invariant_too():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_given_wall_velocity_is_galilean_invariant_too(dim):
     """Walls at rest carrying a given velocity U, fluid moving with U: the
     rates of the same state at rest, with and without viscosity."""
-    case = wl.dam_break_2d(0.05, seed=4)
+    if dim == 2:
+        case = wl.dam_break_2d(0.05, seed=4)
+        U = np.array([0.3, 0.5])
+    else:
+        case = wl.dam_break_3d(0.1, seed=4, W=0.3, DL=2.4, DH=1.3, precision=wl.FP64)
+        U = np.array([0.3, 0.5, -0.2])
     _, rho, drho = developed_state(case, seed=6)
-    U = np.array([0.3, 0.5])
     n = case.n_fluid
     for eta in (0.0, 0.02):
         p = O.params_from_case(case)
         p.eta = eta
         rest = O.Oracle(params=p)
-        rest.set_fluid(case.fluid_pos, vel=np.zeros((n, 2)), rho=rho, drho=drho)
+        rest.set_fluid(case.fluid_pos, vel=np.zeros((n, dim)), rho=rho, drho=drho)
         rest.set_walls(case.wall_pos, case.wall_normal)
         rest.build_config()
         a0, d0 = rest.compute_rates(0.0)
