@@ -70,6 +70,14 @@ MUTATIONS = [
      "for (int k = 0; k < 3; ++k) v[k] += 0.0 * s->vw0[3 * w + k];\n}", None),
     ("given_wall_velocity_sign", "for (int k = 0; k < 3; ++k) v[k] += s->vw0[3 * w + k];\n}",
      "for (int k = 0; k < 3; ++k) v[k] -= s->vw0[3 * w + k];\n}", None),
+    ("wall_right_pressure_reference_density", "*PR = p_i + rho_i * dot3(s->p.g, r_fw);",
+     "*PR = p_i + s->p.rho0 * dot3(s->p.g, r_fw);", None),
+    ("wall_right_density_without_eos", "*rhoR = s->p.rho0 + *PR / (s->p.c0 * s->p.c0);",
+     "*rhoR = s->p.rho0;", None),
+    ("internal_energy_half", "ei += m * c2 * (log(rr) + 1.0 / rr - 1.0);",
+     "ei += 0.5 * m * c2 * (log(rr) + 1.0 / rr - 1.0);", None),
+    ("internal_energy_without_log", "ei += m * c2 * (log(rr) + 1.0 / rr - 1.0);",
+     "ei += m * c2 * (rr + 1.0 / rr - 2.0);", None),
     ("static_flag_ignored_in_states", "if (s->moving && s->wmov[w]) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);",
      "if (s->moving) wall_velocity(s, s->xw + 3 * w, s->wc, t, v);", None),
 ]

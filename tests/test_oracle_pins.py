@@ -392,6 +392,74 @@ def test_wall_hydrostatic_extrapolation_sign():
     assert a0[0, 1] == 0.0
 
 
+def _one_wall_pair(rho_i, g, wall_xy):
+    """One resting fluid particle at (0.05, 0.05) with density rho_i and one
+    wall particle (normal +y) at wall_xy; returns (a_i, drho_i)."""
+    dp = 0.1
+    pts = np.array([[0.05, 0.05]])
+    wall = np.array([wall_xy], dtype=np.float64)
+    p = params(2, dp=dp, lo=(-1, -1, 0), hi=(1, 1, 0), g=g, c0=10.0)
+    o = O.Oracle(params=p)
+    o.set_fluid(pts, rho=np.array([rho_i]))
+    o.set_walls(wall, np.array([[0.0, 1.0]]))
+    o.build_config()
+    a, dr = o.compute_rates(0.0)
+    return a[0], dr[0]
+
+
+@pytest.mark.parametrize("wall_xy", [(0.05, -0.05), (0.12, -0.03), (-0.1, 0.0)])
+def test_wall_right_state_uses_fluid_density(wall_xy):
+    """Eq. eqriepright: P_R = P_L + rho_f g . r_fw with rho_f the fluid
+    particle's own density. A fluid particle at rest (U_L = U_R = 0, so the
+    dissipation limiter is zero and P* is the mean of P_L and P_R) above one
+    wall particle: the gravity-induced part of the wall force relative to the
+    gravity-free force is rho_f (g . r_fw) / (2 p_f), independent of the
+    kernel; the continuity rate of the same one-sided problem is
+    -rho_f^2 (g . r_fw) W' V_w / (rho_bar c0) with rho_bar the mean of rho_f
+    and rho_R = rho0 + P_R / c0^2, which against the force part gives the
+    kernel-free ratio -rho_f^2 / (rho_bar c0)."""
+    rho_i, c0, rho0 = 1.05, 10.0, 1.0
+    g = (0.0, -1.0, 0.0)
+    a_g, dr_g = _one_wall_pair(rho_i, g, wall_xy)
+    a_0, dr_0 = _one_wall_pair(rho_i, (0.0, 0.0, 0.0), wall_xy)
+    p_f = c0 * c0 * (rho_i - rho0)
+    r_fw = np.array(wall_xy) - np.array([0.05, 0.05])
+    e = r_fw / np.linalg.norm(r_fw)
+    g_dot_r = float(np.dot(np.array(g[:2]), r_fw))
+    extra = a_g - np.array(g[:2]) - a_0          # force of the gravity term in P*
+    assert abs(np.dot(extra, [e[1], -e[0]])) < 1e-12 * np.abs(a_0).max()   # along e_iw
+    want = rho_i * g_dot_r / (2.0 * p_f)
+    assert abs(np.dot(extra, e) / np.dot(a_0, e) - want) < 1e-12
+    assert dr_0 == 0.0                            # equal states: no flux without gravity
+    P_R = p_f + rho_i * g_dot_r
+    rho_bar = 0.5 * (rho_i + rho0 + P_R / (c0 * c0))
+    # extra . e = V_w (g . r_fw) W'  and  drho = -rho_f^2 (g . r_fw) W' V_w / (rho_bar c0)
+    assert abs(dr_g / np.dot(extra, e) - (-rho_i * rho_i / (rho_bar * c0))) < 1e-12 * (rho_i ** 2 / c0)
+
+
+@pytest.mark.parametrize("rho", [1.02, 0.985, 1.0])
+def test_internal_energy_is_the_eos_work(rho):
+    """The internal energy of the energy observable is the work of the
+    equation of state (Eq. eqeos, p = c0^2 (rho - rho0)): per unit mass
+    e(rho) = integral from rho0 to rho of p(r) / r^2 dr, evaluated here by
+    quadrature, for a uniformly compressed (or expanded) particle set; the
+    kinetic and potential parts are sum m |v|^2 / 2 and -sum m g . x."""
+    c = wl.config_small(seed=1)
+    o = O.Oracle(c)
+    rng = np.random.Generator(np.random.PCG64(5))
+    vel = rng.uniform(-0.2, 0.2, size=c.fluid_pos.shape)
+    o.set_fluid(c.fluid_pos, vel=vel, rho=np.full(c.n_fluid, rho))
+    d = o.diagnostics()
+    m = c.rho0 * c.dp ** 2
+    e_per_mass, _ = quad(lambda r: c.c0 ** 2 * (r - c.rho0) / (r * r), c.rho0, rho, epsabs=0.0, epsrel=1e-13)
+    want = c.n_fluid * m * e_per_mass
+    assert abs(d["e_int"] - want) <= 1e-10 * max(abs(want), 1e-300) + 1e-300
+    assert d["e_int"] >= 0.0
+    assert abs(d["e_kin"] - 0.5 * m * float(np.sum(vel * vel))) < 1e-12 * d["e_kin"]
+    assert abs(d["e_pot"] - m * float(np.sum(c.fluid_pos[:, 1]))) < 1e-12 * d["e_pot"]
+    assert abs(d["max_drho"] - abs(rho - 1.0)) < 1e-15
+
+
 # --------------------------------------------------------------------------
 # Density re-initialisation (Eq. eqrhosum)
 
