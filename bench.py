@@ -8,7 +8,13 @@ Inputs are seeded synthetic dam breaks (no dataset), resident in device
 memory before the timed region starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload medium|small|large|ensemble|sloshing|surrogate]
+                    [--workload large|medium|small|ensemble|sloshing|surrogate]
+
+Default workload: the 3D dam break (2.0 M fluid and 0.596 M wall particles,
+dp = 0.01, 2 000 advection steps). Its timed window starts mid-run (after
+1 000 untimed advection steps and the warm-up), so the window holds the
+flow after release rather than the resting column; the whole 2 000-step run
+from t = 0 is timed as well and reported in config.whole_run.
 
 Prints one JSON line. value = fluid particles x acoustic sub-steps / wall
 time, in millions per second (summed over the cases for the ensemble of 64
@@ -33,25 +39,48 @@ FP32_VALU_TFLOPS = 157.3       # MI355X FP32 vector peak
 FP64_VALU_TFLOPS = 78.6
 
 
-def algorithmic_bytes(dim, precision, n_fluid, inner_pairs, contact_pairs):
-    """Compulsory bytes per launch of the two sub-step kernels: each fluid
-    particle's own state read and written once, plus the stored neighbour
-    configuration at 4 bytes per directed pair (one index per pair; the
-    paper's configuration stores kernel values and gradients as well)."""
+def algorithmic_bytes(dim, precision, n_fluid):
+    """Compulsory bytes per launch of the two sub-step kernels, state only:
+    each fluid particle's own fields read and written once (r = 4 bytes per
+    FP32 field, 8 per FP64 field; positions always FP64).
+    Pressure relaxation: reads rho, drho/dt, v and the frozen offsets, writes
+    rho^{n+1/2} and v^{n+1}: (3 + 3d) r.
+    Density relaxation: reads v^{n+1}, v^n, rho, the offsets and x, writes
+    rho, drho/dt and x: (3d + 3) r + 16 d.
+    (2D FP32: 36 and 68 bytes per particle; 3D FP32: 48 and 96.) The stored
+    neighbour configuration is not compulsory state: it is reported apart
+    (configuration_bytes)."""
     r = 4 if precision == 1 else 8
-    geo = 2 * r if dim == 2 else 4 * r
-    rec = 4 * r  # packed state / half-step record
-    cnts = 8
-    pairs = 4 * (inner_pairs + contact_pairs)
-    # pressure relaxation: read st (+drho in 3D), geo, counts; write hf
-    k1 = n_fluid * (rec + (r if dim == 3 else 0) + geo + cnts + rec) + pairs
-    # density relaxation: read hf, geo, st (v^n), x (FP64), counts;
-    # write st (+drho in 3D), x
-    k2 = n_fluid * (rec + geo + rec + 8 * dim + cnts + rec + (r if dim == 3 else 0) + 8 * dim) + pairs
+    k1 = n_fluid * (3 + 3 * dim) * r
+    k2 = n_fluid * ((3 * dim + 3) * r + 16 * dim)
     return k1, k2
 
 
+def configuration_bytes(inner_pairs, contact_pairs, n_fluid, bytes_per_pair=4.0, bytes_per_particle=8.0):
+    """Bytes of the stored neighbour configuration one pair kernel reads per
+    launch (entries per directed pair plus per-particle counts or masks)."""
+    return int(bytes_per_pair * (inner_pairs + contact_pairs) + bytes_per_particle * n_fluid)
+
+
 FLOPS_PER_PAIR = 55  # geometry ~25 (incl. rsqrt) + Riemann and accumulation ~30, per directed pair
+
+
+def roofline(nbytes, flops, ms, precision):
+    """Roofline of one launch: time bound max(bytes / HBM peak, flops / VALU
+    peak); frac = that bound over the measured launch time, reported against
+    the bound that is larger."""
+    valu = FP32_VALU_TFLOPS if precision == 1 else FP64_VALU_TFLOPS
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (valu * 1e12)
+    t = ms * 1e-3
+    if t_hbm >= t_alu:
+        out = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        out = {"bound": "alu", "achieved": flops / t / 1e12, "peak": valu, "unit": "TFLOP/s"}
+    out["frac"] = max(t_hbm, t_alu) / t
+    out["hbm_frac"] = t_hbm / t
+    out["alu_frac"] = t_alu / t
+    return out
 
 
 def kernel_source_hash():
@@ -231,12 +260,37 @@ def surrogate_bench(args):
     print(json.dumps(out), flush=True)
 
 
+LARGE_START_STEP = 1000  # mid-run of the 2 000-step 3D dam break
+
+
+def kernel_breakdown(prof, nsub_per_step):
+    """Per-step time of each hot kernel from its HIP-event launch time: the
+    two relaxations run once per acoustic sub-step, the neighbour build (with
+    the fused density re-initialisation) once per advection step."""
+    per_step = {"pressure_relaxation": prof["pressure"] * nsub_per_step,
+                "density_relaxation": prof["density"] * nsub_per_step,
+                "neighbor_build": prof["neighbors"]}
+    total = sum(per_step.values())
+    return {k: {"ms_per_launch": round({"pressure_relaxation": prof["pressure"],
+                                        "density_relaxation": prof["density"],
+                                        "neighbor_build": prof["neighbors"]}[k], 5),
+                "launches_per_step": round(nsub_per_step, 3) if k != "neighbor_build" else 1,
+                "ms_per_step": round(v, 5), "share": round(v / total, 4)}
+            for k, v in per_step.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large", "ensemble", "sloshing", "surrogate"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="large", choices=["small", "medium", "large", "ensemble", "sloshing", "surrogate"])
+    ap.add_argument("--start-step", type=int, default=-1,
+                    help="advection steps taken (untimed) before the warm-up; -1: 1000 for the 3D dam break "
+                         "(mid-run of its 2 000 steps), 0 otherwise")
+    ap.add_argument("--whole-run", type=int, default=-1,
+                    help="also time the first N advection steps from t=0 as one figure (-1: 2000 for the 3D dam "
+                         "break, 0 otherwise); the headline window lies inside this run")
     ap.add_argument("--train-cases", type=int, default=256, help="surrogate: training trajectories")
     ap.add_argument("--test-cases", type=int, default=32, help="surrogate: held-out trajectories")
     ap.add_argument("--train-iters", type=int, default=2000, help="surrogate: Adam steps (16 snapshots each)")
@@ -274,6 +328,7 @@ def main():
     if args.workload == "surrogate":
         return surrogate_bench(args)
 
+    log = lambda m: print(m, file=sys.stderr, flush=True)
     cases = None
     if args.workload == "small":
         case = wl.config_small(0)
@@ -288,6 +343,9 @@ def main():
         cases = wl.ensemble_cases(64, seed=0)
         case = cases[0]
     precision = case.precision
+    large = args.workload == "large"
+    start_step = args.start_step if args.start_step >= 0 else (LARGE_START_STEP if large else 0)
+    whole = args.whole_run if args.whole_run >= 0 else (case.n_adv_steps if large else 0)
 
     stream = None
     torch = None
@@ -301,6 +359,10 @@ def main():
             torch = None
     except Exception:
         torch = None
+
+    def sync():
+        if torch is not None:
+            torch.cuda.synchronize()
 
     if cases is None:
         sim = sphx.Simulation(sphx.params_from_case(case, precision), stream=stream)
@@ -321,23 +383,46 @@ def main():
         lanes = args.lanes
     if args.autotune or (cases is not None and not args.lanes):
         lanes = sim.autotune(10)
-    sim.advance(args.warmup)
-    if torch is not None:
-        torch.cuda.synchronize()
-    d0 = sim.diagnostics_all()
+    nf = [c.n_fluid for c in cases] if cases is not None else [case.n_fluid]
 
+    def work_between(a, b):
+        return sum(n * (y["n_substeps"] - x["n_substeps"]) for n, x, y in zip(nf, a, b))
+
+    # set-up: the run up to the start of the window (untimed for the headline,
+    # but part of the whole-run figure)
+    sync()
+    d_start = sim.diagnostics_all()
+    t_run = time.perf_counter()
+    if start_step:
+        log(f"bench: {name}: advancing {start_step} advection steps to the start of the timed window")
+        sim.advance(start_step)
+    sim.advance(args.warmup)
+    sync()
+    d0 = sim.diagnostics_all()
     t0 = time.perf_counter()
     sim.advance(args.steps)
     d1 = sim.diagnostics_all()
-    if torch is not None:
-        torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    sync()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    whole_run = None
+    if whole and d1[0]["n_steps"] < whole:
+        sim.advance(whole - d1[0]["n_steps"])
+        dw = sim.diagnostics_all()
+        sync()
+        t_end = time.perf_counter()
+        # the host-side reads of the diagnostics between the windows are inside this figure
+        wr_wall = t_end - t_run
+        whole_run = {"advection_steps": dw[0]["n_steps"] - d_start[0]["n_steps"],
+                     "acoustic_substeps": int(dw[0]["n_substeps"] - d_start[0]["n_substeps"]),
+                     "t_end": dw[0]["t"], "wall_s": round(wr_wall, 4),
+                     "value": round(work_between(d_start, dw) / wr_wall / 1e6, 3)}
+        log(f"bench: whole run {whole_run}")
 
-    nf = [c.n_fluid for c in cases] if cases is not None else [case.n_fluid]
     steps_done = d1[0]["n_steps"] - d0[0]["n_steps"]
     steps_all = sum(b["n_steps"] - a["n_steps"] for a, b in zip(d0, d1))
     nsub = sum(b["n_substeps"] - a["n_substeps"] for a, b in zip(d0, d1))
-    work = sum(n * (b["n_substeps"] - a["n_substeps"]) for n, a, b in zip(nf, d0, d1))
+    work = work_between(d0, d1)
     cnt = sim.counts()
     pairs = cnt["inner_pairs"] + cnt["contact_pairs"]
     value = work / wall / 1e6
@@ -349,16 +434,16 @@ def main():
     pair_evals /= wall
 
     prof = sim.profile(args.profile_reps)
-    k1_bytes, k2_bytes = algorithmic_bytes(case.dim, precision, n_fluid, cnt["inner_pairs"],
-                                           cnt["contact_pairs"])
-    kern = {"pressure_relaxation": (prof["pressure"], k1_bytes), "density_relaxation": (prof["density"], k2_bytes)}
-    kname = max(kern, key=lambda k: kern[k][0])
-    ms, nbytes = kern[kname]
-    achieved = nbytes / (ms * 1e-3) / 1e9
+    nsub_per_step = nsub / max(steps_all, 1)
+    breakdown = kernel_breakdown(prof, nsub_per_step)
+    k1_bytes, k2_bytes = algorithmic_bytes(case.dim, precision, n_fluid)
     flops = FLOPS_PER_PAIR * pairs
-    valu = FP32_VALU_TFLOPS if precision == 1 else FP64_VALU_TFLOPS
-    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
-    t_alu = flops / (valu * 1e12)
+    sub = {"pressure_relaxation": (prof["pressure"], k1_bytes), "density_relaxation": (prof["density"], k2_bytes)}
+    kname = max(sub, key=lambda k: sub[k][0])
+    ms, nbytes = sub[kname]
+    rl = roofline(nbytes, flops, ms, precision)
+    cfg_bytes = configuration_bytes(cnt["inner_pairs"], cnt["contact_pairs"], n_fluid)
+    step_dom = max(breakdown, key=lambda k: breakdown[k]["ms_per_step"])
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -380,25 +465,35 @@ def main():
             "dp": case.dp if cases is None else sorted({c.dp for c in cases}),
             "precision": "FP32 fields and pair arithmetic; FP64 positions, clock, diagnostics"
             if precision == 1 else "FP64",
+            "window": f"advection steps {start_step + args.warmup} to {start_step + args.warmup + steps_done} "
+                      f"(after {start_step} untimed set-up and {args.warmup} warm-up steps)",
             "acoustic_substeps": int(nsub),
-            "substeps_per_step": round(nsub / max(steps_all, 1), 3),
+            "substeps_per_step": round(nsub_per_step, 3),
             "pair_evals_per_s": round(pair_evals, 1),
             "t_start": d0[0]["t"],
             "t_end": d1[0]["t"],
             "kernel_ms": {k: round(v, 5) for k, v in prof.items()},
+            "kernels_per_step": breakdown,
+            "step_dominant_kernel": step_dom,
             "pair_lanes": lanes,
+            "whole_run": whole_run,
         },
         "roofline": {
             "kernel": kname,
-            "bound": "hbm" if t_hbm >= t_alu else "alu",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bound": rl["bound"],
+            "achieved": round(rl["achieved"], 3),
+            "peak": rl["peak"],
+            "unit": rl["unit"],
+            "frac": round(rl["frac"], 4),
             "traffic": measured_traffic(case.name if cases is None else "ensemble64", kname),
             "alg_bytes_per_launch": int(nbytes),
             "alg_flops_per_launch": int(flops),
-            "alu_frac": round(flops / (ms * 1e-3) / (valu * 1e12), 4),
+            "ms_per_launch": round(ms, 5),
+            "hbm_frac": round(rl["hbm_frac"], 4),
+            "alu_frac": round(rl["alu_frac"], 4),
+            "config_bytes_per_launch": cfg_bytes,
+            "hbm_frac_with_config": round((nbytes + cfg_bytes) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "step_dominant_kernel": step_dom,
         },
     }
     if not args.no_cpu_baseline:
