@@ -325,18 +325,6 @@ int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes, double* times);
  * another value. */
 int sphx_set_lanes(sphx_ctx* ctx, int32_t lanes);
 
-/* Switch the LDS staging of neighbour-cell rows on (on != 0) or off (the
- * default: measured slower on MI355X, where these kernels are bound by
- * vector-ALU issue, not by their neighbour loads). Where it applies (3D, FP32, no case periodic along x) the
- * neighbour build and the two relaxations copy, per tile of 64 particles,
- * the slot ranges of the stencil rows of its cell rows into LDS and read
- * neighbour records there (Section 9's cell-linked list: a neighbour lies
- * in the 3^d cells around the particle's cell); elsewhere, and with staging
- * off, they read them from device memory. The arithmetic and its order are
- * the same either way, so the lists and every result are bit-identical.
- * Call between advances. */
-int sphx_set_staging(sphx_ctx* ctx, int32_t on);
-
 /* ---------------------------------------------------------------------
  * Message-passing surrogate (2D contexts only; SPHX_EINVAL in 3D).
  *

@@ -786,176 +786,6 @@ __global__ __launch_bounds__(BLOCK) void k_gather_wall(
 template <int B> struct BodyTag { static constexpr int value = B; };
 
 // ---------------------------------------------------------------------
-// LDS staging of neighbour-cell rows (3D, FP32). The particles of one tile
-// are cut into runs: maximal sequences of consecutive particles in one row
-// of cells (a row runs along x and is contiguous in the cell-sorted order).
-// Every fluid neighbour of a run spanning cells X0..X1 of row (y, z) lies
-// in one of the nine stencil rows (y + dy, z + dz), cells X0 - 1 .. X1 + 1,
-// and each of those is one contiguous slot range [A, B). The block copies
-// these ranges into LDS once, with coalesced loads, and the pair loops read
-// neighbour records there: a list entry j of stencil row r of run q sits at
-// LDS slot j + off[q][r]. Runs beyond the LDS capacity (or beyond SRUNS per
-// tile) read their neighbours from global memory as before, so the result
-// does not depend on what was staged. Requires a non-periodic x axis (rows
-// must not wrap).
-constexpr int SRUNS = 8;                     // runs per tile staged at most
-constexpr int SROWS = 16;                    // off[] stride: row code (dy + 1) | (dz + 1) << 2
-constexpr int SOFF_NONE = -0x7fffffff - 1;   // run not staged
-
-struct StageTab {
-    int off[SRUNS * SROWS];
-    int seg_a[SRUNS * 9], seg_n[SRUNS * 9], seg_b[SRUNS * 9];  // global start, length, LDS base
-    int rrow[SRUNS], rx0[SRUNS], rx1[SRUNS];
-    int runof[TILE];  // run of each particle of the tile, -1 if its run is not staged
-    int nrun, nseg, nstaged;
-};
-
-// LDS of a staged kernel: the table and CAP records per staged array (a
-// placeholder byte where the kernel does not stage).
-template <typename R, int CAP, int NREC> struct StageLds {
-    StageTab tb;
-    uint8_t seg[CAP];  // segment of each staged slot
-    R r0[CAP];
-    R r1[NREC == 2 ? CAP : 1];
-};
-template <bool B, typename X, typename Y> struct SelT { using T = X; };
-template <typename X, typename Y> struct SelT<false, X, Y> { using T = Y; };
-
-// Row code of a list entry: (dy + 1) | (dz + 1) << 2 from its stencil code.
-__device__ __forceinline__ int entry_row(uint32_t e) { return (int)(e >> (NBR_SHIFT + 2)); }
-
-// Stage the stencil rows of the tile starting at slot i0 (all NT threads of
-// the block call this; it ends with a barrier). `cell`: global cell of each
-// slot; `start`: cell starts of the same configuration. Copies NREC record
-// arrays (g0 -> l0, and g1 -> l1 if NREC == 2) of at most `cap` records.
-template <int NREC, int NT, int CAP, typename real, typename R0, typename R1>
-__device__ __forceinline__ void stage_rows(const KP<real>& P, int i0, const int32_t* __restrict__ cell,
-                                           const int32_t* __restrict__ start, StageTab& tb, uint8_t* segof,
-                                           const R0* __restrict__ g0, R0* l0, const R1* __restrict__ g1, R1* l1)
-{
-    constexpr int cap = CAP;
-    const int fend = P.fbase + P.nf;
-    const int n0 = P.n[0];
-    const int tid = threadIdx.x;
-    // runs of the tile, one lane per particle
-    if (tid < 64) {
-        const int i = i0 + tid;
-        const bool act = i < fend;  // the active lanes are a prefix
-        int row = -1, cx = 0;
-        if (act) {
-            const int kc = cell[i] - P.cbase;
-            row = kc / n0;
-            cx = kc - row * n0;
-        }
-        const int prow = __shfl_up(row, 1);
-        const bool head = act && (tid == 0 || prow != row);
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long acts = __ballot(act);
-        const unsigned long long le = tid == 63 ? ~0ull : ((1ull << (tid + 1)) - 1ull);
-        const int run = act ? __popcll(heads & le) - 1 : -1;
-        const bool tail = act && (tid == 63 || !((acts >> (tid + 1)) & 1ull) || ((heads >> (tid + 1)) & 1ull));
-        tb.runof[tid] = run < SRUNS ? run : -1;
-        if (head && run < SRUNS) {
-            tb.rrow[run] = row;
-            tb.rx0[run] = cx;
-        }
-        if (tail && run < SRUNS) tb.rx1[run] = cx;
-        if (tid == 0) tb.nrun = min(__popcll(heads), SRUNS);
-    }
-    __syncthreads();
-    // one entry per (run, stencil row): its slot range
-    if (tid < SRUNS * 9) {
-        const int q = tid / 9, r = tid - 9 * q;
-        int a = 0, n = 0;
-        if (q < tb.nrun) {
-            int c[3];
-            cell_coords(P, tb.rrow[q] * n0, c);
-            const int dy = r % 3 - 1, dz = r / 3 - 1;
-            int cy = c[1] + dy, cz = c[2] + dz;
-            bool ok = true;
-            if (P.periodic[1]) cy = cy < 0 ? cy + P.n[1] : (cy >= P.n[1] ? cy - P.n[1] : cy);
-            else ok = ok && cy >= 0 && cy < P.n[1];
-            if (P.periodic[2]) cz = cz < 0 ? cz + P.n[2] : (cz >= P.n[2] ? cz - P.n[2] : cz);
-            else ok = ok && cz >= 0 && cz < P.n[2];
-            if (ok) {
-                const int rowc = P.cbase + n0 * cell_row(P, cy, cz);
-                const int xlo = max(tb.rx0[q] - 1, 0), xhi = min(tb.rx1[q] + 1, n0 - 1);
-                a = min(start[rowc + xlo], fend);
-                n = max(min(start[rowc + xhi + 1], fend) - a, 0);
-            }
-        }
-        tb.seg_a[tid] = a;
-        tb.seg_n[tid] = n;
-    }
-    __syncthreads();
-    // LDS bases: runs in order while they fit
-    if (tid < 64) {
-        const int q = tid;
-        int tot = 0;
-        if (q < SRUNS)
-            for (int r = 0; r < 9; ++r) tot += tb.seg_n[9 * q + r];
-        int incl = tot;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(incl, o);
-            if (tid >= o) incl += u;
-        }
-        const bool staged = q < tb.nrun && incl <= cap;
-        const int nst = __popcll(__ballot(staged));  // a prefix of the runs
-        if (q < SRUNS) {
-            int b = incl - tot;
-            for (int r = 0; r < 9; ++r) {
-                const int code = (r % 3) | ((r / 3) << 2);
-                tb.seg_b[9 * q + r] = b;
-                tb.off[SROWS * q + code] = staged ? b - tb.seg_a[9 * q + r] : SOFF_NONE;
-                b += tb.seg_n[9 * q + r];
-            }
-        }
-        const int staged_tot = __shfl(incl, nst > 0 ? nst - 1 : 0);  // whole wavefront
-        if (tid == 0) {
-            tb.nseg = 9 * nst;
-            tb.nstaged = nst > 0 ? staged_tot : 0;
-        }
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const int q = tb.runof[tid];
-        if (q >= 0 && tb.off[SROWS * q + 5] == SOFF_NONE) tb.runof[tid] = -1;
-    }
-    // segment of every staged slot (LDS writes only), then the copy with all
-    // of a thread's loads in flight together
-    const int nseg = tb.nseg, ntot = tb.nstaged;
-    for (int sg = 0; sg < nseg; ++sg) {
-        const int n = __builtin_amdgcn_readfirstlane(tb.seg_n[sg]);
-        const int b = __builtin_amdgcn_readfirstlane(tb.seg_b[sg]);
-        for (int k = tid; k < n; k += NT) segof[b + k] = (uint8_t)sg;
-    }
-    __syncthreads();
-    constexpr int PER = (CAP + NT - 1) / NT;
-    R0 v0[PER];
-    R1 v1[NREC == 2 ? PER : 1];
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int k = tid + m * NT;
-        if (k < ntot) {
-            const int sg = segof[k];
-            const int j = tb.seg_a[sg] + (k - tb.seg_b[sg]);
-            v0[m] = g0[j];
-            if constexpr (NREC == 2) v1[m] = g1[j];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-        const int k = tid + m * NT;
-        if (k < ntot) {
-            l0[k] = v0[m];
-            if constexpr (NREC == 2) l1[k] = v1[m];
-        }
-    }
-    __syncthreads();
-}
-
-// ---------------------------------------------------------------------
 // S2: neighbour configuration. For each fluid particle scan the 3^d cells
 // around its cell in the fluid and wall cell lists and keep j != i with
 // r^2 < (2h)^2, the predicate evaluated exactly as stated on the FP64
@@ -978,7 +808,7 @@ __device__ __forceinline__ void stage_rows(const KP<real>& P, int i0, const int3
 // re-initialisation (Eq. eqrhosum / eqrhosumnosurface) here, saving a
 // launch: the kernel sum over the accepted neighbours is taken while they
 // are found, from the frozen offsets.
-template <int D, typename real, int T, int TB, bool STAGED = false>
+template <int D, typename real, int T, int TB>
 __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int force,
     const double* __restrict__ x0, const double* __restrict__ x1, const double* __restrict__ x2,
@@ -1000,19 +830,6 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const int i = b * TILE + (int)threadIdx.x / TB;
     const int l = threadIdx.x % TB;
     const int fend = P.fbase + P.nf, wend = P.wbase + P.nw;
-    // 3D FP32: the fluid candidates of the tile's stencil rows come from LDS
-    constexpr int SCAP = 2048;
-    __shared__ typename SelT<STAGED, StageLds<G, SCAP, 1>, char>::T lds;
-    int srun = -1;
-    const G* stage_rec = nullptr;  // the staged offsets (LDS)
-    const int* stage_off = nullptr;  // LDS slot offsets of the particle's run, by row code
-    if constexpr (STAGED) {
-        static_assert(D == 3 && sizeof(real) == 4, "staged build: 3D FP32");
-        stage_rows<1, TILE * TB, SCAP>(P, b * TILE, cell, fstart, lds.tb, lds.seg, geo, lds.r0, geo, lds.r1);
-        srun = lds.tb.runof[threadIdx.x / TB];
-        stage_rec = lds.r0;
-        stage_off = lds.tb.off + SROWS * (srun >= 0 ? srun : 0);
-    }
     if (i >= fend) return;  // whole lane groups leave together
     const int gbase = (int)(threadIdx.x & 63) & ~(TB - 1);
     const unsigned long long gmask = TB == 64 ? ~0ull : ((1ull << TB) - 1ull);
@@ -1032,10 +849,9 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     // compile-time constant so that every choice below is static); cell
     // offset in x from the range boundaries b1, b2 (first candidate of the
     // 2nd and 3rd cell).
-    auto scan = [&](auto bodyc, auto srcc, int soff, int j0, int j1, int b1, int b2, int dcx0, uint32_t tag_yz)
+    auto scan = [&](auto bodyc, int j0, int j1, int b1, int b2, int dcx0, uint32_t tag_yz)
                     __attribute__((always_inline)) {
         constexpr int BODY = decltype(bodyc)::value;
-        constexpr bool FROM_LDS = decltype(srcc)::value == 1;  // candidate offsets at LDS slot j + soff
         const G* csrc = BODY ? wgeo : geo;
         const double* bx0 = BODY ? wx0 : x0;
         const double* bx1 = BODY ? wx1 : x1;
@@ -1054,9 +870,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
 #pragma unroll
             for (int u = 0; u < NBATCH; ++u) {
                 const int j = min(jb + u * TB + l, j1 - 1);
-                if constexpr (FROM_LDS) {
-                    oj[u] = stage_rec[j + soff];
-                } else if constexpr (PREFILTER) {
+                if constexpr (PREFILTER) {
                     oj[u] = csrc[j];
                 } else {
                     xq[u][0] = bx0[j];
@@ -1114,33 +928,24 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     };
 
     // One stencil row (three x-adjacent cells) of one body.
-    auto row_from = [&](auto bodyc, auto srcc, int soff, int rowc, uint32_t tag_yz) __attribute__((always_inline)) {
+    auto row = [&](auto bodyc, int rowc, uint32_t tag_yz) __attribute__((always_inline)) {
         constexpr int BODY = decltype(bodyc)::value;
         const int32_t* st_ = BODY ? wstart : fstart;
         const int lim = BODY ? wend : fend;
         if (ci[0] >= 1 && ci[0] + 1 < P.n[0]) {
             // the three cells are contiguous: one range
             const int c = rowc + ci[0];
-            scan(bodyc, srcc, soff, min(st_[c - 1], lim), min(st_[c + 2], lim), min(st_[c], lim),
-                 min(st_[c + 1], lim), -1, tag_yz);
+            scan(bodyc, min(st_[c - 1], lim), min(st_[c + 2], lim), min(st_[c], lim), min(st_[c + 1], lim), -1,
+                 tag_yz);
         } else {
             for (int dx = -1; dx <= 1; ++dx) {
                 int cx = ci[0] + dx;
                 if (P.periodic[0]) cx = cx < 0 ? cx + P.n[0] : (cx >= P.n[0] ? cx - P.n[0] : cx);
                 else if (cx < 0 || cx >= P.n[0]) continue;
                 const int c = rowc + cx;
-                scan(bodyc, srcc, soff, min(st_[c], lim), min(st_[c + 1], lim), 0x7fffffff, 0x7fffffff, dx, tag_yz);
+                scan(bodyc, min(st_[c], lim), min(st_[c + 1], lim), 0x7fffffff, 0x7fffffff, dx, tag_yz);
             }
         }
-    };
-    auto row = [&](auto bodyc, int rowc, uint32_t tag_yz) __attribute__((always_inline)) {
-        if constexpr (STAGED && decltype(bodyc)::value == 0) {
-            if (srun >= 0) {
-                row_from(bodyc, BodyTag<1>{}, stage_off[(int)(tag_yz >> 2)], rowc, tag_yz);
-                return;
-            }
-        }
-        row_from(bodyc, BodyTag<0>{}, 0, rowc, tag_yz);
     };
 
     const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
@@ -1475,10 +1280,7 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
 // with fluid and wall neighbours and gravity, velocity update. T lanes share
 // a particle: each takes every T-th neighbour, partial sums are combined
 // with shuffles and lane 0 writes.
-// Pair-loop LDS capacity of the staged 3D kernels (records per array).
-constexpr int PCAP = 1280;
-
-template <int D, typename real, int T, bool MOVE, int NT = pair_threads<T>(), bool STAGED = false>
+template <int D, typename real, int T, bool MOVE>
 __device__ __forceinline__ void pressure_body(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
@@ -1486,11 +1288,9 @@ __device__ __forceinline__ void pressure_body(
     const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
     const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
     real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all,
-    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg,
-    const int32_t* __restrict__ cell = nullptr, const int32_t* __restrict__ fstart = nullptr,
-    typename SelT<STAGED, StageLds<R4<real>, PCAP, 2>, char>::T* ldsp = nullptr)
+    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
-    const int i0 = xcd_block(blockIdx.x, gridDim.x) * (NT / T);
+    const int i0 = pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x));
     const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
     Ctrl* ctrl = ctrl_all + P.case_id;
     unsigned long long* vslot = vslot_all + (size_t)P.case_id * 2 * VSLOTS;
@@ -1521,16 +1321,10 @@ __device__ __forceinline__ void pressure_body(
     }
     if (first && threadIdx.x < VSLOTS) vslot[(q & 1) * VSLOTS + threadIdx.x] = 0ull;
     if (!S.active || err) return;
-    using G = typename GeoSel<D, real>::T;
-    int srun = -1;
-    if constexpr (STAGED) {
-        static_assert(D == 3 && sizeof(real) == 4 && NT == TILE * T, "staged pair kernels: 3D FP32, one tile per block");
-        stage_rows<2, NT, PCAP>(P, i0, cell, fstart, ldsp->tb, ldsp->seg, geo, ldsp->r0, st, ldsp->r1);
-        srun = ldsp->tb.runof[threadIdx.x / T];
-    }
     const int i = i0 + (int)threadIdx.x / T;
     const int l = threadIdx.x % T;
     if (i >= P.fbase + P.nf) return;
+    using G = typename GeoSel<D, real>::T;
     const real dt = (real)S.dt;
     const real half = (real)0.5 * dt;
     // moving walls: velocity rates at the sub-step's start (the level of v^n),
@@ -1556,7 +1350,16 @@ __device__ __forceinline__ void pressure_body(
     real acc[3] = {0, 0, 0};
     struct FluidJ { G o; R4<real> s; };
     struct WallJ { G o; G n; R4<real> k, g; };
-    auto fluid_pair = [&](uint32_t e, const FluidJ& r) {
+    for_pairs<T, BATCH>(
+        nbr, i, ncnt[i], P.maxn, l,
+        [&](uint32_t e) {
+            uint32_t j = e & NBR_MASK;
+            FluidJ r;
+            r.o = geo[j];
+            r.s = st[j];
+            return r;
+        },
+        [&](uint32_t e, const FluidJ& r) {
             Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
             const R4<real>& sj = r.s;
             // 3D: the neighbour's density rate is the w of its frozen offsets
@@ -1574,35 +1377,7 @@ __device__ __forceinline__ void pressure_body(
             acc[0] -= cd * pq.d[0];
             acc[1] -= cd * pq.d[1];
             if (D == 3) acc[2] -= cd * pq.d[2];
-        };
-    bool from_lds = false;
-    if constexpr (STAGED) {
-        if (srun >= 0) {
-            from_lds = true;
-            const int* offr = ldsp->tb.off + SROWS * srun;
-            for_pairs<T, BATCH>(
-                nbr, i, ncnt[i], P.maxn, l,
-                [&](uint32_t e) {
-                    const int slot = (int)(e & NBR_MASK) + offr[entry_row(e)];
-                    FluidJ r;
-                    r.o = ldsp->r0[slot];
-                    r.s = ldsp->r1[slot];
-                    return r;
-                },
-                fluid_pair);
-        }
-    }
-    if (!from_lds)
-        for_pairs<T, BATCH>(
-            nbr, i, ncnt[i], P.maxn, l,
-            [&](uint32_t e) {
-                uint32_t j = e & NBR_MASK;
-                FluidJ r;
-                r.o = geo[j];
-                r.s = st[j];
-                return r;
-            },
-            fluid_pair);
+        });
     for_pairs<T, BATCH>(
         wnb, i, wcnt[i], P.maxw, l,
         [&](uint32_t e) {
@@ -1698,7 +1473,7 @@ __global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR void k_pressure(
 // position half-steps land here, in the paper's order) and density, and the
 // block maxima of |v| for the next acoustic step. T lanes share a particle
 // as in S6.
-template <int D, typename real, int T, bool MOVE, int NT = pair_threads<T>(), bool STAGED = false>
+template <int D, typename real, int T, bool MOVE>
 __device__ __forceinline__ void density_body(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int finalize,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
@@ -1707,26 +1482,16 @@ __device__ __forceinline__ void density_body(
     const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
     double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
     unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt,
-    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg,
-    const int32_t* __restrict__ cell = nullptr, const int32_t* __restrict__ fstart = nullptr,
-    typename SelT<STAGED, StageLds<R4<real>, PCAP, 2>, char>::T* ldsp = nullptr)
+    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg)
 {
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int i0 = b * (NT / T);
+    const int i0 = pair_block_first<T>(b);
     const KP<real> P = Pt[tcase[i0 / TILE]];  // a copy: the fields stay in registers through the loops
     Ctrl* ctrl = ctrl_all + P.case_id;
     const SubState S = ctrl->ss[q & 1];
     if (!S.active || ctrl->err) return;
-    __shared__ double smax[NT / 64];
+    __shared__ double smax[BLOCK / 64];
     using G = typename GeoSel<D, real>::T;
-    int srun = -1;
-    if constexpr (STAGED) {
-        static_assert(D == 3 && sizeof(real) == 4 && NT == TILE * T, "staged pair kernels: 3D FP32, one tile per block");
-        // (the w of the staged offsets may be this launch's density rate or
-        // the previous one: the density relaxation's pair loop reads x, y, z)
-        stage_rows<2, NT, PCAP>(P, i0, cell, fstart, ldsp->tb, ldsp->seg, geo, ldsp->r0, hf, ldsp->r1);
-        srun = ldsp->tb.runof[threadIdx.x / T];
-    }
     const double dtd = S.dt;
     const real dt = (real)dtd;
     const real half = (real)0.5 * dt;
@@ -1763,7 +1528,16 @@ __device__ __forceinline__ void density_body(
         real sum = 0;
         struct HalfJ { G o; R4<real> h; };
         struct WallJ { G o; G n; R4<real> k, g; };
-        auto fluid_pair = [&](uint32_t e, const HalfJ& r) {
+        for_pairs<T, BATCH>(
+            nbr, i, ncnt[i], P.maxn, l,
+            [&](uint32_t e) {
+                uint32_t j = e & NBR_MASK;
+                HalfJ r;
+                r.o = geo[j];
+                r.h = hf[j];
+                return r;
+            },
+            [&](uint32_t e, const HalfJ& r) {
                 Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
                 const R4<real>& hj = r.h;
                 real dev_j = D == 2 ? hj.z : hj.w;
@@ -1777,35 +1551,7 @@ __device__ __forceinline__ void density_body(
                 // 2 (U* - U_L) = (v_i - v_j) . d / r + 2 c (dev_i - dev_j) / (rho_i + rho_j)
                 real dus2 = dvd * pq.rinv + div_r(two_c * (dev_i - dev_j), rho_i + rho_j);
                 sum += half_m * inv_rho_j * dus2 * pq.dW;
-            };
-        bool from_lds = false;
-        if constexpr (STAGED) {
-            if (srun >= 0) {
-                from_lds = true;
-                const int* offr = ldsp->tb.off + SROWS * srun;
-                for_pairs<T, BATCH>(
-                    nbr, i, ncnt[i], P.maxn, l,
-                    [&](uint32_t e) {
-                        const int slot = (int)(e & NBR_MASK) + offr[entry_row(e)];
-                        HalfJ r;
-                        r.o = ldsp->r0[slot];
-                        r.h = ldsp->r1[slot];
-                        return r;
-                    },
-                    fluid_pair);
-            }
-        }
-        if (!from_lds)
-            for_pairs<T, BATCH>(
-                nbr, i, ncnt[i], P.maxn, l,
-                [&](uint32_t e) {
-                    uint32_t j = e & NBR_MASK;
-                    HalfJ r;
-                    r.o = geo[j];
-                    r.h = hf[j];
-                    return r;
-                },
-                fluid_pair);
+            });
         for_pairs<T, BATCH>(
             wnb, i, wcnt[i], P.maxw, l,
             [&](uint32_t e) {
@@ -1893,7 +1639,7 @@ __device__ __forceinline__ void density_body(
     __syncthreads();
     if (threadIdx.x == 0) {
         double bm = smax[0];
-        for (int w = 1; w < NT / 64; ++w) bm = fmax(bm, smax[w]);
+        for (int w = 1; w < pair_threads<T>() / 64; ++w) bm = fmax(bm, smax[w]);
         // relaxed, result unused: no wait, no fence; read after the kernel ends
         unsigned long long* vslot = vslot_all + (size_t)P.case_id * 2 * VSLOTS;
         atomicMax(&vslot[(q & 1) * VSLOTS + (b & (VSLOTS - 1))], speed_bits((real)bm));
@@ -1939,71 +1685,6 @@ __attribute__((amdgpu_waves_per_eu((D == 2 && !MOVE) ? 8 : 1))) void k_density(
     const KP<real>& P = Pt[tcase[i0 / TILE]];
     Ctrl* ctrl = ctrl_all + P.case_id;
     bin_slots<D>(P, ctrl, update_due(P, ctrl, 0, q), i0, pair_threads<T>() / T, x0, x1, x2, cell, key, rank, cnt);
-}
-
-// Staged 3D FP32 relaxations: one tile per block (TILE * T threads), the
-// tile's stencil rows in LDS (see stage_rows); same arithmetic and list
-// order as k_pressure / k_density, so the results are bit-identical.
-template <int D, typename real, int T, bool MOVE>
-__global__ __launch_bounds__(TILE * T) void k_pressure_st(
-    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
-    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
-    const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
-    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
-    const R4<real>* __restrict__ st, const real* __restrict__ dr3, R4<real>* __restrict__ hf,
-    real* __restrict__ acc_out, int q, int adv, unsigned long long* __restrict__ vslot_all,
-    const R4<real>* __restrict__ avt, const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg,
-    const int32_t* __restrict__ cell, const int32_t* __restrict__ fstart)
-{
-    constexpr int NT = TILE * T;
-    __shared__ StageLds<R4<real>, PCAP, 2> lds;
-    if constexpr (MOVE) {
-        if (!wall_velocity_case(Pt, tcase, xcd_block(blockIdx.x, gridDim.x) * TILE)) {
-            pressure_body<D, real, T, false, NT, true>(
-                Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all,
-                avt, wmot, wvg, cell, fstart, &lds);
-            return;
-        }
-    }
-    pressure_body<D, real, T, MOVE, NT, true>(
-        Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all, avt,
-        wmot, wvg, cell, fstart, &lds);
-}
-
-template <int D, typename real, int T, bool MOVE>
-__global__ __launch_bounds__(TILE * T) void k_density_st(
-    const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all, int finalize,
-    const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
-    const typename GeoSel<D, real>::T* __restrict__ wnrm, const uint32_t* __restrict__ nbr,
-    const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb, const int32_t* __restrict__ wcnt,
-    const R4<real>* __restrict__ hf, R4<real>* __restrict__ st, real* __restrict__ dr3, double* __restrict__ x0,
-    double* __restrict__ x1, double* __restrict__ x2, real* __restrict__ drho_out,
-    unsigned long long* __restrict__ vslot_all, int q, const R4<real>* __restrict__ avt,
-    const R4<real>* __restrict__ wmot, const R4<real>* __restrict__ wvg, int bin,
-    const int32_t* __restrict__ cell, int32_t* __restrict__ key, int32_t* __restrict__ rank,
-    int32_t* __restrict__ cnt, const int32_t* __restrict__ fstart)
-{
-    constexpr int NT = TILE * T;
-    __shared__ StageLds<R4<real>, PCAP, 2> lds;
-    const int i0 = xcd_block(blockIdx.x, gridDim.x) * TILE;
-    bool static_code = !MOVE;
-    if constexpr (MOVE) static_code = !wall_velocity_case(Pt, tcase, i0);
-    if (static_code) {
-        density_body<D, real, T, false, NT, true>(
-            Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2,
-            drho_out, vslot_all, q, avt, wmot, wvg, cell, fstart, &lds);
-    } else {
-        density_body<D, real, T, MOVE, NT, true>(
-            Pt, tcase, ctrl_all, finalize, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st, dr3, x0, x1, x2,
-            drho_out, vslot_all, q, avt, wmot, wvg, cell, fstart, &lds);
-    }
-    if (!bin) return;
-    // the cell binning of the configuration update, as in k_density
-    __syncthreads();
-    if (threadIdx.x >= 64) return;
-    const KP<real>& P = Pt[tcase[i0 / TILE]];
-    Ctrl* ctrl = ctrl_all + P.case_id;
-    bin_slots<D>(P, ctrl, update_due(P, ctrl, 0, q), i0, TILE, x0, x1, x2, cell, key, rank, cnt);
 }
 
 // S5 after the last queued density relaxation, for case c, by one

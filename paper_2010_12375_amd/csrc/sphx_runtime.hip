@@ -77,7 +77,6 @@ struct EngineBase {
     virtual int counts(int c, int64_t* out) = 0;
     virtual int autotune(int32_t reps, int32_t* lanes, double* times) = 0;
     virtual int set_lanes(int32_t lanes) = 0;
-    virtual int set_staging(int32_t on) = 0;
     virtual int set_params_case(int c, const sphx_params* q) = 0;
     virtual int gnn_set_params(const float* p, int64_t n) = 0;
     virtual int gnn_get(int which, float* p, int64_t n) = 0;
@@ -124,7 +123,6 @@ struct Engine final : EngineBase {
     hipStream_t s;
     static constexpr int LB = 4;  // lanes per particle in the neighbour build (one tile per block)
     int ln = D == 2 ? 4 : 8;      // lanes per particle in the pair kernels (2, 4, 8 or 16)
-    bool stage_on = false;        // LDS staging of neighbour-cell rows where the case allows it (3D FP32)
     int C = 0;                    // cases
     std::vector<KP<real>> hP;     // parameter table (host copy)
     KP<real>* dP = nullptr;
@@ -948,74 +946,15 @@ struct Engine final : EngineBase {
     // a step ended or `force`, the identity elsewhere). The cell counters are
     // zero on entry (zeroed at allocation and by every scan that consumes
     // them).
-    // Whether the build and the relaxations stage their neighbour-cell rows
-    // in LDS: 3D FP32 with no case periodic along x, unless switched off.
-    static constexpr bool kStageable = D == 3 && std::is_same<real, float>::value;
-    bool staged() const
-    {
-        if (!kStageable || !stage_on) return false;
-        for (int c = 0; c < C; ++c)
-            if (hP[c].periodic[0]) return false;
-        return true;
-    }
-
     template <int T>
     void launch_neighbors(int force, int b, int reinit = 0)
     {
         // with two lanes per particle in the pair kernels (large 2D batches,
         // issue-bound) the build packs two lanes per particle as well
         constexpr int TB = T < LB ? T : LB;
-        if constexpr (kStageable) {
-            if (staged()) {
-                k_neighbors<D, real, T, TB, true><<<ntiles, TILE * TB, 0, s>>>(
-                    dP, tcase, ctrl, force, x[b][0], x[b][1], x[b][2], cell[b], fstart, geo[b], wx[0], wx[1], wx[2],
-                    wstart, wgeo, nbr, ncnt, wnb, wcnt, reinit, st[b]);
-                return;
-            }
-        }
         k_neighbors<D, real, T, TB><<<ntiles, TILE * TB, 0, s>>>(dP, tcase, ctrl, force, x[b][0], x[b][1], x[b][2],
                                                                 cell[b], fstart, geo[b], wx[0], wx[1], wx[2], wstart,
                                                                 wgeo, nbr, ncnt, wnb, wcnt, reinit, st[b]);
-    }
-
-    // The two relaxations of one sub-step on set a (staged or not).
-    template <int T>
-    void launch_pressure(int a, int q, int adv, real* acc)
-    {
-        by_motion([&](auto mc) {
-            constexpr bool MV = decltype(mc)::value;
-            if constexpr (kStageable) {
-                if (staged()) {
-                    k_pressure_st<D, real, T, MV><<<ntiles, TILE * T, 0, s>>>(
-                        dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, acc, q, adv,
-                        vslot, avt_arg(), wmot_arg(), wvg_arg(), cell[a], fstart);
-                    return;
-                }
-            }
-            k_pressure<D, real, T, MV><<<pair_blocks(), pair_threads<T>(), 0, s>>>(
-                dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, acc, q, adv, vslot,
-                avt_arg(), wmot_arg(), wvg_arg());
-        });
-    }
-
-    template <int T>
-    void launch_density(int a, int q, int finalize, real* dro, int bin)
-    {
-        by_motion([&](auto mc) {
-            constexpr bool MV = decltype(mc)::value;
-            if constexpr (kStageable) {
-                if (staged()) {
-                    k_density_st<D, real, T, MV><<<ntiles, TILE * T, 0, s>>>(
-                        dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st[a], dr3[a],
-                        x[a][0], x[a][1], x[a][2], dro, vslot, q, avt_arg(), wmot_arg(), wvg_arg(), bin, cell[a], key,
-                        rank, cnt, fstart);
-                    return;
-                }
-            }
-            k_density<D, real, T, MV><<<pair_blocks(), pair_threads<T>(), 0, s>>>(
-                dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
-                x[a][1], x[a][2], dro, vslot, q, avt_arg(), wmot_arg(), wvg_arg(), bin, cell[a], key, rank, cnt);
-        });
     }
 
     // `q` >= 0: at the end of a queue whose last sub-step is q (the scan
@@ -1044,8 +983,18 @@ struct Engine final : EngineBase {
     template <int T>
     void launch_substep(int a, int q, int adv, int finalize, real* acc, real* dro, int bin)
     {
-        launch_pressure<T>(a, q, adv, acc);
-        launch_density<T>(a, q, finalize, dro, bin);
+        const int nb = pair_blocks();
+        R4<real>* av = avt_arg();
+        R4<real>* wm = wmot_arg();
+        R4<real>* wg = wvg_arg();
+        by_motion([&](auto mc) {
+            constexpr bool MV = decltype(mc)::value;
+            k_pressure<D, real, T, MV><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
+                                                            st[a], dr3[a], hf, acc, q, adv, vslot, av, wm, wg);
+            k_density<D, real, T, MV><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt,
+                                                           wnb, wcnt, hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2],
+                                                           dro, vslot, q, av, wm, wg, bin, cell[a], key, rank, cnt);
+        });
     }
 
     // Pressure and density relaxation of sub-step q on set a; `adv`: close
@@ -1611,8 +1560,21 @@ struct Engine final : EngineBase {
     {
         const int nb = pair_blocks();
         const int a = cur;
-        RETCHK(time_launches(reps, &ms[0], [&] { launch_pressure<T>(a, 0, 0, nullptr); }));
-        RETCHK(time_launches(reps, &ms[1], [&] { launch_density<T>(a, 0, 1, nullptr, 0); }));
+        RETCHK(time_launches(reps, &ms[0], [&] {
+            by_motion([&](auto mc) {
+                k_pressure<D, real, T, decltype(mc)::value><<<nb, pair_threads<T>(), 0, s>>>(
+                    dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, nullptr, 0, 0,
+                    vslot, avt_arg(), wmot_arg(), wvg_arg());
+            });
+        }));
+        RETCHK(time_launches(reps, &ms[1], [&] {
+            by_motion([&](auto mc) {
+                k_density<D, real, T, decltype(mc)::value><<<nb, pair_threads<T>(), 0, s>>>(
+                    dP, tcase, ctrl, 1, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, hf, st[a], dr3[a], x[a][0],
+                    x[a][1], x[a][2], nullptr, vslot, 0, avt_arg(), wmot_arg(), wvg_arg(), 0, nullptr, nullptr, nullptr,
+                    nullptr);
+            });
+        }));
         // the list build is idempotent on the current set
         RETCHK(time_launches(reps, &ms[2], [&] { launch_neighbors<T>(1, a); }));
         RETCHK(time_launches(reps, &ms[3], [&] {
@@ -1717,15 +1679,6 @@ struct Engine final : EngineBase {
 
     // Set the lanes per particle of the pair kernels; an existing
     // configuration is rebuilt in the new list layout (the same lists).
-    int set_staging(int32_t on) override
-    {
-        if ((on != 0) == stage_on) return SPHX_OK;
-        HIPCHK(hipStreamSynchronize(s));
-        stage_on = on != 0;
-        drop_graphs();  // captured graphs hold the kernel choice
-        return SPHX_OK;
-    }
-
     int set_lanes(int32_t lanes) override
     {
         const bool ok = D == 2 ? (lanes == 2 || lanes == 4 || lanes == 8) : (lanes == 4 || lanes == 8 || lanes == 16);
@@ -2459,8 +2412,6 @@ int sphx_counts(sphx_ctx* ctx, int64_t* out) { ENG_CALL(counts(-1, out)); }
 int sphx_counts_case(sphx_ctx* ctx, int32_t c, int64_t* out) { ENG_CALL(counts(c, out)); }
 
 int sphx_set_lanes(sphx_ctx* ctx, int32_t lanes) { ENG_CALL(set_lanes(lanes)); }
-
-int sphx_set_staging(sphx_ctx* ctx, int32_t on) { ENG_CALL(set_staging(on)); }
 
 int sphx_autotune(sphx_ctx* ctx, int32_t reps, int32_t* lanes, double* times)
 {

@@ -32,7 +32,7 @@ EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_set_para
             "sphx_build_neighbors", "sphx_get_neighbors", "sphx_get_neighbors_case", "sphx_density_reinit",
             "sphx_time_steps", "sphx_time_steps_case", "sphx_compute_rates", "sphx_compute_rates_case",
             "sphx_advance", "sphx_case_status", "sphx_get_field", "sphx_get_field_case", "sphx_diagnostics",
-            "sphx_diagnostics_case", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune", "sphx_set_lanes", "sphx_set_staging",
+            "sphx_diagnostics_case", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune", "sphx_set_lanes",
             "sphx_gnn_num_params", "sphx_gnn_set_params", "sphx_gnn_get_params", "sphx_gnn_get_grad",
             "sphx_gnn_forward", "sphx_gnn_get_output_case", "sphx_gnn_set_target_case", "sphx_gnn_train_step",
             "sphx_gnn_profile", "sphx_surrogate_advance")
@@ -115,7 +115,6 @@ def load(path=None):
         "sphx_counts_case": [vp, i32, pi64],
         "sphx_autotune": [vp, i32, C.POINTER(i32), pd],
         "sphx_set_lanes": [vp, i32],
-        "sphx_set_staging": [vp, i32],
         "sphx_gnn_set_params": [vp, vp, i64],
         "sphx_gnn_get_params": [vp, vp, i64],
         "sphx_gnn_get_grad": [vp, vp, i64],
@@ -434,10 +433,6 @@ class Simulation:
     def set_lanes(self, lanes):
         """Lanes per particle of the pair kernels (2, 4, 8 in 2D; 4, 8, 16 in 3D)."""
         self._check(self._L.sphx_set_lanes(self._h, int(lanes)), "sphx_set_lanes")
-
-    def set_staging(self, on):
-        """LDS staging of neighbour-cell rows (3D FP32; bit-identical results)."""
-        self._check(self._L.sphx_set_staging(self._h, int(bool(on))), "sphx_set_staging")
 
     def autotune(self, reps=10, with_times=False):
         lanes = C.c_int32()
