@@ -212,13 +212,18 @@ int sphx_set_fluid_device(sphx_ctx* ctx, int32_t c, int64_t n, const double* pos
  * values). Returns when the copy is complete. */
 int sphx_get_field_device(sphx_ctx* ctx, int32_t c, int field, double* out);
 
-/* Checkpoint (save and load of a run): sphx_save writes the parameters of
+/* Checkpoint (save and load of a run; the restart files of the paper's I/O
+ * table, Section 9): sphx_save writes the parameters of
  * every case, its walls, wall motion and given wall velocities, its clock
  * and time step state, and its particle state in the library's current slot
  * order to `path`; sphx_load restores such a file into a context created with the
  * same parameters (same number of cases, dimension, precision and every
  * sphx_params field except nsub_queue; SPHX_EINVAL otherwise or for a
- * truncated or foreign file). The neighbour configuration is rebuilt on the
+ * truncated or foreign file, and for corrupt contents, checked on the host
+ * before anything is uploaded: particle ids that are not a permutation of
+ * each case's particles, non-finite positions, state, walls or motion, a
+ * negative or non-finite clock or step state, unknown error bits; the
+ * context is then unchanged). The neighbour configuration is rebuilt on the
  * next call that needs it; from the restored state the run continues bit for
  * bit as the saved context would have, given the same lanes per particle
  * (sphx_set_lanes; not part of the file). The surrogate's parameters are not
@@ -236,7 +241,9 @@ int sphx_load(sphx_ctx* ctx, const char* path);
  * (SPHX_ESTATE otherwise). */
 int sphx_build_neighbors(sphx_ctx* ctx);
 
-/* Neighbour lists as CSR of original ids, ascending within each row.
+/* Neighbour lists (the inner and contact relations of Section 9; the
+ * particle table's neighbor_relation unit holds this configuration) as CSR
+ * of original ids, ascending within each row.
  * kind: SPHX_INNER or SPHX_CONTACT. off: n_fluid + 1 entries (may be NULL);
  * idx: cap entries (may be NULL). *n_out receives the number of entries;
  * SPHX_ECAP if idx is given and cap < *n_out. */
@@ -251,8 +258,9 @@ int sphx_get_neighbors_case(sphx_ctx* ctx, int32_t c, int kind, int64_t* off, in
  * neighbours; every case. */
 int sphx_density_reinit(sphx_ctx* ctx);
 
-/* The two time-step criteria for the current state (Eqs. dt-advection
- * without viscosity, |v|max floored at u_ref, and dt-relax). */
+/* The two time-step criteria for the current state (Eq. dt-advection with
+ * |v|max floored at u_ref and, for a case with viscosity eta > 0, the
+ * h^2/nu limit, nu = eta/rho0; Eq. dt-relax). */
 int sphx_time_steps(sphx_ctx* ctx, double* dt_ad, double* dt_ac);
 int sphx_time_steps_case(sphx_ctx* ctx, int32_t c, double* dt_ad, double* dt_ac);
 
@@ -264,7 +272,8 @@ int sphx_time_steps_case(sphx_ctx* ctx, int32_t c, double* dt_ad, double* dt_ac)
 int sphx_compute_rates(sphx_ctx* ctx, double dt, double* dvdt, double* drhodt);
 int sphx_compute_rates_case(sphx_ctx* ctx, int32_t c, double dt, double* dvdt, double* drhodt);
 
-/* Advance every case by up to n_steps advection steps (each: dt_ad, density
+/* Advance every case by up to n_steps advection steps (the dual-criteria
+ * time stepping of Section 2.4; each: dt_ad, density
  * re-initialisation, acoustic sub-steps until the step is covered, the last
  * clipped to land on it, then the configuration update), each case stopping
  * early when its clock reaches t_stop (a step is clipped to end exactly on
@@ -283,11 +292,16 @@ int sphx_advance(sphx_ctx* ctx, int32_t n_steps, double t_stop, int64_t* n_subst
  * batch succeeds). */
 int sphx_case_status(sphx_ctx* ctx, int32_t c);
 
-/* Field in original order as FP64 (SPHX_FIELD_*). */
+/* Field in original order as FP64 (SPHX_FIELD_*; the particle fields the
+ * paper's observers and state output write, Section 9 I/O table). */
 int sphx_get_field(sphx_ctx* ctx, int field, double* out);
 int sphx_get_field_case(sphx_ctx* ctx, int32_t c, int field, double* out);
 
-/* FP64 global observables of the current state (reduced on the device). */
+/* FP64 global observables of the current state (reduced on the device):
+ * mass, momentum, kinetic, potential and internal energy (the work of the
+ * EoS, Eq. eqeos), surge front and the largest density deviation (the
+ * quantity Section 2.1 keeps near 1 %), for the paper's observers
+ * (Section 9 I/O table). */
 int sphx_diagnostics(sphx_ctx* ctx, sphx_diag* out);
 
 /* The same for case c into out[0]; for c < 0, every case into out[0 ..

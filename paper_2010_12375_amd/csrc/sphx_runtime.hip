@@ -1390,6 +1390,61 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
+    // Sanity of a checkpoint's contents (SPHX_EINVAL with the reason): the
+    // particle ids of each case's used slots are a permutation of [0, nf)
+    // (they become write indices when fields are returned in original
+    // order); positions, particle state, walls and motion are finite; the
+    // control block holds a finite, non-negative clock and step state,
+    // flags that are 0 or 1, non-negative counters and known error bits.
+    template <typename Rec>
+    int check_loaded(const std::vector<Rec>& rec, const std::vector<std::vector<double>>& hx,
+                     const std::vector<R4<real>>& hs, const std::vector<real>& hd, const std::vector<int32_t>& hi)
+    {
+        auto bad = [&](int c, const char* what) { return ctx->fail(SPHX_EINVAL, case_tag(c) + "corrupt checkpoint: " + what); };
+        auto fin = [](double v) { return std::isfinite(v); };
+        const uint32_t known = ERR_ESCAPE | ERR_NAN | ERR_NBR_OVERFLOW;
+        for (int c = 0; c < C; ++c) {
+            const Rec& r = rec[c];
+            const int nf = r.lay[0], base = r.lay[2];
+            std::vector<char> seen((size_t)nf, 0);
+            for (int i = base; i < base + nf; ++i) {
+                const int32_t v = hi[(size_t)i];
+                if (v < 0 || v >= nf || seen[(size_t)v]) return bad(c, "particle ids are not a permutation");
+                seen[(size_t)v] = 1;
+                for (int k = 0; k < D; ++k)
+                    if (!fin(hx[k][(size_t)i])) return bad(c, "non-finite position");
+                const R4<real>& q = hs[(size_t)i];
+                if (!fin((double)q.x) || !fin((double)q.y) || !fin((double)q.z) || !fin((double)q.w))
+                    return bad(c, "non-finite particle state");
+                if (D == 3 && !fin((double)hd[(size_t)i])) return bad(c, "non-finite density rate");
+            }
+            for (double v : r.wp)
+                if (!fin(v)) return bad(c, "non-finite wall position");
+            for (double v : r.wn)
+                if (!fin(v)) return bad(c, "non-finite wall normal");
+            for (double v : r.wv)
+                if (!fin(v)) return bad(c, "non-finite wall velocity");
+            for (int32_t v : r.fl)
+                if (v != 0 && v != 1) return bad(c, "wall motion flags other than 0 or 1");
+            for (double v : r.mo)
+                if (!fin(v)) return bad(c, "non-finite wall motion");
+            if (r.wmove != 0 && r.wmove != 1) return bad(c, "wall motion switch other than 0 or 1");
+            const Ctrl& k = r.k;
+            if (!fin(k.t) || k.t < 0.0 || !fin(k.t_end) || k.t_end < 0.0 || std::isnan(k.t_stop) ||
+                !fin(k.dt_ad) || k.dt_ad < 0.0 || !fin(k.vmax) || k.vmax < 0.0)
+                return bad(c, "clock or time step state");
+            for (const SubState& q : k.ss)
+                if (!fin(q.tau) || q.tau < 0.0 || !fin(q.dt) || q.dt < 0.0 || (q.last != 0 && q.last != 1) ||
+                    (q.active != 0 && q.active != 1) || q.nsub < 0)
+                    return bad(c, "sub-step state");
+            if ((k.midstep != 0 && k.midstep != 1) || (k.rebuild != 0 && k.rebuild != 1) || k.nsub_total < 0 ||
+                k.steps_done < 0 || k.steps_target < 0)
+                return bad(c, "step counters");
+            if ((k.err & ~known) || (k.err_pending & ~known)) return bad(c, "unknown error bits");
+        }
+        return SPHX_OK;
+    }
+
     int load(const char* path) override
     {
         if (!path) return ctx->fail(SPHX_EINVAL, "no checkpoint path");
@@ -1459,6 +1514,9 @@ struct Engine final : EngineBase {
         std::vector<int32_t> hi(n);
         get(hi.data(), n * sizeof(int32_t));
         if (!ok) return ctx->fail(SPHX_EINVAL, "truncated checkpoint");
+        // Everything below indexes device and host memory by these values:
+        // check them all on the host before anything reaches the device.
+        RETCHK(check_loaded(rec, hx, hs, hd, hi));
         // layout exactly as saved, state into set 0
         HIPCHK(hipStreamSynchronize(s));
         for (int c = 0; c < C; ++c) {

@@ -224,6 +224,48 @@ def test_checkpoint_refused_for_other_parameters(tmp_path):
         d.load(bad)
 
 
+@pytest.mark.parametrize("flaw", ["duplicate_id", "id_out_of_range", "nan_position", "nan_clock", "error_bits"])
+def test_checkpoint_with_corrupt_contents_refused(flaw, tmp_path):
+    """A full-length checkpoint whose contents are corrupt (ids that are not
+    a permutation, non-finite positions or clock, unknown error bits) is
+    refused with SPHX_EINVAL, and the context stays usable."""
+    import ctypes as C
+    case = wl.config_small(0)
+    a = sphx.Simulation.from_case(case, FP32)
+    a.advance(2)
+    path = tmp_path / "run.ckpt"
+    a.save(path)
+    raw = bytearray(path.read_bytes())
+    n = ((case.n_fluid + 63) // 64) * 64          # slots of the one case (whole tiles)
+    ids = len(raw) - 4 * n                         # the ids close the file
+    pos0 = ids - 16 * n - 8 * n * case.dim         # FP32 records (16 B) before the ids, positions before them
+    ctrl = 8 + 16 + C.sizeof(sphx.sphx_params) + 16  # magic, header, parameters, layout
+    if flaw == "duplicate_id":
+        raw[ids + 4:ids + 8] = raw[ids:ids + 4]
+    elif flaw == "id_out_of_range":
+        raw[ids:ids + 4] = np.int32(case.n_fluid).tobytes()
+    elif flaw == "nan_position":
+        raw[pos0 + 8 * 5:pos0 + 8 * 6] = np.float64(np.nan).tobytes()
+    elif flaw == "nan_clock":
+        raw[ctrl:ctrl + 8] = np.float64(np.nan).tobytes()
+    else:
+        err = ctrl + 5 * 8 + 8 + 2 * 32 + 2 * 4 + 3 * 8  # Ctrl.err after the doubles, sub-steps, flags, counters
+        raw[err:err + 4] = np.uint32(1 << 7).tobytes()
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(bytes(raw))
+    b = sphx.Simulation(sphx.params_from_case(case, FP32))
+    b.set_fluid(case.fluid_pos)
+    b.set_walls(case.wall_pos, case.wall_normal)
+    with pytest.raises(sphx.SphxError) as e:
+        b.load(bad)
+    assert e.value.code == sphx.SPHX_EINVAL
+    assert "corrupt checkpoint" in str(e.value)
+    # the intact file still loads into the same context
+    b.load(path)
+    b.advance(1)
+    assert b.diagnostics()["n_steps"] == 3
+
+
 class _DeviceBuffer:
     """Device memory from the HIP runtime (standing in for a framework
     tensor): a data_ptr() and host copies in and out."""
