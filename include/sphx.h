@@ -308,6 +308,21 @@ int sphx_diagnostics(sphx_ctx* ctx, sphx_diag* out);
  * n_cases). */
 int sphx_diagnostics_case(sphx_ctx* ctx, int32_t c, sphx_diag* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): sphx_diagnostics_case
+ * with no allocation of any kind in the call. Its per-tile partials and
+ * per-case sums live in a file-scope device array of 4 MiB per GPU (held
+ * until the process ends; its address is taken once per device when a
+ * context is created there). Same arguments and results as
+ * sphx_diagnostics_case (the same kernels, so the same values).
+ * SPHX_ESTATE if the context has no device layout yet (the first call that
+ * needs its particles, e.g. sphx_build_neighbors or sphx_diagnostics_case,
+ * makes it); SPHX_EINVAL if its tiles of 64 particle slots plus its cases
+ * exceed 65 536. All contexts on one GPU share that array: calls that
+ * overlap on one GPU (other threads, other streams) race; every value a
+ * call reads it has written itself. */
+int sphx_diagnostics_noalloc(sphx_ctx* ctx, int32_t c, sphx_diag* out);
+
 /* Average device time per launch (milliseconds) of the hot kernels,
  * measured with HIP events on the context's stream over `reps` launches
  * each, on the current state of every case (each case one acoustic sub-step

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -23,15 +24,51 @@ using namespace sphx;
 
 struct EngineBase;
 
+// Scratch of the allocation-free diagnostics (sphx_diagnostics_noalloc): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes `scratch` itself to a kernel (its host-side name is
+// not a device address): each device's address comes from
+// hipGetSymbolAddress, taken once per device at context creation with that
+// device current, and kept in scratch_addr.
+constexpr size_t SCRATCH_DOUBLES = (size_t)1 << 19;  // 4 MiB per GPU
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static double* scratch_addr[SCRATCH_MAX_DEVICES] = {};
+static std::mutex scratch_mu;
+
+// Address of the current device's scratch (taken on first use per device).
+static hipError_t scratch_for_device(int dev, double** out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_addr[dev] = (double*)p;
+    }
+    *out = scratch_addr[dev];
+    return hipSuccess;
+}
+
 struct sphx_ctx {
     std::vector<sphx_params> prm;
     hipStream_t stream = nullptr;
+    int device = -1;  // current device at creation (the context's GPU)
     bool own_stream = false;
     std::string err;
     std::unique_ptr<EngineBase> eng;
     int fail(int code, const std::string& msg)
     {
         err = msg;
+        return code;
+    }
+    // (a literal into the capacity reserved at creation: no allocation for
+    // messages shorter than that)
+    int fail(int code, const char* msg)
+    {
+        err.assign(msg);
         return code;
     }
 };
@@ -73,6 +110,7 @@ struct EngineBase {
     virtual int case_status(int c) = 0;
     virtual int get_field(int c, int which, double* out) = 0;
     virtual int diagnostics(int c, sphx_diag* out) = 0;
+    virtual int diagnostics_noalloc(int c, sphx_diag* out) = 0;
     virtual int profile(int32_t reps, double* ms) = 0;
     virtual int counts(int c, int64_t* out) = 0;
     virtual int autotune(int32_t reps, int32_t* lanes, double* times) = 0;
@@ -1574,9 +1612,57 @@ struct Engine final : EngineBase {
             HIPCHK(hipMemcpyAsync(r.data(), diag_out, sizeof(double) * NDIAG * C, hipMemcpyDeviceToHost, s));
         }
         RETCHK(sync_ctrl());
-        for (int d = (c < 0 ? 0 : c), k = 0; d < (c < 0 ? C : c + 1); ++d, ++k) {
-            const double* v = &r[(size_t)d * NDIAG];
-            sphx_diag& o = out[k];
+        for (int d = (c < 0 ? 0 : c), k = 0; d < (c < 0 ? C : c + 1); ++d, ++k) fill_diag(d, &r[(size_t)d * NDIAG], out[k]);
+        return SPHX_OK;
+    }
+
+    // The same observables with the per-tile partials and the per-case sums
+    // in the GPU's file-scope scratch: no allocation of any kind (device or
+    // host) in the call. Needs the device layout (SPHX_ESTATE before the
+    // first call that makes it) and at most SCRATCH_DOUBLES / NDIAG tiles and
+    // cases together (SPHX_EINVAL beyond). Calls that overlap on one GPU share
+    // its scratch and race; every value read is written by the same call.
+    int diagnostics_noalloc(int c, sphx_diag* out) override
+    {
+        if (!out) return ctx->fail(SPHX_EINVAL, "NULL output");
+        if (c >= C) return ctx->fail(SPHX_EINVAL, "case index out of range");
+        if (!laid_out)
+            return ctx->fail(SPHX_ESTATE, "no device layout yet (it is made by the first call that needs the "
+                                          "particles, e.g. sphx_build_neighbors; this call allocates nothing)");
+        const size_t need = (size_t)NDIAG * ((size_t)ntiles + (size_t)C);
+        if (need > SCRATCH_DOUBLES)
+            return ctx->fail(SPHX_EINVAL, "batch too large for the allocation-free diagnostics: tiles of 64 "
+                                          "particle slots plus cases must not exceed 65536 (4 MiB of scratch)");
+        double* base = (ctx->device >= 0 && ctx->device < SCRATCH_MAX_DEVICES) ? scratch_addr[ctx->device] : nullptr;
+        if (!base) return ctx->fail(SPHX_EHIP, "device scratch address unknown");
+        double* part = base;
+        double* sums = base + (size_t)NDIAG * ntiles;
+        constexpr int CHUNK = 32;  // cases per copy through the stack buffer
+        double r[NDIAG * CHUNK];
+        const int c0 = c < 0 ? 0 : c, c1 = c < 0 ? C : c + 1;
+        if (ntiles > 0) {
+            k_diag<D, real><<<nblk(ntot), BLOCK, 0, s>>>(dP, tcase, ntiles, x[cur][0], x[cur][1], x[cur][2], st[cur],
+                                                          part);
+            k_diag_fin<real><<<C, BLOCK, 0, s>>>(dP, part, sums);
+            HIPCHK(hipGetLastError());
+        }
+        RETCHK(sync_ctrl());
+        for (int d0 = c0; d0 < c1; d0 += CHUNK) {
+            const int nd = std::min(CHUNK, c1 - d0);
+            if (ntiles > 0) {
+                HIPCHK(hipMemcpyAsync(r, sums + (size_t)d0 * NDIAG, sizeof(double) * NDIAG * nd, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+            } else {
+                for (int q = 0; q < NDIAG * nd; ++q) r[q] = 0.0;
+            }
+            for (int k = 0; k < nd; ++k) fill_diag(d0 + k, r + (size_t)k * NDIAG, out[d0 - c0 + k]);
+        }
+        return SPHX_OK;
+    }
+
+    void fill_diag(int d, const double* v, sphx_diag& o) const
+    {
+        {
             bool any = hP[d].nf > 0;
             o.mass = hP[d].md * hP[d].nf;
             o.momentum[0] = v[0];
@@ -1591,7 +1677,6 @@ struct Engine final : EngineBase {
             o.n_substeps = hctrl[d].nsub_total;
             o.n_steps = hctrl[d].steps_done;
         }
-        return SPHX_OK;
     }
 
     template <typename F>
@@ -2313,6 +2398,14 @@ static int create_impl(const sphx_params* params, int32_t n, void* stream, sphx_
     std::unique_ptr<sphx_ctx> ctx(new (std::nothrow) sphx_ctx());
     if (!ctx) return SPHX_ENOMEM;
     ctx->prm.assign(params, params + n);
+    ctx->err.reserve(1024);
+    {
+        // the context's GPU, and its scratch address (set-up of the
+        // allocation-free diagnostics, once per device)
+        if (hipGetDevice(&ctx->device) != hipSuccess) return SPHX_EHIP;
+        double* sp = nullptr;
+        if (scratch_for_device(ctx->device, &sp) != hipSuccess) return SPHX_EHIP;
+    }
     if (stream) {
         ctx->stream = (hipStream_t)stream;
     } else {
@@ -2462,6 +2555,8 @@ int sphx_get_field_case(sphx_ctx* ctx, int32_t c, int field, double* out) { ENG_
 int sphx_diagnostics(sphx_ctx* ctx, sphx_diag* out) { ENG_CALL(diagnostics(0, out)); }
 
 int sphx_diagnostics_case(sphx_ctx* ctx, int32_t c, sphx_diag* out) { ENG_CALL(diagnostics(c, out)); }
+
+int sphx_diagnostics_noalloc(sphx_ctx* ctx, int32_t c, sphx_diag* out) { ENG_CALL(diagnostics_noalloc(c, out)); }
 
 int sphx_profile(sphx_ctx* ctx, int32_t reps, double* ms) { ENG_CALL(profile(reps, ms)); }
 

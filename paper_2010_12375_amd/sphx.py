@@ -32,7 +32,7 @@ EXPORTED = ("sphx_create", "sphx_create_batch", "sphx_num_cases", "sphx_set_para
             "sphx_build_neighbors", "sphx_get_neighbors", "sphx_get_neighbors_case", "sphx_density_reinit",
             "sphx_time_steps", "sphx_time_steps_case", "sphx_compute_rates", "sphx_compute_rates_case",
             "sphx_advance", "sphx_case_status", "sphx_get_field", "sphx_get_field_case", "sphx_diagnostics",
-            "sphx_diagnostics_case", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune", "sphx_set_lanes",
+            "sphx_diagnostics_case", "sphx_diagnostics_noalloc", "sphx_profile", "sphx_counts", "sphx_counts_case", "sphx_autotune", "sphx_set_lanes",
             "sphx_gnn_num_params", "sphx_gnn_set_params", "sphx_gnn_get_params", "sphx_gnn_get_grad",
             "sphx_gnn_forward", "sphx_gnn_get_output_case", "sphx_gnn_set_target_case", "sphx_gnn_train_step",
             "sphx_gnn_profile", "sphx_surrogate_advance")
@@ -110,6 +110,7 @@ def load(path=None):
         "sphx_get_field_case": [vp, i32, C.c_int, vp],
         "sphx_diagnostics": [vp, C.POINTER(sphx_diag)],
         "sphx_diagnostics_case": [vp, i32, C.POINTER(sphx_diag)],
+        "sphx_diagnostics_noalloc": [vp, i32, C.POINTER(sphx_diag)],
         "sphx_profile": [vp, i32, pd],
         "sphx_counts": [vp, pi64],
         "sphx_counts_case": [vp, i32, pi64],
@@ -360,6 +361,14 @@ class Simulation:
         d = sphx_diag()
         self._check(self._L.sphx_diagnostics_case(self._h, case, C.byref(d)), "sphx_diagnostics_case")
         return self._diag_dict(d)
+
+    def diagnostics_noalloc(self, case=-1):
+        """sphx_diagnostics_noalloc: the observables with no allocation in the
+        call (case < 0: every case)."""
+        n = self.n_cases if case < 0 else 1
+        arr = (sphx_diag * n)()
+        self._check(self._L.sphx_diagnostics_noalloc(self._h, case, arr), "sphx_diagnostics_noalloc")
+        return [self._diag_dict(d) for d in arr]
 
     def diagnostics_all(self):
         arr = (sphx_diag * self.n_cases)()
