@@ -174,3 +174,42 @@ def test_apply_is_exact_for_constant_rates():
     assert np.allclose(x2, x + v * dt + 0.5 * a * dt * dt, rtol=1e-14, atol=1e-15)
     assert np.allclose(v2, v + a * dt, rtol=1e-14, atol=1e-15)
     assert np.allclose(r2, rho + Y[:, 2] * 0.02 * dt, rtol=1e-14, atol=1e-15)
+
+
+def test_two_node_forward_by_hand():
+    """A two-particle graph (0 <-> 1, and a wall edge of particle 0) with a
+    parameter set sparse enough to evaluate the network by hand (FP64, no
+    bf16 rounding). Hidden unit 0 carries v_x/u_ref; the first layer's
+    message unit 2 is relu(P_i + Q_j + R_e) with P_i = h_i, Q_j = 2 h_j (qw =
+    0.5 for the wall) and R_e = relu((x_j - x_i)/h); the node update moves
+    relu(A_2) into unit 5, which the decoder passes to the first output.
+    So Y_0 = relu(0.3 + 2 0.1 + 0.5) + relu(0.3 + 0.5 + relu(-0.4)) = 1.8 and
+    Y_1 = relu(0.1 + 2 0.3 + relu(-0.5)) = 0.7; with the roles of the source
+    and the destination swapped (P_j + Q_i) Y_0 would be 1.2 + 0.8 = 2.0, with
+    the messages summed at the destination instead of the source Y_1 would be
+    1.0, and with R left out Y_0 would be 1.3."""
+    g = G.Graph(2, np.array([0, 1, 2]), np.array([1, 0]), np.array([0, 1, 1]), np.array([0]))
+    h, u = 0.1, 2.0
+    prm = dict(h=h, rho0=1.0, u_ref=u, g=1.0, c0=20.0, gvec=(0.0, -1.0, 0.0))
+    x = np.array([[1.0, 1.0], [1.0 + 0.5 * h, 1.0]])
+    v = np.array([[0.3 * u, 0.0], [0.1 * u, 0.0]])
+    rho = np.array([1.0, 1.0])
+    xw = np.array([[1.0 - 0.4 * h, 1.0]])
+    F, E = G.features(g, x, v, rho, xw, prm)
+    flat = np.zeros(gi.n_params())
+    p, names = G.unpack(flat)
+    p = {k: np.zeros_like(a) for k, a in p.items()}
+    p["Wn"][0, 0] = 1.0            # H[:, 0] = relu(v_x / u_ref)
+    p["We"][0, 1] = 1.0            # E0[:, 1] = relu((x_j - x_i) / h)
+    p["Wa0"][0, 2] = 1.0           # P[:, 2] = H[:, 0]
+    p["Wb0"][0, 2] = 2.0           # Q[:, 2] = 2 H[:, 0]
+    p["Wc0"][1, 2] = 1.0           # R[:, 2] = E0[:, 1]
+    p["qw0"][2] = 0.5              # a wall edge's Q
+    p["Wu0"][64 + 2, 5] = 1.0      # H[:, 5] += relu(A[:, 2])
+    p["Wo1"][5, 0] = 1.0
+    p["Wo2"][0, 0] = 1.0
+    flat = G.pack(p, names)
+    Y, _ = G.forward(flat, g, F, E, emu=False)
+    assert Y[0, 0] == pytest.approx(1.8, abs=1e-12)
+    assert Y[1, 0] == pytest.approx(0.7, abs=1e-12)
+    assert np.all(Y[:, 1:] == 0.0)
