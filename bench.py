@@ -37,6 +37,7 @@ METRIC = "particle-steps/s (M) WCSPH dam-break; surrogate speedup at ≤1% front
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VALU_TFLOPS = 157.3       # MI355X FP32 vector peak
 FP64_VALU_TFLOPS = 78.6
+BF16_MFMA_TFLOPS = 2500.0      # MI355X dense bf16 matrix peak
 
 
 def algorithmic_bytes(dim, precision, n_fluid):
@@ -203,11 +204,14 @@ def surrogate_bench(args):
     gp = sim.gnn_profile(20)
     sim.close()
     E, N = gp["edges"], gp["nodes"]
-    kern = {"edge_gemm": (gp["edge_gemm"], E * (64 * 4 + 64 * 4)),
-            "messages": (gp["messages"], E * (64 * 4 + 4) + N * (3 * 64 * 4 + 4))}
-    kname = max(kern, key=lambda k: kern[k][0])
-    ms, nbytes = kern[kname]
-    achieved = nbytes / (ms * 1e-3) / 1e9
+    # the fused layer: reads the edge features (8 FP32), the edge's two
+    # endpoints, P and Q once per node, writes A; the matrix cores do the edge
+    # encoder (K = 32, 8 of it features) and the edge product (K = 64)
+    fused_bytes = E * (8 * 4 + 8) + N * (4 + 3 * 64 * 4)
+    fused_flops = E * (2 * 32 * 64 + 2 * 64 * 64)
+    ms = gp["fused_layer"]
+    t_hbm = fused_bytes / (HBM_PEAK_GBS * 1e9)
+    t_mfma = fused_flops / (BF16_MFMA_TFLOPS * 1e12)
     n_fluid = sum(c.n_fluid for c in te)
     ref = best or sweep[0]
     rate_plain = n_fluid * (ref["nsub_plain"] / len(te)) / ref["wall_plain"] / 1e6
@@ -233,6 +237,7 @@ def surrogate_bench(args):
                       "loss_last100": float(np.mean(losses[-100:])), "generate_s": round(gen_s, 1),
                       "train_s": round(train_s, 1)},
             "gnn_kernel_ms": {k: round(v, 5) for k, v in gp.items() if k not in ("nodes", "edges")},
+            "forward_speedup_fused": round(gp["forward_unfused"] / gp["forward"], 3),
             "graph": {"nodes": N, "edges": E},
         },
         "surrogate": {
@@ -243,16 +248,19 @@ def surrogate_bench(args):
             "sweep": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in sweep],
         },
         "roofline": {
-            "kernel": kname,
-            "bound": "hbm",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "kernel": "fused_message_layer",
+            "bound": "hbm" if t_hbm >= t_mfma else "mfma",
+            "achieved": round(fused_bytes / (ms * 1e-3) / 1e9, 2) if t_hbm >= t_mfma
+            else round(fused_flops / (ms * 1e-3) / 1e12, 3),
+            "peak": HBM_PEAK_GBS if t_hbm >= t_mfma else BF16_MFMA_TFLOPS,
+            "unit": "GB/s" if t_hbm >= t_mfma else "TFLOP/s",
+            "frac": round(max(t_hbm, t_mfma) / (ms * 1e-3), 4),
             "traffic": None,
-            "alg_bytes_per_launch": int(nbytes),
-            "alg_flops_per_launch": int(2 * E * 64 * 64) if kname == "edge_gemm" else int(3 * E * 64),
-            "mfma_frac": round(2 * E * 64 * 64 / (gp["edge_gemm"] * 1e-3) / 2.5e15, 5),
+            "alg_bytes_per_launch": int(fused_bytes),
+            "alg_flops_per_launch": int(fused_flops),
+            "ms_per_launch": round(ms, 5),
+            "hbm_frac": round(t_hbm / (ms * 1e-3), 4),
+            "mfma_frac": round(t_mfma / (ms * 1e-3), 4),
         },
     }
     if not args.no_cpu_baseline:

@@ -402,11 +402,15 @@ int sphx_gnn_set_target_case(sphx_ctx* ctx, int32_t c, const double* target);
 int sphx_gnn_train_step(sphx_ctx* ctx, double lr, double* loss);
 
 /* Per-launch device time (ms, HIP events over `reps` launches) of the
- * surrogate's kernels on the current configuration: ms[0] the edge product
- * R = E0 Wc, ms[1] the message sums of one layer, ms[2] the node update
- * product, ms[3] one whole forward pass including the graph and features
- * (the last includes a host synchronisation per pass). sizes (may be NULL):
- * [0] node rows, [1] edges. */
+ * surrogate's kernels on the current configuration; ms has 7 entries:
+ * ms[0] one fused message-passing layer (edge encoder, edge product,
+ * messages and their sums in one kernel, no edge array in device memory),
+ * ms[1] the graph's edge features, ms[2] the node update product, ms[3] one
+ * whole forward pass as inference runs it (graph and features included, one
+ * host synchronisation per pass); for comparison the same with the edge
+ * activations through device memory (the training forward's form): ms[4]
+ * the whole pass, ms[5] its edge product R = E0 Wc, ms[6] its message sums
+ * of one layer. sizes (may be NULL): [0] node rows, [1] edges. */
 int sphx_gnn_profile(sphx_ctx* ctx, int32_t reps, double* ms, int64_t* sizes);
 
 /* `windows` surrogate windows: each predicts every case's mean rates over

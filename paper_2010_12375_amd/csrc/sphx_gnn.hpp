@@ -27,6 +27,7 @@ namespace gnn {
 
 constexpr int HID = 64;
 constexpr int FPAD = 32;   // padded encoder input width
+constexpr int EFEAT = 8;   // edge features used
 constexpr int NOUT = 3;
 constexpr int WALL_EDGE = -1;  // edst < 0: wall edge, wall index -1 - edst
 
@@ -242,13 +243,19 @@ __device__ __forceinline__ float wendland_ratio(float q)
 // FP32 from the density deviations before any rounding; node features
 // v/u_ref, (rho - rho0)/(0.01 rho0), inner and contact counts / 32 and / 16
 // (2D).
+//
+// G rows hold `ldg` floats: FPAD (zero-padded, for the training path's
+// encoder product) or EFEAT (the features alone, for the fused inference
+// layer). esrc (may be null) receives each edge's particle; the reverse
+// edges (erev, training only: the backward of Q_j) are searched only when
+// erev is given.
 template <typename real, int T>
 __global__ __launch_bounds__(BLOCK) void k_gnn_edges(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, int ntiles, const int32_t* __restrict__ eoff,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncnt, const uint32_t* __restrict__ wnb,
     const int32_t* __restrict__ wcnt, const R2<real>* __restrict__ geo, const R2<real>* __restrict__ wgeo,
     const R4<real>* __restrict__ st, int32_t* __restrict__ edst, int32_t* __restrict__ erev,
-    float* __restrict__ G, float* __restrict__ F)
+    int32_t* __restrict__ esrc, float* __restrict__ G, int ldg, float* __restrict__ F)
 {
     const int tile = wave_tile();
     if (tile >= ntiles) return;
@@ -278,7 +285,8 @@ __global__ __launch_bounds__(BLOCK) void k_gnn_edges(
     const R2<real> oi = geo[i];
     int e = eoff[i];
     auto edge = [&](int e_, float dx, float dy, float dvx, float dvy, float wall, float dpres) {
-        float* gr = G + (size_t)e_ * FPAD;
+        float* gr = G + (size_t)e_ * ldg;
+        if (esrc) esrc[e_] = i;
         const float rr = sqrtf(dx * dx + dy * dy);
         gr[0] = -dx * inv_h;  // x_j - x_i
         gr[1] = -dy * inv_h;
@@ -288,7 +296,7 @@ __global__ __launch_bounds__(BLOCK) void k_gnn_edges(
         gr[5] = wendland_ratio(rr * inv_h);
         gr[6] = wall;
         gr[7] = dpres * inv_pscale;
-        for (int k = 8; k < FPAD; ++k) gr[k] = 0.f;
+        for (int k = EFEAT; k < ldg; ++k) gr[k] = 0.f;
     };
     for (int k = 0; k < nin; ++k, ++e) {
         const uint32_t ent = nbr[ell_at<T>(i, k, P.maxn)];
@@ -300,15 +308,17 @@ __global__ __launch_bounds__(BLOCK) void k_gnn_edges(
         const R4<real> sj = st[j];
         edge(e, dx, dy, (float)sj.x - vix, (float)sj.y - viy, 0.f, c2 * ((float)sj.z - devi));
         edst[e] = j;
-        // the reverse edge: i in the inner list of j (the lists are symmetric)
-        int rv = -1;
-        const int nj = ncnt[j];
-        for (int kk = 0; kk < nj; ++kk)
-            if ((int)(nbr[ell_at<T>(j, kk, P.maxn)] & NBR_MASK) == i) {
-                rv = eoff[j] + kk;
-                break;
-            }
-        erev[e] = rv;
+        if (erev) {
+            // the reverse edge: i in the inner list of j (the lists are symmetric)
+            int rv = -1;
+            const int nj = ncnt[j];
+            for (int kk = 0; kk < nj; ++kk)
+                if ((int)(nbr[ell_at<T>(j, kk, P.maxn)] & NBR_MASK) == i) {
+                    rv = eoff[j] + kk;
+                    break;
+                }
+            erev[e] = rv;
+        }
     }
     for (int k = 0; k < nwl; ++k, ++e) {
         const uint32_t ent = wnb[ell_at<T>(i, k, P.maxw)];
@@ -319,7 +329,7 @@ __global__ __launch_bounds__(BLOCK) void k_gnn_edges(
         const float dy = (float)((oi.y - ow.y) - (real)((int)((code >> 2) & 3u) - 1) * P.L[1]);
         edge(e, dx, dy, -vix, -viy, 1.f, ((float)P.rho0 + devi) * (gx * -dx + gy * -dy));
         edst[e] = -1 - wj;
-        erev[e] = -1;
+        if (erev) erev[e] = -1;
     }
 }
 
@@ -345,6 +355,124 @@ __global__ __launch_bounds__(256) void k_gnn_msg(int N, const int32_t* __restric
         acc += fmaxf(pre, 0.f);
     }
     X[(size_t)i * 2 * HID + HID + f] = acc;
+}
+
+// One message-passing layer for inference, fused: for every node i, over
+// its edges e in CSR order,
+//   E0_e = relu(G_e We + be),  R_e = E0_e Wc,
+//   m_e  = relu((P_i + (Q_j | qw)) + R_e),  A_i = sum_e m_e -> X[i][64 + f],
+// with the edge encoder and the edge product on the matrix cores, so that
+// neither E0 nor R nor the messages leave the wavefront (no E x 64 array in
+// HBM). Each wavefront takes NPW consecutive nodes and their edges in tiles
+// of 16. The products are computed transposed (features as MFMA rows, the
+// 16 edges as columns: A = W^T, B = the edge rows), so that each lane then
+// holds four consecutive features of one edge and gathers P_i and Q_j with
+// 16-byte loads. E0 goes from the accumulator layout to the operand layout
+// through LDS, rounded to bf16 as every product operand is; the messages go
+// through LDS to one lane per feature, which sums them per node in CSR
+// order. G rows hold the EFEAT edge features (the encoder's other inputs
+// are zero).
+template <int NPW>
+__global__ __launch_bounds__(256) void k_gnn_layer_fused(
+    int N, const int32_t* __restrict__ eoff, const int32_t* __restrict__ edst, const int32_t* __restrict__ esrc,
+    const float* __restrict__ G, const uint16_t* __restrict__ WeT, const float* __restrict__ be,
+    const uint16_t* __restrict__ WcT, const float* __restrict__ Pm, const float* __restrict__ Qm,
+    const float* __restrict__ qw, float* __restrict__ X)
+{
+    __shared__ __align__(16) uint16_t Es[4][16][HID + 8];
+    __shared__ __align__(16) float Ms[4][16][HID + 4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int n0 = (blockIdx.x * 4 + wv) * NPW;
+    if (n0 >= N) return;
+    const int n1 = min(n0 + NPW, N);
+    const int e_beg = eoff[n0], e_end = eoff[n1];
+    // weight fragments and the encoder bias of this lane, kept for all tiles
+    bf16x8 wef[4], wcf[2][4];
+    float bev[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        wef[t] = frag_from_bf16(WeT + (size_t)(16 * t + r) * FPAD + 8 * g);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) wcf[k][t] = frag_from_bf16(WcT + (size_t)(16 * t + r) * HID + 32 * k + 8 * g);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bev[t][q] = be[16 * t + 4 * g + q];
+    }
+    // the reduction: lane = feature, running node `cur` (uniform)
+    int cur = n0;
+    int cend = eoff[n0 + 1];
+    float sum = 0.f;
+    for (int eb = e_beg; eb < e_end; eb += 16) {
+        const int e = eb + r;
+        const bool ok = e < e_end;
+        const int src = ok ? esrc[e] : n0;
+        const int dst = ok ? edst[e] : -1;
+        // E0^T = We^T G^T: lane (r, g) holds edge r, features 16 t + 4 g + q
+        const bf16x8 gfr = frag_from_f32(G + (size_t)(ok ? e : e_beg) * EFEAT, ok && g == 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f32x4 a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wef[t], gfr, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            uint2 pk;
+            pk.x = bf16_bits(fmaxf(a[0] + bev[t][0], 0.f)) | (bf16_bits(fmaxf(a[1] + bev[t][1], 0.f)) << 16);
+            pk.y = bf16_bits(fmaxf(a[2] + bev[t][2], 0.f)) | (bf16_bits(fmaxf(a[3] + bev[t][3], 0.f)) << 16);
+            *(uint2*)&Es[wv][r][16 * t + 4 * g] = pk;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // R^T = Wc^T E0^T, two K steps of 32
+        f32x4 racc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) racc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const bf16x8 efr = frag_from_bf16(&Es[wv][r][32 * k + 8 * g]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                racc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcf[k][t], efr, racc[t], 0, 0, 0);
+        }
+        // messages of edge r, features 16 t + 4 g .. + 3
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int f0 = 16 * t + 4 * g;
+            const float4 pv = *(const float4*)(Pm + (size_t)src * HID + f0);
+            const float4 qv = dst >= 0 ? *(const float4*)(Qm + (size_t)dst * HID + f0) : *(const float4*)(qw + f0);
+            float4 mv;
+            mv.x = fmaxf((pv.x + qv.x) + (racc[t][0] + 0.f), 0.f);
+            mv.y = fmaxf((pv.y + qv.y) + (racc[t][1] + 0.f), 0.f);
+            mv.z = fmaxf((pv.z + qv.z) + (racc[t][2] + 0.f), 0.f);
+            mv.w = fmaxf((pv.w + qv.w) + (racc[t][3] + 0.f), 0.f);
+            *(float4*)&Ms[wv][r][f0] = mv;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // per-node sums in CSR order (every node of the range, edgeless ones
+        // too); the tile's rows are read first, then summed in order
+        const int nrow = min(16, e_end - eb);
+        float mrow[16];
+#pragma unroll
+        for (int row = 0; row < 16; ++row) mrow[row] = Ms[wv][row][lane];
+#pragma unroll
+        for (int row = 0; row < 16; ++row) {
+            if (row >= nrow) break;
+            const int ee = eb + row;
+            while (ee >= cend) {
+                X[(size_t)cur * 2 * HID + HID + lane] = sum;
+                sum = 0.f;
+                ++cur;
+                cend = eoff[cur + 1];
+            }
+            sum += mrow[row];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (; cur < n1; ++cur) {
+        X[(size_t)cur * 2 * HID + HID + lane] = sum;
+        sum = 0.f;
+    }
 }
 
 // Backward of the messages: dM_e = dA_i [pre_e > 0]; dP_i = sum_e dM_e;

@@ -1887,7 +1887,9 @@ struct Engine final : EngineBase {
         long long Ecap = 0;
         bool Ecap_train = false, Ncap_train = false;
         std::vector<void*> fixed, nodes, edges;
-        int32_t *ecount = nullptr, *eoff = nullptr, *bsumN = nullptr, *edst = nullptr, *erev = nullptr;
+        int32_t *ecount = nullptr, *eoff = nullptr, *bsumN = nullptr, *edst = nullptr, *erev = nullptr,
+                *esrc = nullptr;
+        bool fused = true;  // inference forward with the fused layer kernel (else edge activations in HBM)
         float *F = nullptr, *X[3] = {}, *Hs = nullptr, *Z[3] = {}, *P = nullptr, *Q = nullptr, *D1 = nullptr,
               *Y = nullptr, *T = nullptr, *dY = nullptr;
         float *dH = nullptr, *dZ = nullptr, *dA = nullptr, *dPb = nullptr, *dQb = nullptr, *wsum = nullptr;
@@ -1974,6 +1976,7 @@ struct Engine final : EngineBase {
         const size_t e64 = (size_t)cap * gnn::HID;
         RETCHK(dalloc(A, gn.edst, cap));
         RETCHK(dalloc(A, gn.erev, cap));
+        RETCHK(dalloc(A, gn.esrc, cap));
         RETCHK(dalloc(A, gn.G, (size_t)cap * gnn::FPAD));
         RETCHK(dalloc(A, gn.E0, e64));
         RETCHK(dalloc(A, gn.R, e64));
@@ -2044,8 +2047,10 @@ struct Engine final : EngineBase {
         return SPHX_OK;
     }
 
-    // The CSR graph and the features of the current configuration.
-    int gnn_graph(bool train)
+    // The CSR graph and the features of the current configuration (with
+    // `compact`: the edge features alone per row, source indices, no reverse
+    // edges, for the fused inference layer).
+    int gnn_graph(bool train, bool compact = false)
     {
         RETCHK(gnn_nodes(train));
         const int N = ntot;
@@ -2063,7 +2068,8 @@ struct Engine final : EngineBase {
         if constexpr (D == 2) {
             by_lanes([&](auto t) {
                 gnn::k_gnn_edges<real, decltype(t)::value><<<nblk(N), BLOCK, 0, s>>>(
-                    dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt, geo[cur], wgeo, st[cur], gn.edst, gn.erev, gn.G,
+                    dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt, geo[cur], wgeo, st[cur], gn.edst,
+                    compact ? nullptr : gn.erev, compact ? gn.esrc : nullptr, gn.G, compact ? gnn::EFEAT : gnn::FPAD,
                     gn.F);
             });
         }
@@ -2102,8 +2108,21 @@ struct Engine final : EngineBase {
             gnn::k_copy64<<<(int)((n + 255) / 256), 256, 0, s>>>((int)M, src, lds, out, ldo);
     }
 
+    static constexpr int FUSED_NPW = 8;  // nodes per wavefront of the fused layer
+
+    void fused_layer(int l)
+    {
+        const int N = ntot;
+        const int per_block = 4 * FUSED_NPW;
+        gnn::k_gnn_layer_fused<FUSED_NPW><<<(N + per_block - 1) / per_block, 256, 0, s>>>(
+            N, gn.eoff, gn.edst, gn.esrc, gn.G, gn.wt + gn.L.pWe, gn.p + gn.L.be, gn.wt + gn.L.pWc[l], gn.P, gn.Q,
+            gn.p + gn.L.qw[l], gn.X[l]);
+    }
+
     int gnn_forward_impl(bool train)
     {
+        // inference: the fused layers (E0, R and the messages stay on chip)
+        if (!train && gn.fused) return gnn_forward_fused();
         RETCHK(gnn_graph(train));
         const GnnLayout& L = gn.L;
         const int N = ntot;
@@ -2119,6 +2138,29 @@ struct Engine final : EngineBase {
             gemm<64, gnn::EPI_STORE>(E, gn.E0, H, gn.wt + L.pWc[l], nullptr, gn.R, H);
             gnn::k_gnn_msg<<<(N + 3) / 4, 256, 0, s>>>(N, gn.eoff, gn.edst, gn.P, gn.Q, gn.R, p + L.qw[l],
                                                        train ? gn.pre[l] : nullptr, gn.X[l]);
+            gemm<128, gnn::EPI_RESID>(N, gn.X[l], 2 * H, gn.wt + L.pWu[l], p + L.bu[l], gn.Hs, H, gn.Z[l], H);
+            if (l < 2) elem64(N, gn.Hs, H, nullptr, 0, gn.X[l + 1], 2 * H);
+        }
+        gemm<64, gnn::EPI_RELU>(N, gn.Hs, H, gn.wt + L.pWo1, p + L.bo1, gn.D1, H);
+        gnn::k_gnn_out<<<nblk(N), BLOCK, 0, s>>>(N, gn.D1, p + L.Wo2, p + L.bo2, gn.Y);
+        HIPCHK(hipGetLastError());
+        gn.gen = conf_gen;
+        return SPHX_OK;
+    }
+
+    int gnn_forward_fused()
+    {
+        RETCHK(gnn_graph(false, true));
+        const GnnLayout& L = gn.L;
+        const int N = ntot;
+        float* p = gn.p;
+        constexpr int H = gnn::HID;
+        gemm<32, gnn::EPI_RELU>(N, gn.F, 32, gn.wt + L.pWn, p + L.bn, gn.X[0], 2 * H);
+        elem64(N, gn.X[0], 2 * H, nullptr, 0, gn.Hs, H);
+        for (int l = 0; l < 3; ++l) {
+            gemm<64, gnn::EPI_STORE>(N, gn.X[l], 2 * H, gn.wt + L.pWa[l], p + L.bm[l], gn.P, H);
+            gemm<64, gnn::EPI_STORE>(N, gn.X[l], 2 * H, gn.wt + L.pWb[l], nullptr, gn.Q, H);
+            fused_layer(l);
             gemm<128, gnn::EPI_RESID>(N, gn.X[l], 2 * H, gn.wt + L.pWu[l], p + L.bu[l], gn.Hs, H, gn.Z[l], H);
             if (l < 2) elem64(N, gn.Hs, H, nullptr, 0, gn.X[l + 1], 2 * H);
         }
@@ -2260,32 +2302,52 @@ struct Engine final : EngineBase {
     {
         RETCHK(gnn_check_ready());
         if (reps < 1 || !ms) return ctx->fail(SPHX_EINVAL, "bad profile arguments");
-        RETCHK(gnn_forward_impl(false));
         const GnnLayout& L = gn.L;
         const int N = ntot;
-        const long long E = gn.E;
         constexpr int H = gnn::HID;
         float* p = gn.p;
-        RETCHK(time_launches(reps, &ms[0], [&] { gemm<64, gnn::EPI_STORE>(E, gn.E0, H, gn.wt + L.pWc[0], nullptr, gn.R, H); }));
-        RETCHK(time_launches(reps, &ms[1], [&] {
+        auto whole = [&](bool fused, double* out) {
+            const bool keep = gn.fused;
+            gn.fused = fused;
+            hipEvent_t ev[2];
+            HIPCHK(hipEventCreate(&ev[0]));
+            HIPCHK(hipEventCreate(&ev[1]));
+            HIPCHK(hipEventRecord(ev[0], s));
+            int rc = SPHX_OK;
+            for (int r = 0; r < reps && rc == SPHX_OK; ++r) rc = gnn_forward_impl(false);
+            HIPCHK(hipEventRecord(ev[1], s));
+            HIPCHK(hipEventSynchronize(ev[1]));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+            gn.fused = keep;
+            *out = (double)t / reps;
+            return rc;
+        };
+        // the unfused forward (edge activations and products through HBM)
+        RETCHK(whole(false, &ms[4]));
+        const long long E = gn.E;
+        RETCHK(time_launches(reps, &ms[5], [&] { gemm<64, gnn::EPI_STORE>(E, gn.E0, H, gn.wt + L.pWc[0], nullptr, gn.R, H); }));
+        RETCHK(time_launches(reps, &ms[6], [&] {
             gnn::k_gnn_msg<<<(N + 3) / 4, 256, 0, s>>>(N, gn.eoff, gn.edst, gn.P, gn.Q, gn.R, p + L.qw[0], nullptr,
                                                        gn.X[0]);
+        }));
+        // the fused forward (the default)
+        RETCHK(whole(true, &ms[3]));
+        RETCHK(time_launches(reps, &ms[0], [&] { fused_layer(0); }));
+        RETCHK(time_launches(reps, &ms[1], [&] {
+            if constexpr (D == 2) {
+                by_lanes([&](auto t) {
+                    gnn::k_gnn_edges<real, decltype(t)::value><<<nblk(N), BLOCK, 0, s>>>(
+                        dP, tcase, ntiles, gn.eoff, nbr, ncnt, wnb, wcnt, geo[cur], wgeo, st[cur], gn.edst, nullptr,
+                        gn.esrc, gn.G, gnn::EFEAT, gn.F);
+                });
+            }
         }));
         RETCHK(time_launches(reps, &ms[2], [&] {
             gemm<128, gnn::EPI_STORE>(N, gn.X[0], 2 * H, gn.wt + L.pWu[0], p + L.bu[0], gn.Z[0], H);
         }));
-        hipEvent_t ev[2];
-        HIPCHK(hipEventCreate(&ev[0]));
-        HIPCHK(hipEventCreate(&ev[1]));
-        HIPCHK(hipEventRecord(ev[0], s));
-        for (int r = 0; r < reps; ++r) RETCHK(gnn_forward_impl(false));
-        HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(hipEventSynchronize(ev[1]));
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
-        (void)hipEventDestroy(ev[0]);
-        (void)hipEventDestroy(ev[1]);
-        ms[3] = (double)t / reps;
         if (sizes) {
             sizes[0] = N;
             sizes[1] = E;
@@ -2314,11 +2376,18 @@ struct Engine final : EngineBase {
         for (int w = 0; w < windows; ++w) {
             RETCHK(sync_ctrl());
             const bool plain_turn = plain_every > 0 && (w % plain_every) == plain_every - 1;
-            if (plain_turn) {  // a plain window for every case: no prediction needed
-                std::vector<long long> steps(C, 2);
-                for (int c = 0; c < C; ++c) nfb += hctrl[c].err ? 0 : 1;
+            if (plain_turn) {
+                // a plain window for every case: no prediction needed; a run
+                // of consecutive plain windows (every window, with
+                // plain_every 1) goes to the device as one advance, which
+                // gives the same bits as window by window
+                int k = 1;
+                if (plain_every == 1) k = windows - w;
+                std::vector<long long> steps(C, 2LL * k);
+                for (int c = 0; c < C; ++c) nfb += hctrl[c].err ? 0 : k;
                 int rc = advance_cases(steps, std::numeric_limits<double>::infinity(), nullptr, nullptr);
                 if (rc != SPHX_OK && rc != SPHX_EESCAPE && rc != SPHX_ENAN && rc != SPHX_EOVERFLOW) return rc;
+                w += k - 1;
                 continue;
             }
             RETCHK(gnn_forward_impl(false));

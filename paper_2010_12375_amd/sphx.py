@@ -428,10 +428,11 @@ class Simulation:
         return loss.value
 
     def gnn_profile(self, reps=20):
-        ms = (C.c_double * 4)()
+        ms = (C.c_double * 7)()
         sz = (C.c_int64 * 2)()
         self._check(self._L.sphx_gnn_profile(self._h, int(reps), ms, sz), "sphx_gnn_profile")
-        return dict(edge_gemm=ms[0], messages=ms[1], node_gemm=ms[2], forward=ms[3], nodes=sz[0], edges=sz[1])
+        return dict(fused_layer=ms[0], edge_features=ms[1], node_gemm=ms[2], forward=ms[3],
+                    forward_unfused=ms[4], edge_gemm_unfused=ms[5], messages_unfused=ms[6], nodes=sz[0], edges=sz[1])
 
     def surrogate_advance(self, windows, max_drho=0.01, plain_every=0):
         a, b = C.c_int64(), C.c_int64()

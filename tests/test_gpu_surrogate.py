@@ -13,8 +13,14 @@ output (which reaches several times the root-mean-square output) and, less,
 the outputs of its three-hop neighbourhood (three message-passing layers).
 So per particle the error must stay within 8 x 2^-8 (3 %) of the rms output,
 at 90 % of the particles within 2^-8, and at the median within 1e-4 (any
-systematic mistake breaks the last two); gradients within 2e-2 of each
-tensor's norm.
+systematic mistake breaks the last two); gradients within 5e-3 of each
+tensor's norm (the same flips, summed over the 800 particles of the case;
+measured at most 2.0e-3).
+
+Inference runs the fused layer kernel (edge encoder, edge product,
+messages and their sums in one kernel); training runs the layer through
+device memory (it keeps the pre-activations for the backward pass). Both
+are held to the same reference bars.
 """
 import math
 import sys
@@ -130,7 +136,7 @@ def test_training_step_matches_reference():
         err = np.linalg.norm(pg[n] - po[n])
         say(f"grad {n}: rel err {err / max(nrm, 1e-30):.2e}")
         if nrm > 0:
-            assert err <= 2e-2 * nrm, n
+            assert err <= 5e-3 * nrm, n
         else:
             assert err == 0.0, n
     # Adam's first step moves every parameter by lr against its gradient's sign
