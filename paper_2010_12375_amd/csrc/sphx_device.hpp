@@ -156,6 +156,22 @@ __host__ __device__ __forceinline__ size_t ell_at(int i, int k, int mx)
     return (tile * (size_t)(mx / T) + (size_t)(k / T)) * 64 + (size_t)p * T + (size_t)(k % T);
 }
 
+// The same address split into a per-particle base and a per-entry offset
+// (unsigned shifts for the power-of-two T), for loops that write many
+// entries of one particle.
+template <int T>
+__device__ __forceinline__ size_t ell_base(int i, int mx)
+{
+    constexpr unsigned PW = 64 / T;
+    const unsigned ui = (unsigned)i;
+    return ((size_t)(ui / PW) * (size_t)((unsigned)mx / T)) * 64 + (size_t)((ui % PW) * T);
+}
+template <int T>
+__device__ __forceinline__ unsigned ell_off(unsigned k)
+{
+    return (k / T) * 64u + (k % T);
+}
+
 // XCD-aware block order. Workgroups are dispatched round-robin over the 8
 // XCDs, each with its own L2; remapping so that XCD k runs the k-th
 // contiguous slice of the (cell-sorted) particle range keeps neighbouring
@@ -317,6 +333,51 @@ template <int D, typename real> struct Pair {
     real dW;
     real dW_r;  // dW/dr / r
 };
+
+// The same from the cell offset vector c = (dc_x L_x, dc_y L_y, dc_z L_z)
+// of the entry's stencil code, read from a per-block table (CellOffsets):
+// (o_i - o_j) - c equals (o_i - o_j) - dc L bit for bit (dc L is exact), and
+// saves the code's decoding per pair.
+template <int D, typename real, typename G>
+__device__ __forceinline__ Pair<D, real> pair_geo_c(const KP<real>& P, const G& oi, const G& oj, const R4<real>& c)
+{
+    Pair<D, real> q;
+    real* dx = q.d;
+    dx[0] = (oi.x - oj.x) - c.x;
+    dx[1] = (oi.y - oj.y) - c.y;
+    if constexpr (D == 3) dx[2] = (oi.z - zc(oj)) - c.z;
+    else dx[2] = (real)0;
+    real r2 = dx[0] * dx[0] + dx[1] * dx[1] + (D == 3 ? dx[2] * dx[2] : (real)0);
+    real rinv = rsqrt_r(r2);
+    real r = r2 * rinv;
+    real s = (real)1 + P.s_r * r;
+    q.dW_r = P.dWr * s * s * s;
+    q.dW = q.dW_r * r;
+    q.r = r;
+    q.rinv = rinv;
+    q.e[0] = -dx[0] * rinv;
+    q.e[1] = -dx[1] * rinv;
+    q.e[2] = -dx[2] * rinv;
+    return q;
+}
+
+// Cell offset vectors of the 64 stencil codes (27 used) for the block's
+// case, in LDS: entry c = ((c & 3) - 1) L_x, ((c >> 2 & 3) - 1) L_y,
+// ((c >> 4 & 3) - 1) L_z. Filled by the block's first 64 threads; the caller
+// synchronises the block before use.
+template <typename real>
+__device__ __forceinline__ void fill_cell_offsets(const KP<real>& P, R4<real>* tab)
+{
+    const int c = threadIdx.x;
+    if (c < 64) {
+        R4<real> v;
+        v.x = (real)((c & 3) - 1) * P.L[0];
+        v.y = (real)(((c >> 2) & 3) - 1) * P.L[1];
+        v.z = (real)(((c >> 4) & 3) - 1) * P.L[2];
+        v.w = (real)0;
+        tab[c] = v;
+    }
+}
 
 template <int D, typename real, typename G>
 __device__ __forceinline__ Pair<D, real> pair_geo(const KP<real>& P, const G& oi, const G& oj, uint32_t code)
@@ -856,8 +917,8 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
         const double* bx0 = BODY ? wx0 : x0;
         const double* bx1 = BODY ? wx1 : x1;
         const double* bx2 = BODY ? wx2 : x2;
-        uint32_t* out = BODY ? wnb : nbr;
         const int mx = BODY ? P.maxw : P.maxn;
+        uint32_t* out = (BODY ? wnb : nbr) + ell_base<T>(i, mx);
         int& nn = BODY ? cnt_w : cnt_f;
         // NBATCH rounds per iteration: all candidate loads first, then the
         // tests and ballots in candidate order
@@ -911,7 +972,7 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
                 if (in) {
                     int slot = nn + __popcll(m & below);
                     uint32_t code = (uint32_t)(dcx + 1) | tag_yz;
-                    if (slot < mx) out[ell_at<T>(i, slot, mx)] = (uint32_t)j | (code << NBR_SHIFT);
+                    if (slot < mx) out[ell_off<T>((unsigned)slot)] = (uint32_t)j | (code << NBR_SHIFT);
                     else over = 1;
                     if (do_reinit) {
                         if constexpr (PREFILTER) {
@@ -1321,6 +1382,9 @@ __device__ __forceinline__ void pressure_body(
     }
     if (first && threadIdx.x < VSLOTS) vslot[(q & 1) * VSLOTS + threadIdx.x] = 0ull;
     if (!S.active || err) return;
+    __shared__ R4<real> coff[64];
+    fill_cell_offsets(P, coff);
+    __syncthreads();
     const int i = i0 + (int)threadIdx.x / T;
     const int l = threadIdx.x % T;
     if (i >= P.fbase + P.nf) return;
@@ -1360,7 +1424,7 @@ __device__ __forceinline__ void pressure_body(
             return r;
         },
         [&](uint32_t e, const FluidJ& r) {
-            Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+            Pair<D, real> pq = pair_geo_c<D, real>(P, oi, r.o, coff[e >> NBR_SHIFT]);
             const R4<real>& sj = r.s;
             // 3D: the neighbour's density rate is the w of its frozen offsets
             real dev_j = D == 2 ? sj.z + half * sj.w : sj.w + half * geo_w(r.o);
@@ -1390,7 +1454,7 @@ __device__ __forceinline__ void pressure_body(
             return r;
         },
         [&](uint32_t e, const WallJ& r) {
-            Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+            Pair<D, real> pq = pair_geo_c<D, real>(P, oi, r.o, coff[e >> NBR_SHIFT]);
             const G& nw = r.n;
             real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
             real uw = 0;  // u_w = -n_w . v_w, zero for a static wall
@@ -1491,6 +1555,9 @@ __device__ __forceinline__ void density_body(
     const SubState S = ctrl->ss[q & 1];
     if (!S.active || ctrl->err) return;
     __shared__ double smax[BLOCK / 64];
+    __shared__ R4<real> coff[64];
+    fill_cell_offsets(P, coff);
+    __syncthreads();
     using G = typename GeoSel<D, real>::T;
     const double dtd = S.dt;
     const real dt = (real)dtd;
@@ -1538,7 +1605,7 @@ __device__ __forceinline__ void density_body(
                 return r;
             },
             [&](uint32_t e, const HalfJ& r) {
-                Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+                Pair<D, real> pq = pair_geo_c<D, real>(P, oi, r.o, coff[e >> NBR_SHIFT]);
                 const R4<real>& hj = r.h;
                 real dev_j = D == 2 ? hj.z : hj.w;
                 // U_R - U_L = (v_j - v_i) . e_ij = (v_i - v_j) . d / r
@@ -1564,7 +1631,7 @@ __device__ __forceinline__ void density_body(
                 return r;
             },
             [&](uint32_t e, const WallJ& r) {
-                Pair<D, real> pq = pair_geo<D, real>(P, oi, r.o, e >> NBR_SHIFT);
+                Pair<D, real> pq = pair_geo_c<D, real>(P, oi, r.o, coff[e >> NBR_SHIFT]);
                 const G& nw = r.n;
                 real UL = -(nw.x * vi[0] + nw.y * vi[1] + (D == 3 ? zc(nw) * vi[2] : (real)0));
                 // g . r_fw with r_fw = x_w - x_i = -d
