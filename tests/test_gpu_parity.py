@@ -383,6 +383,36 @@ def test_dambreak_large_steps_conserve_mass_and_stay_bounded(large_pair):
     assert d1["max_drho"] < 0.05
 
 
+def test_dambreak_large_fp32_tracks_oracle_run():
+    """The 3D dam break (2.0 M fluid, 0.596 M wall particles) in FP32, in the
+    benchmark's launch configuration, against the FP64 oracle's run of the
+    same input (tests/golden/oracle_dambreak3d_2M.json, observers every 0.1
+    over the extent the file holds, at least t = 0.3): surge front within 1 %
+    while it is short of the far wall (x_f < DL - 2h), total energy within
+    1 % of E(0) at every observer time."""
+    case = wl.config_large(0)
+    gold = load_golden("oracle_dambreak3d_2M.json")["seeds"]["0"]
+    t_last = gold[-1]["t"]
+    assert t_last >= 0.3 - 1e-9 and len(gold) >= 4
+    g, _ = make_pair(case, FP32)
+    say(f"large run to t={t_last:.2f} ({len(gold)} observer rows)")
+    rows = run_observed(g, t_last + 1e-9)
+    g.close()
+    assert len(rows) == len(gold)
+    E0 = energy(gold[0])
+    DL = case.tank[0]
+    worst_front = worst_energy = 0.0
+    for r, go in zip(rows, gold):
+        assert r["t"] == pytest.approx(go["t"], abs=1e-9)
+        if go["front"] < DL - 2 * case.h:
+            worst_front = max(worst_front, abs(r["front"] - go["front"]) / go["front"])
+        worst_energy = max(worst_energy, abs(energy(r) - energy(go)) / E0)
+    say(f"large run: worst front rel err {worst_front:.3e}, worst energy err / E0 {worst_energy:.3e}, "
+        f"steps {rows[-1]['n_steps']} vs oracle {gold[-1]['nadv']}")
+    assert worst_front <= 0.01
+    assert worst_energy <= 0.01
+
+
 def run_medium_to_t20():
     case = wl.config_medium(0)
     gold = load_golden("oracle_dambreak2d_51k.json")["seeds"]["0"]
