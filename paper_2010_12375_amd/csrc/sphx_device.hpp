@@ -53,6 +53,15 @@ constexpr int BATCH = SPHX_PAIR_BATCH;  // list entries loaded ahead per lane (p
 #endif
 constexpr int NBATCH = SPHX_BUILD_BATCH;  // candidate rounds loaded ahead per lane (neighbour build)
 constexpr uint32_t NO_ENTRY = 0xffffffffu;  // stencil code 63 never occurs
+// Inside a cell the particles are ordered by x sub-bin (XSUB bins of width
+// L/XSUB along x), then by previous slot. The sub-bin rides in the bits above
+// CELL_BITS of a slot's cell word and binning key (global cell indices stay
+// below 2^CELL_BITS); per cell, the cumulative sub-bin counts let the
+// neighbour build skip the parts of the outer cells of a stencil row that lie
+// beyond 2h in x.
+constexpr int XSUB = 4;
+constexpr int CELL_BITS = 28;
+constexpr int32_t CELL_MASK = (1 << CELL_BITS) - 1;
 constexpr int VSLOTS = 64;  // slots the density relaxation folds its block maxima into
 #ifndef SPHX_PAIR_WAVES
 #define SPHX_PAIR_WAVES 0
@@ -129,6 +138,7 @@ template <typename real> struct KP {
     double rc2, sigma0, rho0d;
     double cfl_ad_h, cfl_ac_h, u_ref, c0d;
     int maxn, maxw;                           // list capacity per particle (same for every case)
+    int xsub_margin;                          // 0 if L_x > 2h (beyond rounding), else 1 sub-bin of slack
     real eta, p0;                             // dynamic viscosity, transport background pressure
     double visc_dt;                           // CFL_ad h^2 / nu (0: inviscid)
     int reinit_mode;                          // 0: free surface (max), 1: no free surface
@@ -257,6 +267,28 @@ __device__ __forceinline__ int cell_coord(const KP<real>& P, int k, double xk)
     if (!(f >= 0.0)) f = 0.0;
     if (f > (double)(P.n[k] - 1)) f = (double)(P.n[k] - 1);
     return (int)f;
+}
+
+// x sub-bin of a position in x cell cx: floor(XSUB t) - XSUB cx with
+// t = (x - lo) / L (the quotient cell_coord floors; scaling by the power of
+// two XSUB is exact), clamped to [0, XSUB) for the clamped edge cells.
+template <typename real>
+__device__ __forceinline__ int xsub_bin(const KP<real>& P, double x, int cx)
+{
+    const double f = floor((x - P.lo[0]) / P.Ld[0] * (double)XSUB) - (double)XSUB * (double)cx;
+    return f < 0.0 ? 0 : (f > (double)(XSUB - 1) ? XSUB - 1 : (int)f);
+}
+
+// Particles of a cell below / above an x sub-bin, from the cell's packed
+// cumulative counts w (byte b: particles with sub-bin <= b for b < XSUB - 1,
+// top byte: all; 0 where the cell is empty or holds more than 255).
+__device__ __forceinline__ int xsub_below(uint32_t w, int b)
+{
+    return b <= 0 ? 0 : (int)((w >> (8 * (b - 1))) & 0xffu);
+}
+__device__ __forceinline__ int xsub_above(uint32_t w, int b)
+{
+    return b >= XSUB - 1 ? 0 : (int)(w >> 24) - (int)((w >> (8 * b)) & 0xffu);
 }
 
 // Cell order. Each row of cells along x is contiguous (the neighbour build
@@ -529,10 +561,11 @@ __device__ __forceinline__ void bin_slots(const KP<real>& P, Ctrl* __restrict__ 
     const int i = i0 + lane;
     if (lane == 0 && i0 % TILE == 0 && i0 + TILE == P.fbase + P.fcap) cnt[P.cbase + P.ncell] = P.fcap - P.nf;
     const bool act = lane < n && i < P.fbase + P.nf;  // the active lanes are a prefix of the wavefront
-    int kc = -1;
+    int kc = -1, sb = 0;
     if (!act) {
     } else if (!full) {
-        kc = cell[i];
+        kc = cell[i] & CELL_MASK;
+        sb = (int)((uint32_t)cell[i] >> CELL_BITS);
     } else {
         double* xs[3] = {x0, x1, x2};
         int c[3] = {0, 0, 0};
@@ -549,6 +582,7 @@ __device__ __forceinline__ void bin_slots(const KP<real>& P, Ctrl* __restrict__ 
             }
             if (!(xk >= P.lo[k] && xk < P.hi[k])) bad |= ERR_ESCAPE;
             c[k] = cell_coord(P, k, xk);
+            if (k == 0) sb = xsub_bin(P, xk, c[0]);
         }
         if (bad) atomicOr(&ctrl->err_pending, bad);
         kc = P.cbase + cell_index(P, c[0], c[1], c[2]);
@@ -572,7 +606,7 @@ __device__ __forceinline__ void bin_slots(const KP<real>& P, Ctrl* __restrict__ 
     }
     base = __shfl(base, h);
     if (!act) return;
-    key[i] = kc;
+    key[i] = kc | (sb << CELL_BITS);
     rank[i] = base + (lane - h);
 }
 
@@ -667,7 +701,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_add(int32_t* __restrict__ start,
     if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = bsum[nb];
 }
 
-// Arrival-order list of each cell's fluid particles.
+// Arrival-order list of each cell's fluid particles: slot | sub-bin <<
+// CELL_BITS (slots stay below 2^CELL_BITS).
 template <typename real>
 __global__ __launch_bounds__(BLOCK) void k_scatter(const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase,
                                                    int ntiles, int n, const int32_t* __restrict__ key,
@@ -679,16 +714,20 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const KP<real>* __restrict__ 
     const KP<real>& P = Pt[tcase[tile]];
     const int i = tile * TILE + (threadIdx.x & 63);
     if (i >= P.fbase + P.nf) return;
-    int p = start[key[i]] + rank[i];
-    if (p < n) perm[p] = i;  // always true for consistent counts
+    const int kw = key[i];
+    int p = start[kw & CELL_MASK] + rank[i];
+    if (p < n) perm[p] = i | (kw & ~CELL_MASK);  // always true for consistent counts
 }
 
 // Stable placement: a particle's slot in its new cell is the number of
-// particles of that cell with a smaller previous index (counted over the
-// cell's arrival-order list from k_scatter), which is the order of a stable
-// counting sort. The particle's state moves there; with a full update the
-// configuration geometry is frozen anew as offsets from the cell origin,
-// otherwise (identity placement) the frozen offsets move along.
+// particles of that cell before it in (x sub-bin, previous index) order
+// (counted over the cell's arrival-order list from k_scatter), the order of a
+// stable counting sort by (cell, sub-bin). The particle that lands first in
+// its cell stores the cell's cumulative sub-bin counts. The particle's state
+// moves there; with a full update the configuration geometry is frozen anew
+// as offsets from the cell origin, otherwise (identity placement: the kept
+// cells and sub-bins are already in this order) the frozen offsets move
+// along.
 template <int D, typename real>
 __global__ __launch_bounds__(BLOCK) void k_place_fluid(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, int ntiles,
@@ -698,7 +737,7 @@ __global__ __launch_bounds__(BLOCK) void k_place_fluid(
     const real* __restrict__ adr, const int32_t* __restrict__ aid, const typename GeoSel<D, real>::T* __restrict__ ageo,
     double* __restrict__ bx0, double* __restrict__ bx1, double* __restrict__ bx2, R4<real>* __restrict__ bst,
     real* __restrict__ bdr, int32_t* __restrict__ bid, int32_t* __restrict__ bcell,
-    typename GeoSel<D, real>::T* __restrict__ bgeo)
+    typename GeoSel<D, real>::T* __restrict__ bgeo, uint32_t* __restrict__ xcum)
 {
     const int tile = wave_tile();
     if (tile >= ntiles) return;
@@ -706,11 +745,21 @@ __global__ __launch_bounds__(BLOCK) void k_place_fluid(
     const bool full = full_update(ctrl_all + P.case_id, force);
     const int i = tile * TILE + (threadIdx.x & 63);
     if (i >= P.fbase + P.nf) return;
-    int kc = key[i];
+    const int kw = key[i];
+    const int kc = kw & CELL_MASK;
+    const int sb = (int)((uint32_t)kw >> CELL_BITS);
     int s0 = start[kc], s1 = min(start[kc + 1], n);
     int s = s0;
-    for (int q = s0; q < s1; ++q) s += arrival[q] < i;
+    uint32_t cum = 0;  // byte b: arrivals with sub-bin <= b
+    for (int q = s0; q < s1; ++q) {
+        const int a = arrival[q];
+        const int j = a & CELL_MASK;
+        const int sj = (int)((uint32_t)a >> CELL_BITS);
+        s += sj < sb || (sj == sb && j < i);
+        cum += (0x010101u << (8 * sj)) & 0xffffffu;
+    }
     if (s >= n) return;  // never for consistent counts
+    if (s == s0) xcum[kc] = s1 - s0 > 255 ? 0u : (cum | ((uint32_t)(s1 - s0) << 24));
     double x[3] = {ax0[i], ax1[i], D == 3 ? ax2[i] : 0.0};
     bx0[s] = x[0];
     bx1[s] = x[1];
@@ -718,7 +767,7 @@ __global__ __launch_bounds__(BLOCK) void k_place_fluid(
     bst[s] = ast[i];
     if (D == 3) bdr[s] = adr[i];
     bid[s] = aid[i];
-    bcell[s] = kc;
+    bcell[s] = kw;
     if (!full) {
         bgeo[s] = ageo[i];
         return;
@@ -877,7 +926,8 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const typename GeoSel<D, real>::T* __restrict__ geo, const double* __restrict__ wx0,
     const double* __restrict__ wx1, const double* __restrict__ wx2, const int32_t* __restrict__ wstart,
     const typename GeoSel<D, real>::T* __restrict__ wgeo, uint32_t* __restrict__ nbr, int32_t* __restrict__ ncnt,
-    uint32_t* __restrict__ wnb, int32_t* __restrict__ wcnt, int reinit, R4<real>* __restrict__ st)
+    uint32_t* __restrict__ wnb, int32_t* __restrict__ wcnt, int reinit, R4<real>* __restrict__ st,
+    const uint32_t* __restrict__ xcum)
 {
     static_assert(64 % TB == 0, "lane groups must tile a wavefront");
     using G = typename GeoSel<D, real>::T;
@@ -900,9 +950,13 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
     const float Lm = (float)dmax(P.L[0], dmax(P.L[1], D == 3 ? P.L[2] : P.L[1]));
     const float margin = 8e-6f * Lm * Lm;
     const float rc2f = (float)P.rc2;
-    const int kc = cell[i] - P.cbase;
+    const int kc = (cell[i] & CELL_MASK) - P.cbase;
     int ci[3];
     cell_coords(P, kc, ci);
+    // fluid candidates of the outer cells of a row lie beyond 2h in x below
+    // sub-bin sb_lo of the left cell and above sb_hi of the right one
+    const int sb_i = (int)((uint32_t)cell[i] >> CELL_BITS);
+    const int sb_lo = sb_i - P.xsub_margin, sb_hi = sb_i + P.xsub_margin;
     int cnt_f = 0, cnt_w = 0;
     uint32_t over = 0;
 
@@ -994,10 +1048,17 @@ __global__ __launch_bounds__(TILE * TB) void k_neighbors(
         const int32_t* st_ = BODY ? wstart : fstart;
         const int lim = BODY ? wend : fend;
         if (ci[0] >= 1 && ci[0] + 1 < P.n[0]) {
-            // the three cells are contiguous: one range
+            // the three cells are contiguous: one range (fluid: trimmed to
+            // the sub-bins within reach)
             const int c = rowc + ci[0];
-            scan(bodyc, min(st_[c - 1], lim), min(st_[c + 2], lim), min(st_[c], lim), min(st_[c + 1], lim), -1,
-                 tag_yz);
+            int j0 = st_[c - 1], j1 = st_[c + 2];
+            if constexpr (BODY == 0) {
+                // (the counts of a cell that has emptied are stale: the
+                // clamps make them 0)
+                j0 = min(j0 + xsub_below(xcum[c - 1], sb_lo), st_[c]);
+                j1 = max(j1 - xsub_above(xcum[c + 1], sb_hi), st_[c + 1]);
+            }
+            scan(bodyc, min(j0, lim), min(j1, lim), min(st_[c], lim), min(st_[c + 1], lim), -1, tag_yz);
         } else {
             for (int dx = -1; dx <= 1; ++dx) {
                 int cx = ci[0] + dx;

@@ -185,6 +185,7 @@ struct Engine final : EngineBase {
     int32_t* wcnt = nullptr;
     int32_t *key = nullptr, *rank = nullptr, *perm = nullptr;
     int32_t *cnt = nullptr, *fstart = nullptr, *bsum = nullptr;
+    uint32_t* xcum = nullptr;  // per cell: cumulative x sub-bin counts of its fluid particles
     // single-pass scan: per-tile status words, ticket counter, epoch, fault flag
     unsigned long long* lb_status = nullptr;
     int32_t *lb_ticket = nullptr, *lb_fault = nullptr;
@@ -245,7 +246,7 @@ struct Engine final : EngineBase {
         free_list(gn.edges);
         for (void* p : {(void*)lb_status, (void*)lb_ticket, (void*)lb_fault, (void*)lb_epoch})
             if (p) (void)hipFree(p);
-        for (void* p : {(void*)ctrl, (void*)cnt, (void*)fstart, (void*)bsum, (void*)wstart, (void*)diag_out,
+        for (void* p : {(void*)ctrl, (void*)cnt, (void*)fstart, (void*)xcum, (void*)bsum, (void*)wstart, (void*)diag_out,
                         (void*)dP, (void*)vslot, (void*)stage})
             (void)hipFree(p);
         if (hctrl) (void)hipHostFree(hctrl);
@@ -370,6 +371,9 @@ struct Engine final : EngineBase {
         P.u_ref = q.u_ref;
         P.maxn = maxn;
         P.maxw = maxw;
+        // the build skips fluid candidates by x sub-bin where the cell width
+        // exceeds 2h by more than the rounding of the cell coordinate
+        P.xsub_margin = P.Ld[0] > rc * (1.0 + 1e-9) ? 0 : 1;
         if (!(q.eta >= 0.0) || !std::isfinite(q.eta) || !std::isfinite(q.p_background))
             return ctx->fail(SPHX_EINVAL, case_tag(c) + "bad viscosity or background pressure");
         P.eta = (real)q.eta;
@@ -410,6 +414,7 @@ struct Engine final : EngineBase {
         HIPCHK(hipMemsetAsync(vslot, 0, sizeof(unsigned long long) * 2 * VSLOTS * C, s));
         HIPCHK(hipMalloc((void**)&cnt, sizeof(int32_t) * (size_t)ncell));
         HIPCHK(hipMalloc((void**)&fstart, sizeof(int32_t) * ((size_t)ncell + 1)));
+        HIPCHK(hipMalloc((void**)&xcum, sizeof(uint32_t) * (size_t)ncell));
         HIPCHK(hipMalloc((void**)&wstart, sizeof(int32_t) * ((size_t)ncell + 1)));
         HIPCHK(hipMalloc((void**)&bsum, sizeof(int32_t) * ((size_t)nblk_scan() + 1)));
         HIPCHK(hipMalloc((void**)&lb_status, sizeof(unsigned long long) * (size_t)nblk_lb()));
@@ -427,6 +432,7 @@ struct Engine final : EngineBase {
         HIPCHK(hipMalloc((void**)&diag_out, sizeof(double) * NDIAG * C));
         HIPCHK(hipMemsetAsync(wstart, 0, sizeof(int32_t) * ((size_t)ncell + 1), s));
         HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)ncell, s));
+        HIPCHK(hipMemsetAsync(xcum, 0, sizeof(uint32_t) * (size_t)ncell, s));
         RETCHK(upload_params());
         HIPCHK(hipStreamSynchronize(s));
         return SPHX_OK;
@@ -564,6 +570,10 @@ struct Engine final : EngineBase {
         real* odr = dr3[cur];
         int32_t* oid = id[cur];
         int32_t* ocell = cell[cur];
+        long long slots = 0;
+        for (int c = 0; c < C; ++c) slots += hP[c].fcap;
+        if (slots > (long long)CELL_MASK)  // slot indices share a word with a sub-bin (k_scatter)
+            return ctx->fail(SPHX_EINVAL, "too many particle slots");
         std::vector<void*> old_allocs;
         old_allocs.swap(fluid_allocs);
         int base = 0;
@@ -992,7 +1002,7 @@ struct Engine final : EngineBase {
         constexpr int TB = T < LB ? T : LB;
         k_neighbors<D, real, T, TB><<<ntiles, TILE * TB, 0, s>>>(dP, tcase, ctrl, force, x[b][0], x[b][1], x[b][2],
                                                                 cell[b], fstart, geo[b], wx[0], wx[1], wx[2], wstart,
-                                                                wgeo, nbr, ncnt, wnb, wcnt, reinit, st[b]);
+                                                                wgeo, nbr, ncnt, wnb, wcnt, reinit, st[b], xcum);
     }
 
     // `q` >= 0: at the end of a queue whose last sub-step is q (the scan
@@ -1011,7 +1021,7 @@ struct Engine final : EngineBase {
         k_scatter<real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ntot, key, rank, fstart, perm);
         k_place_fluid<D, real><<<nb, BLOCK, 0, s>>>(dP, tcase, ntiles, ctrl, force, ntot, perm, key, fstart, x[a][0],
                                                      x[a][1], x[a][2], st[a], dr3[a], id[a], geo[a], x[b][0], x[b][1],
-                                                     x[b][2], st[b], dr3[b], id[b], cell[b], geo[b]);
+                                                     x[b][2], st[b], dr3[b], id[b], cell[b], geo[b], xcum);
         // at the end of a queue the next step's density re-initialisation rides along
         by_lanes([&](auto t) { launch_neighbors<decltype(t)::value>(force, b, q >= 0 ? 1 : 0); });
         HIPCHK(hipGetLastError());
