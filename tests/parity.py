@@ -72,3 +72,18 @@ def load_golden(name):
 
 def energy(row):
     return row["e_kin"] + row["e_pot"] + row["e_int"]
+
+
+ENVELOPE_HALF_WINDOW = 0.5
+
+
+def rounding_envelope(gold, perturbed, E0, half_window=ENVELOPE_HALF_WINDOW):
+    """Spread of the oracle's own runs in total energy, per observer time:
+    the largest |E_a - E_b| / E(0) over every pair of the unperturbed and
+    perturbed oracle trajectories and every observer time within
+    +-half_window of it."""
+    traj = [[energy(r) / E0 for r in gold]] + [[energy(r) / E0 for r in p] for p in perturbed]
+    n = len(gold)
+    spread = [max(tr[k] for tr in traj) - min(tr[k] for tr in traj) for k in range(n)]
+    ts = [r["t"] for r in gold]
+    return [max(spread[m] for m in range(n) if abs(ts[m] - ts[k]) <= half_window + 1e-9) for k in range(n)]

@@ -15,7 +15,7 @@ import oracle as O
 from oracle_cases import jitter, lattice
 from paper_2010_12375_amd import sphx
 from paper_2010_12375_amd import workloads as wl
-from parity import developed_state, energy, load_golden, make_pair, rate_errors
+from parity import developed_state, energy, load_golden, make_pair, rate_errors, rounding_envelope
 
 pytestmark = pytest.mark.gpu
 
@@ -387,13 +387,13 @@ def test_dambreak_large_fp32_tracks_oracle_run():
     """The 3D dam break (2.0 M fluid, 0.596 M wall particles) in FP32, in the
     benchmark's launch configuration, against the FP64 oracle's run of the
     same input (tests/golden/oracle_dambreak3d_2M.json, observers every 0.1
-    over the extent the file holds, at least t = 0.3): surge front within 1 %
+    over the extent the file holds, at least t = 0.5): surge front within 1 %
     while it is short of the far wall (x_f < DL - 2h), total energy within
     1 % of E(0) at every observer time."""
     case = wl.config_large(0)
     gold = load_golden("oracle_dambreak3d_2M.json")["seeds"]["0"]
     t_last = gold[-1]["t"]
-    assert t_last >= 0.3 - 1e-9 and len(gold) >= 4
+    assert t_last >= 0.5 - 1e-9 and len(gold) >= 6
     g, _ = make_pair(case, FP32)
     say(f"large run to t={t_last:.2f} ({len(gold)} observer rows)")
     rows = run_observed(g, t_last + 1e-9)
@@ -453,27 +453,34 @@ def test_dambreak_medium_fp32_through_impact():
     assert worst_energy <= 0.01
 
 
+
+PERTURBED_RUNS = ("oracle_dambreak2d_51k_perturbed.json", "oracle_dambreak2d_51k_perturbed_1.json")
+
+
 def test_dambreak_medium_fp32_whole_run_within_rounding_envelope():
     """Over the whole run to t = 20. After the plunging wave closes on
-    itself (t ~ 6-8) the flow is chaotic: the FP64 oracle rerun from positions
-    moved by at most 2e-9 (tests/golden/oracle_dambreak2d_51k_perturbed.json)
-    departs from its own unperturbed run by up to 3 % of E(0) in total
-    energy. The FP32 run keeps the surge front within 1 % throughout, and the
-    total energy within 1 % of E(0) or within twice the oracle's own spread
-    up to that time, whichever is larger."""
+    itself (t ~ 6-8) the flow is chaotic: FP64 oracle reruns from positions
+    moved by at most 2e-9 (tests/golden/oracle_dambreak2d_51k_perturbed*.json,
+    one per perturbation seed) depart from the unperturbed run and from each
+    other by up to 3 % of E(0) in total energy, so a run whose rounding
+    differs from the oracle's cannot be expected to stay within 1 % of it
+    throughout. The FP32 run keeps the surge front within 1 % throughout and
+    the total energy within 1 % of E(0) or within the oracle's own spread
+    (rounding_envelope over the unperturbed and perturbed oracle
+    trajectories, +-0.5 around the observer time), whichever is larger."""
     case, gold, rows = medium_run()
-    pert = load_golden("oracle_dambreak2d_51k_perturbed.json")["seeds"]["0"]
-    assert len(pert) == len(gold)
+    perturbed = [load_golden(f)["seeds"]["0"] for f in PERTURBED_RUNS]
+    for p in perturbed:
+        assert len(p) == len(gold) and all(a["t"] == b["t"] for a, b in zip(p, gold))
     E0 = energy(gold[0])
-    env = worst_front = worst_ratio = worst_dev = 0.0
-    for r, go, gp in zip(rows, gold, pert):
-        assert gp["t"] == go["t"]
-        env = max(env, abs(energy(gp) - energy(go)) / E0)
+    env = rounding_envelope(gold, perturbed, E0)
+    worst_front = worst_ratio = worst_dev = 0.0
+    for r, go, e in zip(rows, gold, env):
         dev = abs(energy(r) - energy(go)) / E0
         worst_dev = max(worst_dev, dev)
-        worst_ratio = max(worst_ratio, dev / max(0.01, 2.0 * env))
+        worst_ratio = max(worst_ratio, dev / max(0.01, e))
         worst_front = max(worst_front, abs(r["front"] - go["front"]) / go["front"])
     say(f"whole run: worst front rel err {worst_front:.3e}, worst energy err / E0 {worst_dev:.3e}, "
-        f"oracle spread {env:.3e}, worst err / allowance {worst_ratio:.3f}")
+        f"largest oracle spread {max(env):.3e}, worst err / allowance {worst_ratio:.3f}")
     assert worst_front <= 0.01
     assert worst_ratio <= 1.0
