@@ -89,6 +89,30 @@ def test_neighbors_bitexact_ties_at_support():
     assert lists_equal(g, o, sphx.SPHX_INNER)
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neighbors_bitexact_cells_exactly_2h_wide(precision, dim):
+    """A box whose x length is 15 x 2h, so the cells are 2h wide up to
+    rounding (the build keeps one x sub-bin of slack there), with lattice
+    particles on sub-bin boundaries (offsets L/4 and 3L/4) and pairs at
+    r = 2h, half of them moved by up to 1e-12 either way."""
+    dp = 0.1
+    n1 = 14 if dim == 2 else 8
+    pos = lattice((n1,) * dim, dp)
+    rng = np.random.Generator(np.random.PCG64(5 + dim))
+    pos[::2] += rng.uniform(-1e-12, 1e-12, size=pos[::2].shape)
+    box = 3.0
+    case = wl.Case(name=f"cells2h_{dim}d", dim=dim, dp=dp, h=dp, rho0=1.0, c0=10.0, u_ref=1.0, cfl_ad=0.25,
+                   cfl_ac=0.6, gravity=(0, 0, 0), lo=(0.0, 0.0, 0.0), hi=(box, box, box if dim == 3 else 0.0),
+                   periodic=(0, 0, 0), fluid_pos=pos, wall_pos=np.zeros((0, dim)), wall_normal=np.zeros((0, dim)),
+                   column=(1.4, 1.4))
+    assert box / 15 == 2 * case.h  # the cell width the grid takes
+    g, o = make_pair(case, precision, walls=False)
+    g.build_neighbors()
+    o.build_config()
+    assert lists_equal(g, o, sphx.SPHX_INNER)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
 def test_neighbors_bitexact_dambreak_small(seed):
     case = wl.config_small(seed)
