@@ -903,8 +903,11 @@ template <int B> struct BodyTag { static constexpr int value = B; };
 // rebuilt from cell offsets.
 //
 // TB lanes share one particle; a block is one tile. The three x-adjacent
-// cells of a stencil row are one contiguous range of the sorted order,
-// scanned TB candidates per round; hits are appended in candidate order
+// cells of a stencil row are one contiguous range of the sorted order; of
+// its fluid candidates those in x sub-bins out of reach (below the
+// particle's own sub-bin in the left cell, above it in the right one) are
+// skipped. The rest is scanned TB candidates per round; hits are appended in
+// candidate order
 // through a ballot, so the list does not depend on TB. In FP32 mode a
 // candidate is first classified on the FP32 cell offsets: |r2_32 - r2| <=
 // 6 * 2^-24 L (2 r) + 3 * 2^-24 r^2 < 2.4e-6 L^2 for r <= L (offsets and cell
