@@ -1217,12 +1217,15 @@ template <int T, int U, typename Load, typename Use>
 __device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int i, int n, int mx, int l,
                                           Load load, Use use)
 {
-    for (int k0 = l; k0 < n; k0 += T * U) {
+    // entry l + T r of the lane sits 64 r words past its entry l (ell_at),
+    // so a batch reads at fixed offsets from one pointer
+    const uint32_t* q = list + ell_base<T>(i, mx) + l;
+    for (int k0 = l; k0 < n; k0 += T * U, q += 64 * U) {
         uint32_t e[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int k = k0 + u * T;
-            e[u] = k < n ? list[ell_at<T>(i, k, mx)] : NO_ENTRY;
+            e[u] = k < n ? q[64 * u] : NO_ENTRY;
         }
         decltype(load(0u)) g[U];
 #pragma unroll
