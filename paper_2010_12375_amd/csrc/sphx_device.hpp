@@ -52,7 +52,6 @@ constexpr int BATCH = SPHX_PAIR_BATCH;  // list entries loaded ahead per lane (p
 #define SPHX_BUILD_BATCH 4
 #endif
 constexpr int NBATCH = SPHX_BUILD_BATCH;  // candidate rounds loaded ahead per lane (neighbour build)
-constexpr uint32_t NO_ENTRY = 0xffffffffu;  // stencil code 63 never occurs
 // Inside a cell the particles are ordered by x sub-bin (XSUB bins of width
 // L/XSUB along x), then by previous slot. The sub-bin rides in the bits above
 // CELL_BITS of a slot's cell word and binning key (global cell indices stay
@@ -1219,21 +1218,25 @@ __device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int
 {
     // entry l + T r of the lane sits 64 r words past its entry l (ell_at),
     // so a batch reads at fixed offsets from one pointer
+    // (entry u of a batch exists where k0 + u T < n: decided from the index,
+    // so nothing waits on a loaded word to know it)
     const uint32_t* q = list + ell_base<T>(i, mx) + l;
     for (int k0 = l; k0 < n; k0 += T * U, q += 64 * U) {
+        bool ok[U];
         uint32_t e[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int k = k0 + u * T;
-            e[u] = k < n ? q[64 * u] : NO_ENTRY;
+            ok[u] = k0 + u * T < n;
+            e[u] = 0u;
+            if (ok[u]) e[u] = q[64 * u];
         }
         decltype(load(0u)) g[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (e[u] != NO_ENTRY) g[u] = load(e[u]);
+            if (ok[u]) g[u] = load(e[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (e[u] != NO_ENTRY) use(e[u], g[u]);
+            if (ok[u]) use(e[u], g[u]);
     }
 }
 
