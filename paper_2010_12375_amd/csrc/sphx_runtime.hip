@@ -159,7 +159,9 @@ struct Engine final : EngineBase {
     using G = typename GeoSel<D, real>::T;
     sphx_ctx* ctx;
     hipStream_t s;
-    static constexpr int LB = 4;  // lanes per particle in the neighbour build (one tile per block)
+    // lanes per particle in the neighbour build (one tile per block): the 3D
+    // rows, trimmed to the x sub-bins in reach, are short enough for two
+    static constexpr int LB = D == 3 ? 2 : 4;
     int ln = D == 2 ? 4 : 8;      // lanes per particle in the pair kernels (2, 4, 8 or 16)
     int C = 0;                    // cases
     std::vector<KP<real>> hP;     // parameter table (host copy)
