@@ -1209,17 +1209,16 @@ __global__ void k_adv_begin(const KP<real>* __restrict__ Pt, Ctrl* __restrict__ 
 }
 
 // Visit the list entries k = l, l + T, ... < n of particle i in batches of
-// U: first the U index loads, then the U gathers (`load`), then the U
-// updates (`use`), so that several memory round trips are in flight per
-// lane. Each lane still accumulates its entries in ascending k.
+// U: first the U list words (entry l + T r of the lane sits 64 r words past
+// its entry l, ell_at, so a batch reads at fixed offsets from one pointer),
+// then the U gathers (`load`), then the U updates (`use`), so that several
+// memory round trips are in flight per lane. Which entries of a batch exist
+// is decided from their index (k < n), so nothing waits on a loaded word to
+// know it. Each lane still accumulates its entries in ascending k.
 template <int T, int U, typename Load, typename Use>
 __device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int i, int n, int mx, int l,
                                           Load load, Use use)
 {
-    // entry l + T r of the lane sits 64 r words past its entry l (ell_at),
-    // so a batch reads at fixed offsets from one pointer
-    // (entry u of a batch exists where k0 + u T < n: decided from the index,
-    // so nothing waits on a loaded word to know it)
     const uint32_t* q = list + ell_base<T>(i, mx) + l;
     for (int k0 = l; k0 < n; k0 += T * U, q += 64 * U) {
         bool ok[U];
