@@ -1214,20 +1214,24 @@ __global__ void k_adv_begin(const KP<real>* __restrict__ Pt, Ctrl* __restrict__ 
 // then the U gathers (`load`), then the U updates (`use`), so that several
 // memory round trips are in flight per lane. Which entries of a batch exist
 // is decided from their index (k < n), so nothing waits on a loaded word to
-// know it. Each lane still accumulates its entries in ascending k.
-template <int T, int U, typename Load, typename Use>
+// know it. Each lane still accumulates its entries in ascending k. The
+// lists may be laid out for TL = 2T lanes (the pressure relaxation in 3D
+// runs with half the lanes of the layout): entry l + T r then sits in row
+// r / 2 at column l + T (r mod 2), still at fixed offsets within a batch.
+template <int T, int U, int TL, typename Load, typename Use>
 __device__ __forceinline__ void for_pairs(const uint32_t* __restrict__ list, int i, int n, int mx, int l,
                                           Load load, Use use)
 {
-    const uint32_t* q = list + ell_base<T>(i, mx) + l;
-    for (int k0 = l; k0 < n; k0 += T * U, q += 64 * U) {
+    static_assert(TL == T || (TL == 2 * T && U % 2 == 0), "layout of T or 2T lanes");
+    const uint32_t* q = list + ell_base<TL>(i, mx) + l;
+    for (int k0 = l; k0 < n; k0 += T * U, q += 64 * U * T / TL) {
         bool ok[U];
         uint32_t e[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             ok[u] = k0 + u * T < n;
             e[u] = 0u;
-            if (ok[u]) e[u] = q[64 * u];
+            if (ok[u]) e[u] = q[TL == T ? 64 * u : 64 * (u >> 1) + T * (u & 1)];
         }
         decltype(load(0u)) g[U];
 #pragma unroll
@@ -1280,8 +1284,8 @@ __global__ __launch_bounds__(BLOCK) void k_reinit(
         Pair<D, real> q = pair_geo<D, real>(P, oi, oj, e >> NBR_SHIFT);
         sigma += (double)kernel_W(P, q.r);
     };
-    for_pairs<T, BATCH>(nbr, i, ncnt[i], P.maxn, l, [&](uint32_t e) { return geo[e & NBR_MASK]; }, add_w);
-    for_pairs<T, BATCH>(wnb, i, wcnt[i], P.maxw, l, [&](uint32_t e) { return wgeo[e & NBR_MASK]; }, add_w);
+    for_pairs<T, BATCH, T>(nbr, i, ncnt[i], P.maxn, l, [&](uint32_t e) { return geo[e & NBR_MASK]; }, add_w);
+    for_pairs<T, BATCH, T>(wnb, i, wcnt[i], P.maxw, l, [&](uint32_t e) { return wgeo[e & NBR_MASK]; }, add_w);
     sigma = group_sum<T>(sigma) + (double)P.Wc;  // + W(0), the particle itself
     if (l != 0) return;
     reinit_density<D>(P, sigma, st + i);
@@ -1324,7 +1328,7 @@ __device__ __forceinline__ void adv_forces_body(
     if (mv) wall_rates(P, ctrl->t, Vw, omw);
     struct FluidJ { G o; R4<real> s; };
     struct WallJ { G o; R4<real> k, g; };
-    for_pairs<T, BATCH>(
+    for_pairs<T, BATCH, T>(
         nbr, i, ncnt[i], P.maxn, l,
         [&](uint32_t e) {
             uint32_t j = e & NBR_MASK;
@@ -1347,7 +1351,7 @@ __device__ __forceinline__ void adv_forces_body(
             at[1] += ct * q.e[1];
             if (D == 3) at[2] += ct * q.e[2];
         });
-    for_pairs<T, BATCH>(
+    for_pairs<T, BATCH, T>(
         wnb, i, wcnt[i], P.maxw, l,
         [&](uint32_t e) {
             uint32_t w = e & NBR_MASK;
@@ -1409,8 +1413,9 @@ __global__ __launch_bounds__(BLOCK) void k_adv_forces(
 // half-steps are applied together in S7), EoS, Riemann momentum equation
 // with fluid and wall neighbours and gravity, velocity update. T lanes share
 // a particle: each takes every T-th neighbour, partial sums are combined
-// with shuffles and lane 0 writes.
-template <int D, typename real, int T, bool MOVE>
+// with shuffles and lane 0 writes. TL: the lanes the lists are laid out for
+// (T or 2T).
+template <int D, typename real, int T, bool MOVE, int TL>
 __device__ __forceinline__ void pressure_body(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
@@ -1483,7 +1488,7 @@ __device__ __forceinline__ void pressure_body(
     real acc[3] = {0, 0, 0};
     struct FluidJ { G o; R4<real> s; };
     struct WallJ { G o; G n; R4<real> k, g; };
-    for_pairs<T, BATCH>(
+    for_pairs<T, BATCH, TL>(
         nbr, i, ncnt[i], P.maxn, l,
         [&](uint32_t e) {
             uint32_t j = e & NBR_MASK;
@@ -1511,7 +1516,7 @@ __device__ __forceinline__ void pressure_body(
             acc[1] -= cd * pq.d[1];
             if (D == 3) acc[2] -= cd * pq.d[2];
         });
-    for_pairs<T, BATCH>(
+    for_pairs<T, BATCH, TL>(
         wnb, i, wcnt[i], P.maxw, l,
         [&](uint32_t e) {
             uint32_t w = e & NBR_MASK;
@@ -1576,7 +1581,7 @@ __device__ __forceinline__ void pressure_body(
     }
 }
 
-template <int D, typename real, int T, bool MOVE>
+template <int D, typename real, int T, bool MOVE, int TL = T>
 __global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR void k_pressure(
     const KP<real>* __restrict__ Pt, const int32_t* __restrict__ tcase, Ctrl* __restrict__ ctrl_all,
     const typename GeoSel<D, real>::T* __restrict__ geo, const typename GeoSel<D, real>::T* __restrict__ wgeo,
@@ -1589,13 +1594,13 @@ __global__ __launch_bounds__(BLOCK) SPHX_PAIR_ATTR void k_pressure(
     if constexpr (MOVE) {
         // cases with static walls run the static instantiation's code
         if (!wall_velocity_case(Pt, tcase, pair_block_first<T>(xcd_block(blockIdx.x, gridDim.x)))) {
-            pressure_body<D, real, T, false>(
+            pressure_body<D, real, T, false, TL>(
                 Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all,
                 avt, wmot, wvg);
             return;
         }
     }
-    pressure_body<D, real, T, MOVE>(
+    pressure_body<D, real, T, MOVE, TL>(
         Pt, tcase, ctrl_all, geo, wgeo, wnrm, nbr, ncnt, wnb, wcnt, st, dr3, hf, acc_out, q, adv, vslot_all, avt,
         wmot, wvg);
 }
@@ -1664,7 +1669,7 @@ __device__ __forceinline__ void density_body(
         real sum = 0;
         struct HalfJ { G o; R4<real> h; };
         struct WallJ { G o; G n; R4<real> k, g; };
-        for_pairs<T, BATCH>(
+        for_pairs<T, BATCH, T>(
             nbr, i, ncnt[i], P.maxn, l,
             [&](uint32_t e) {
                 uint32_t j = e & NBR_MASK;
@@ -1688,7 +1693,7 @@ __device__ __forceinline__ void density_body(
                 real dus2 = dvd * pq.rinv + div_r(two_c * (dev_i - dev_j), rho_i + rho_j);
                 sum += half_m * inv_rho_j * dus2 * pq.dW;
             });
-        for_pairs<T, BATCH>(
+        for_pairs<T, BATCH, T>(
             wnb, i, wcnt[i], P.maxw, l,
             [&](uint32_t e) {
                 uint32_t w = e & NBR_MASK;

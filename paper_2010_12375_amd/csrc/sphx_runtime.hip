@@ -443,6 +443,13 @@ struct Engine final : EngineBase {
     int nblk_scan() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
     int nblk_lb() const { return (ncell + LB_TILE - 1) / LB_TILE; }
     int pair_blocks() const { return (int)((long long)ntot * ln / (ln * TILE < BLOCK ? ln * TILE : BLOCK)); }
+    template <int T>
+    int pair_blocks_t() const { return (int)((long long)ntot * T / pair_threads<T>()); }
+    // Lanes of the pressure relaxation for lists laid out for T lanes: in 3D
+    // with 8 layout lanes it runs with 4 (its gathers and shuffles favour
+    // fewer lanes than the density relaxation's).
+    template <int T>
+    static constexpr int pressure_lanes() { return D == 3 && T == 8 ? 4 : T; }
 
     // Whether any case has a shear force or a transport-velocity correction.
     bool any_adv() const
@@ -1039,8 +1046,10 @@ struct Engine final : EngineBase {
         R4<real>* wg = wvg_arg();
         by_motion([&](auto mc) {
             constexpr bool MV = decltype(mc)::value;
-            k_pressure<D, real, T, MV><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt,
-                                                            st[a], dr3[a], hf, acc, q, adv, vslot, av, wm, wg);
+            constexpr int TP = pressure_lanes<T>();
+            k_pressure<D, real, TP, MV, T><<<pair_blocks_t<TP>(), pair_threads<TP>(), 0, s>>>(
+                dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, acc, q, adv, vslot, av, wm,
+                wg);
             k_density<D, real, T, MV><<<nb, pair_threads<T>(), 0, s>>>(dP, tcase, ctrl, finalize, geo[a], wgeo, wnrm, nbr, ncnt,
                                                            wnb, wcnt, hf, st[a], dr3[a], x[a][0], x[a][1], x[a][2],
                                                            dro, vslot, q, av, wm, wg, bin, cell[a], key, rank, cnt);
@@ -1717,7 +1726,8 @@ struct Engine final : EngineBase {
         const int a = cur;
         RETCHK(time_launches(reps, &ms[0], [&] {
             by_motion([&](auto mc) {
-                k_pressure<D, real, T, decltype(mc)::value><<<nb, pair_threads<T>(), 0, s>>>(
+                constexpr int TP = pressure_lanes<T>();
+                k_pressure<D, real, TP, decltype(mc)::value, T><<<pair_blocks_t<TP>(), pair_threads<TP>(), 0, s>>>(
                     dP, tcase, ctrl, geo[a], wgeo, wnrm, nbr, ncnt, wnb, wcnt, st[a], dr3[a], hf, nullptr, 0, 0,
                     vslot, avt_arg(), wmot_arg(), wvg_arg());
             });
