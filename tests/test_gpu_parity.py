@@ -479,7 +479,7 @@ def test_dambreak_medium_fp32_through_impact():
 
 
 PERTURBED_RUNS = ("oracle_dambreak2d_51k_perturbed.json", "oracle_dambreak2d_51k_perturbed_1.json",
-                  "oracle_dambreak2d_51k_perturbed_2.json")
+                  "oracle_dambreak2d_51k_perturbed_2.json", "oracle_dambreak2d_51k_perturbed_3.json")
 
 
 def test_dambreak_medium_fp32_whole_run_within_rounding_envelope():
